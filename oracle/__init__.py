@@ -1,0 +1,170 @@
+"""CPU oracle for the Euler-tour hot path (test infrastructure only).
+
+Only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark may import this package. It wraps ``et_oracle.c`` (plain
+sequential C, built by :func:`build` with gcc) through ctypes and shares no
+code with the GPU library. Arrays go in and come out as numpy arrays.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "et_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build():
+    """Compile the oracle with gcc into ``oracle/liboracle.so``."""
+    tmp = _LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
+                           _SRC, "-o", tmp])
+    os.replace(tmp, _LIB)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "oracle_euler_tour": [P, i32, P, P, P, P, P, P],
+        "oracle_list_rank": [P, i32, P, i32, P],
+        "oracle_lca_climb": [P, P, i32, P, P, i64, P],
+        "oracle_lca_offline": [P, i32, P, P, i64, P],
+        "oracle_sv_tables": [P, P, P, P, i32, P, P, P, P],
+        "oracle_bridges": [P, P, i32, i64, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class OracleInputError(ValueError):
+    """The oracle found the input malformed (code -4)."""
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc, what):
+    if rc == -4:
+        raise OracleInputError(f"{what}: malformed input")
+    if rc != 0:
+        raise RuntimeError(f"{what}: oracle error {rc}")
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def euler_tour(parent):
+    """Euler tour of the tree (children in ascending id order).
+
+    Returns a dict with ``tour`` [2(n-1)], ``rank`` [2n] (-1 on the root's
+    two unused half-edge ids), ``depth``, ``pre``, ``size`` [n] and ``root``.
+    Half-edge 2c goes down into c, 2c+1 goes up out of c.
+    """
+    parent = _i32(parent)
+    n = parent.shape[0]
+    tour = np.empty(max(2 * (n - 1), 0), dtype=np.int32)
+    rank = np.empty(2 * n, dtype=np.int32)
+    depth = np.empty(n, dtype=np.int32)
+    pre = np.empty(n, dtype=np.int32)
+    size = np.empty(n, dtype=np.int32)
+    root = ctypes.c_int32(-1)
+    rc = _load().oracle_euler_tour(_ptr(parent), n, _ptr(tour), _ptr(rank), _ptr(depth),
+                                   _ptr(pre), _ptr(size), ctypes.cast(ctypes.pointer(root), ctypes.c_void_p))
+    _check(rc, "euler_tour")
+    return {"tour": tour, "rank": rank, "depth": depth, "pre": pre, "size": size,
+            "root": int(root.value)}
+
+
+def tree_succ(parent):
+    """Successor array of the Euler tour built from the oracle's tour order
+    (succ[tour[i]] = tour[i+1], -1 at the tail, -2 on the root's ids)."""
+    t = euler_tour(parent)
+    n = len(parent)
+    succ = np.full(2 * n, -2, dtype=np.int32)
+    tour = t["tour"]
+    if tour.shape[0]:
+        succ[tour[:-1]] = tour[1:]
+        succ[tour[-1]] = -1
+    head = int(tour[0]) if tour.shape[0] else -1
+    return succ, head
+
+
+def list_rank(succ, heads):
+    succ = _i32(succ)
+    heads = _i32(heads)
+    rank = np.empty(succ.shape[0], dtype=np.int32)
+    rc = _load().oracle_list_rank(_ptr(succ), succ.shape[0], _ptr(heads), heads.shape[0], _ptr(rank))
+    _check(rc, "list_rank")
+    return rank
+
+
+def lca_climb(parent, depth, qx, qy):
+    parent, depth, qx, qy = _i32(parent), _i32(depth), _i32(qx), _i32(qy)
+    out = np.empty(qx.shape[0], dtype=np.int32)
+    rc = _load().oracle_lca_climb(_ptr(parent), _ptr(depth), parent.shape[0], _ptr(qx), _ptr(qy),
+                                  qx.shape[0], _ptr(out))
+    _check(rc, "lca_climb")
+    return out
+
+
+def lca_offline(parent, qx, qy):
+    parent, qx, qy = _i32(parent), _i32(qx), _i32(qy)
+    out = np.empty(qx.shape[0], dtype=np.int32)
+    rc = _load().oracle_lca_offline(_ptr(parent), parent.shape[0], _ptr(qx), _ptr(qy),
+                                    qx.shape[0], _ptr(out))
+    _check(rc, "lca_offline")
+    return out
+
+
+def sv_tables(parent, depth, pre, size):
+    """Inlabel, ascendant and head tables from their definitions.
+
+    ``head_parent``/``head_depth`` are indexed by inlabel value (n+1
+    entries); labels that no path uses hold -3.
+    """
+    parent, depth, pre, size = _i32(parent), _i32(depth), _i32(pre), _i32(size)
+    n = parent.shape[0]
+    inl = np.empty(n, dtype=np.uint32)
+    asc = np.empty(n, dtype=np.uint32)
+    hp = np.empty(n + 1, dtype=np.int32)
+    hd = np.empty(n + 1, dtype=np.int32)
+    rc = _load().oracle_sv_tables(_ptr(parent), _ptr(depth), _ptr(pre), _ptr(size), n,
+                                  _ptr(inl), _ptr(asc), _ptr(hp), _ptr(hd))
+    _check(rc, "sv_tables")
+    return {"inlabel": inl, "asc": asc, "head_parent": hp, "head_depth": hd}
+
+
+def bridges(row_ptr, col):
+    """Per-slot bridge bitmask (uint32 words) and bridge count."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = _i32(col)
+    n = row_ptr.shape[0] - 1
+    nnz = col.shape[0]
+    mask = np.zeros(max((nnz + 31) // 32, 1), dtype=np.uint32)
+    cnt = ctypes.c_int64(0)
+    rc = _load().oracle_bridges(_ptr(row_ptr), _ptr(col), n, nnz, _ptr(mask),
+                                ctypes.cast(ctypes.pointer(cnt), ctypes.c_void_p))
+    _check(rc, "bridges")
+    return mask[: (nnz + 31) // 32], int(cnt.value)
+
+
+def mask_to_bool(mask, nnz):
+    """Expand a per-slot bitmask into a bool array of length ``nnz``."""
+    bits = np.unpackbits(np.asarray(mask, dtype=np.uint32).view(np.uint8), bitorder="little")
+    return bits[:nnz].astype(bool)
