@@ -1,0 +1,181 @@
+/*
+ * et.h -- C ABI of the MI355X (gfx950) Euler-tour library.
+ *
+ * Implements the data-parallel path of "Euler Meets GPU: Practical Graph
+ * Algorithms with Theoretical Guarantees" (Polak, Siwiec, Stobierski,
+ * arXiv 2103.15217): Euler tour of a rooted tree, list ranking, depth /
+ * preorder / subtree size, batched LCA queries with the Inlabel
+ * (Schieber-Vishkin) scheme, and bridges with Tarjan-Vishkin.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named d_* are DEVICE pointers owned by the caller (for example
+ *    the data_ptr() of a tensor on the current device). h_* pointers are
+ *    host pointers. Nothing is copied between host and device except where
+ *    an entry point says so.
+ *  - Every call is asynchronous and ordered on the HIP stream it is given.
+ *    Outputs are valid once that stream has reached the call's end.
+ *  - An et_ctx owns scratch memory, a device status word and the device it
+ *    was created on. Calls that share a context must be ordered with
+ *    respect to each other (one stream at a time per context).
+ *  - Ids are 0-based int32. Half-edge ids of a tree with n nodes: 2c is the
+ *    half-edge (parent(c) -> c) going down into c, 2c+1 is (c -> parent(c))
+ *    going up out of c; the root r's ids 2r and 2r+1 are unused.
+ *  - Children are visited in ascending id order and the tour starts with
+ *    the half-edge into the root's smallest child. (The paper's DCEL visits
+ *    children cyclically after the parent in sorted order and splits the
+ *    cyclic tour at an arbitrary root edge, Section 2.1; the two agree
+ *    whenever parent ids are smaller than child ids.)
+ *  - Return codes: ET_OK, or a negative ET_E* code. Argument errors that
+ *    the host can see are returned immediately and enqueue nothing.
+ *    Malformed input found on the device (not a tree, a list that is not a
+ *    set of simple paths, an id out of range, a CSR that is not symmetric)
+ *    never faults and never hangs: kernels clamp every index they gather,
+ *    bound every walk, and record the error in the context's status word,
+ *    which et_ctx_status() reports. Outputs of such a call are unspecified.
+ */
+#ifndef ET_H
+#define ET_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ET_OK 0
+#define ET_EINVAL (-1)  /* bad argument: null pointer, negative or too large size */
+#define ET_ENOMEM (-2)  /* device memory exhausted */
+#define ET_EHIP (-3)    /* a HIP runtime call failed */
+#define ET_EINPUT (-4)  /* malformed input detected on the device */
+
+typedef struct et_ctx et_ctx;
+typedef struct et_tree et_tree;
+
+/* Library version as 10000*major + 100*minor + patch. */
+int et_version(void);
+
+/* Human-readable text for a return code. Never NULL. */
+const char* et_strerror(int code);
+
+/* Create a context on the current HIP device. *out receives the handle.
+ * Allocates the device status word; scratch grows on demand. */
+int et_ctx_create(et_ctx** out);
+
+/* Release a context and all scratch it holds. Trees built with it must be
+ * freed first. Waits for the device to finish work that uses the scratch. */
+void et_ctx_destroy(et_ctx* ctx);
+
+/* Wait for stream s, then return ET_OK if no kernel enqueued on this
+ * context since the previous call flagged malformed input, else ET_EINPUT
+ * (or ET_EHIP). Clears the flag. */
+int et_ctx_status(et_ctx* ctx, hipStream_t s);
+
+/* Raw device status bits accumulated since the last et_ctx_status (for
+ * diagnostics; same waiting semantics). */
+int et_ctx_status_bits(et_ctx* ctx, hipStream_t s, uint32_t* h_bits);
+
+/* Kernel timing. With enable != 0 every kernel launch of later calls on
+ * this context is bracketed by a pair of HIP events on its stream. */
+int et_ctx_profile(et_ctx* ctx, int enable);
+
+/* Wait for stream s, then write a JSON object into h_buf (NUL-terminated,
+ * at most buflen bytes): {"kernel": [launches, total_ms, max_ms], ...} over
+ * the launches timed since the previous read; clears the records. Returns
+ * ET_EINVAL if the buffer is too small (records are kept). */
+int et_ctx_profile_read(et_ctx* ctx, hipStream_t s, char* h_buf, int32_t buflen);
+
+/*
+ * List ranking (Section 2.2: the rank of an element is its distance from
+ * the head of its list).
+ *   d_succ[len]      successor of each element; -1 ends a list; -2 marks an
+ *                    unused slot. Every used slot must lie on exactly one
+ *                    of the lists that start at d_heads.
+ *   d_heads[n_heads] first element of each list (device array).
+ *   d_rank[len]      output: steps from the element's list head (head = 0);
+ *                    -1 for unused slots.
+ * Sublist ranking: pseudo-randomly placed splitters cut the lists into
+ * short sublists that wavefront lanes walk independently, the list of
+ * sublists is ranked the same way until it fits one workgroup's LDS, and
+ * the offsets are pushed back down.
+ * len < 2^31 - 2^20. Malformed lists set ET_EINPUT in the status word.
+ */
+int et_list_rank(et_ctx* ctx, const int32_t* d_succ, int32_t len, const int32_t* d_heads,
+                 int32_t n_heads, int32_t* d_rank, hipStream_t s);
+
+/*
+ * Euler tour and node statistics of a rooted tree (Section 2, Section 2.2),
+ * plus the Inlabel tables for LCA queries (Section 3.1).
+ *   d_parent[n]  parent id of every node; exactly one node (the root) has
+ *                parent -1. n >= 1, n < 2^30.
+ * The tree keeps its own device tables (tour successor and rank arrays,
+ * depth / preorder / size, inlabel / ascendant, path-head table); d_parent
+ * may be released once stream s has passed this call. The caller frees the
+ * tree with et_tree_free. A parent array that is not a tree (no root or
+ * several, an id out of range, a cycle) sets ET_EINPUT in ctx's status.
+ */
+int et_tree_build(et_ctx* ctx, const int32_t* d_parent, int32_t n, hipStream_t s,
+                  et_tree** out);
+
+/* Number of nodes of a built tree (host value). */
+int32_t et_tree_size(const et_tree* tree);
+
+/*
+ * Copy tables of a built tree into caller-owned device arrays; any output
+ * may be NULL.
+ *   d_succ[2n], d_rank[2n]   tour successor (-1 at the tail, -2 on the
+ *                            root's two ids) and tour position (-1 there)
+ *   d_depth[n]               distance from the root
+ *   d_pre[n]                 0-based preorder number (root 0)
+ *   d_size[n]                number of nodes in the subtree
+ *   d_inlabel[n], d_asc[n]   Schieber-Vishkin inlabel and ascendant words
+ */
+int et_tree_export(const et_tree* tree, int32_t* d_succ, int32_t* d_rank, int32_t* d_depth,
+                   int32_t* d_pre, int32_t* d_size, uint32_t* d_inlabel, uint32_t* d_asc,
+                   hipStream_t s);
+
+/* Release a tree's device tables (stream-ordered on s). */
+void et_tree_free(et_tree* tree, hipStream_t s);
+
+/*
+ * Batched LCA queries on a built tree (Section 3: for each pair (x_i, y_i)
+ * the deepest node that is an ancestor of both). One lane per query,
+ * constant work per query (Inlabel query of Schieber and Vishkin).
+ *   d_qx[q], d_qy[q]  query endpoints (node ids)
+ *   d_out[q]          output: LCA id; -1 for a query with an id out of
+ *                     range (which also sets ET_EINPUT)
+ */
+int et_lca(const et_tree* tree, const int32_t* d_qx, const int32_t* d_qy, int64_t q,
+           int32_t* d_out, hipStream_t s);
+
+/*
+ * Bridges of an undirected graph (Section 4: edge e is a bridge iff
+ * deleting it disconnects its endpoints), by Tarjan-Vishkin: spanning
+ * forest by hooking connected components, Euler tour of the forest,
+ * preorder and subtree sizes, per-node minimum / maximum preorder over
+ * non-tree neighbours, low / high by range minimum / maximum over subtree
+ * intervals, and the test on tree edges.
+ *   d_row_ptr[n+1], d_col[nnz]  symmetric CSR: every edge {u, w} appears as
+ *                  slot (u, w) in row u and slot (w, u) in row w; each row
+ *                  sorted ascending; parallel edges repeat a column; a
+ *                  self-loop {u, u} gives two (u, u) slots. nnz < 2^31.
+ *   d_mask[ceil(nnz/32)]  output: bit k (word k/32, bit k%32) is set iff
+ *                  slot k belongs to a bridge (both slots of a bridge set)
+ *   h_count        optional host output: number of bridges. When non-NULL
+ *                  the call waits for stream s before returning.
+ * Graphs may be disconnected (one tour per component). A self-loop or an
+ * edge with a parallel copy is never a bridge.
+ */
+int et_bridges(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col, int32_t n,
+               int32_t nnz, uint32_t* d_mask, int64_t* h_count, hipStream_t s);
+
+/* Device-side bridge count of the most recent et_bridges call on ctx
+ * (written to a caller-owned device int64). */
+int et_bridges_count(et_ctx* ctx, int64_t* d_count, hipStream_t s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ET_H */

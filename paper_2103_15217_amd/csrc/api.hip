@@ -1,0 +1,283 @@
+// C-ABI entry points of the Euler-tour library (declared in include/et.h),
+// the per-context scratch pool and the device status word.
+#include <cstdio>
+#include <map>
+#include <new>
+#include <string>
+
+#include "et_internal.hpp"
+
+namespace et {
+
+int tree_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s);
+int tree_export(const et_tree* t, int32_t* succ, int32_t* rank, int32_t* depth, int32_t* pre, int32_t* size,
+                uint32_t* inl, uint32_t* asc, hipStream_t s);
+int tree_lca(Ctx* c, const et_tree* t, const int32_t* qx, const int32_t* qy, int64_t q, int32_t* out,
+             hipStream_t s);
+int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t nnz, uint32_t* mask,
+                hipStream_t s);
+
+namespace {
+constexpr size_t kAlign = 256;
+}
+
+void* pool_get(Ctx* c, size_t bytes) {
+  bytes = (bytes + kAlign - 1) & ~(kAlign - 1);
+  // smallest cached block that fits without wasting more than half of it
+  auto it = c->free_blocks.lower_bound(bytes);
+  if (it != c->free_blocks.end() && it->first <= 2 * bytes + (1u << 20)) {
+    void* p = it->second;
+    c->live_blocks[p] = it->first;
+    c->free_blocks.erase(it);
+    return p;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    // release cached blocks and retry once
+    for (auto& kv : c->free_blocks) {
+      (void)hipFree(kv.second);
+      c->pool_bytes -= kv.first;
+    }
+    c->free_blocks.clear();
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  c->pool_bytes += bytes;
+  c->live_blocks[p] = bytes;
+  return p;
+}
+
+hipEvent_t prof_event(Ctx* c) {
+  if (!c->spare_events.empty()) {
+    hipEvent_t e = c->spare_events.back();
+    c->spare_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+void pool_put(Ctx* c, void* p) {
+  auto it = c->live_blocks.find(p);
+  if (it == c->live_blocks.end()) return;
+  c->free_blocks.emplace(it->second, p);
+  c->live_blocks.erase(it);
+}
+
+}  // namespace et
+
+using et::Ctx;
+
+extern "C" {
+
+int et_version(void) { return 100; }
+
+const char* et_strerror(int code) {
+  switch (code) {
+    case ET_OK: return "ok";
+    case ET_EINVAL: return "invalid argument";
+    case ET_ENOMEM: return "out of device memory";
+    case ET_EHIP: return "HIP runtime error";
+    case ET_EINPUT: return "malformed input detected on the device";
+    default: return "unknown error";
+  }
+}
+
+int et_ctx_create(et_ctx** out) {
+  if (!out) return ET_EINVAL;
+  *out = nullptr;
+  et_ctx* ctx = new (std::nothrow) et_ctx();
+  if (!ctx) return ET_ENOMEM;
+  Ctx* c = &ctx->impl;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete ctx;
+    return ET_EHIP;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, 256) != hipSuccess) {
+    delete ctx;
+    return ET_ENOMEM;
+  }
+  if (hipMemset(p, 0, 256) != hipSuccess) {
+    (void)hipFree(p);
+    delete ctx;
+    return ET_EHIP;
+  }
+  c->d_status = static_cast<uint32_t*>(p);
+  c->d_scalars = reinterpret_cast<int32_t*>(static_cast<char*>(p) + 64);
+  c->d_bcount = reinterpret_cast<int64_t*>(static_cast<char*>(p) + 128);
+  *out = ctx;
+  return ET_OK;
+}
+
+void et_ctx_destroy(et_ctx* ctx) {
+  if (!ctx) return;
+  Ctx* c = &ctx->impl;
+  (void)hipDeviceSynchronize();
+  for (auto& kv : c->free_blocks) (void)hipFree(kv.second);
+  for (auto& kv : c->live_blocks) (void)hipFree(kv.first);
+  (void)hipFree(c->d_status);
+  for (auto& r : c->prof) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : c->spare_events) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+int et_ctx_profile(et_ctx* ctx, int enable) {
+  if (!ctx) return ET_EINVAL;
+  ctx->impl.profiling = enable != 0;
+  return ET_OK;
+}
+
+int et_ctx_profile_read(et_ctx* ctx, hipStream_t s, char* h_buf, int32_t buflen) {
+  if (!ctx || !h_buf || buflen < 3) return ET_EINVAL;
+  Ctx* c = &ctx->impl;
+  if (hipStreamSynchronize(s) != hipSuccess) return ET_EHIP;
+  struct Agg {
+    long n = 0;
+    double total = 0, mx = 0;
+  };
+  std::map<std::string, Agg> agg;
+  for (auto& r : c->prof) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+      (void)hipGetLastError();
+      continue;
+    }
+    Agg& g = agg[r.name];
+    g.n++;
+    g.total += ms;
+    if (ms > g.mx) g.mx = ms;
+  }
+  std::string out = "{";
+  char tmp[256];
+  for (auto& kv : agg) {
+    snprintf(tmp, sizeof(tmp), "%s\"%s\": [%ld, %.6f, %.6f]", out.size() > 1 ? ", " : "", kv.first.c_str(),
+             kv.second.n, kv.second.total, kv.second.mx);
+    out += tmp;
+  }
+  out += "}";
+  if ((int64_t)out.size() + 1 > buflen) return ET_EINVAL;
+  memcpy(h_buf, out.c_str(), out.size() + 1);
+  for (auto& r : c->prof) {
+    c->spare_events.push_back(r.a);
+    c->spare_events.push_back(r.b);
+  }
+  c->prof.clear();
+  return ET_OK;
+}
+
+int et_ctx_status_bits(et_ctx* ctx, hipStream_t s, uint32_t* h_bits) {
+  if (!ctx || !h_bits) return ET_EINVAL;
+  Ctx* c = &ctx->impl;
+  uint32_t bits = 0;
+  if (hipMemcpyAsync(&bits, c->d_status, sizeof(bits), hipMemcpyDeviceToHost, s) != hipSuccess) return ET_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return ET_EHIP;
+  if (hipMemsetAsync(c->d_status, 0, sizeof(uint32_t), s) != hipSuccess) return ET_EHIP;
+  *h_bits = bits;
+  return ET_OK;
+}
+
+int et_ctx_status(et_ctx* ctx, hipStream_t s) {
+  uint32_t bits = 0;
+  int rc = et_ctx_status_bits(ctx, s, &bits);
+  if (rc) return rc;
+  return bits ? ET_EINPUT : ET_OK;
+}
+
+int et_list_rank(et_ctx* ctx, const int32_t* d_succ, int32_t len, const int32_t* d_heads, int32_t n_heads,
+                 int32_t* d_rank, hipStream_t s) {
+  if (!ctx || len < 0 || n_heads < 0 || len > 0x7fffffff - (1 << 20)) return ET_EINVAL;
+  if (len > 0 && (!d_succ || !d_rank)) return ET_EINVAL;
+  if (n_heads > 0 && !d_heads) return ET_EINVAL;
+  if (len > 0 && n_heads == 0) return ET_EINVAL;
+  return et::list_rank_generic(&ctx->impl, d_succ, len, d_heads, n_heads, d_rank, s);
+}
+
+int et_tree_build(et_ctx* ctx, const int32_t* d_parent, int32_t n, hipStream_t s, et_tree** out) {
+  if (!out) return ET_EINVAL;
+  *out = nullptr;
+  if (!ctx || !d_parent || n < 1 || n >= (1 << 30)) return ET_EINVAL;
+  Ctx* c = &ctx->impl;
+  et_tree* t = new (std::nothrow) et_tree();
+  if (!t) return ET_ENOMEM;
+  t->ctx = ctx;
+  t->n = n;
+  const size_t N = (size_t)n;
+  t->d_succ = static_cast<int32_t*>(et::pool_get(c, 2 * N * sizeof(int32_t)));
+  t->d_rank = static_cast<int32_t*>(et::pool_get(c, 2 * N * sizeof(int32_t)));
+  t->d_pre = static_cast<int32_t*>(et::pool_get(c, N * sizeof(int32_t)));
+  t->d_size = static_cast<int32_t*>(et::pool_get(c, N * sizeof(int32_t)));
+  t->d_rec = static_cast<int4*>(et::pool_get(c, N * sizeof(int4)));
+  t->d_head = static_cast<int2*>(et::pool_get(c, (N + 2) * sizeof(int2)));
+  t->d_root = static_cast<int32_t*>(et::pool_get(c, 64));
+  if (!t->d_succ || !t->d_rank || !t->d_pre || !t->d_size || !t->d_rec || !t->d_head || !t->d_root) {
+    et_tree_free(t, s);
+    return ET_ENOMEM;
+  }
+  int rc = et::tree_build(c, t, d_parent, s);
+  if (rc) {
+    et_tree_free(t, s);
+    return rc;
+  }
+  *out = t;
+  return ET_OK;
+}
+
+int32_t et_tree_size(const et_tree* tree) { return tree ? tree->n : -1; }
+
+int et_tree_export(const et_tree* tree, int32_t* d_succ, int32_t* d_rank, int32_t* d_depth, int32_t* d_pre,
+                   int32_t* d_size, uint32_t* d_inlabel, uint32_t* d_asc, hipStream_t s) {
+  if (!tree) return ET_EINVAL;
+  return et::tree_export(tree, d_succ, d_rank, d_depth, d_pre, d_size, d_inlabel, d_asc, s);
+}
+
+void et_tree_free(et_tree* tree, hipStream_t s) {
+  (void)s;
+  if (!tree) return;
+  Ctx* c = &tree->ctx->impl;
+  void* blocks[] = {tree->d_succ, tree->d_rank, tree->d_pre, tree->d_size, tree->d_rec, tree->d_head, tree->d_root};
+  for (void* p : blocks)
+    if (p) et::pool_put(c, p);
+  delete tree;
+}
+
+int et_lca(const et_tree* tree, const int32_t* d_qx, const int32_t* d_qy, int64_t q, int32_t* d_out,
+           hipStream_t s) {
+  if (!tree || q < 0 || q > (int64_t)0x7fffffff * 64) return ET_EINVAL;
+  if (q > 0 && (!d_qx || !d_qy || !d_out)) return ET_EINVAL;
+  return et::tree_lca(&tree->ctx->impl, tree, d_qx, d_qy, q, d_out, s);
+}
+
+int et_bridges(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col, int32_t n, int32_t nnz,
+               uint32_t* d_mask, int64_t* h_count, hipStream_t s) {
+  if (!ctx || n < 0 || nnz < 0 || !d_row_ptr) return ET_EINVAL;
+  if (nnz > 0 && (!d_col || !d_mask)) return ET_EINVAL;
+  Ctx* c = &ctx->impl;
+  int rc = et::bridges_run(c, d_row_ptr, d_col, n, nnz, d_mask, s);
+  if (rc) return rc;
+  if (h_count) {
+    if (hipMemcpyAsync(h_count, c->d_bcount, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return ET_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return ET_EHIP;
+  }
+  return ET_OK;
+}
+
+int et_bridges_count(et_ctx* ctx, int64_t* d_count, hipStream_t s) {
+  if (!ctx || !d_count) return ET_EINVAL;
+  return hipMemcpyAsync(d_count, ctx->impl.d_bcount, sizeof(int64_t), hipMemcpyDeviceToDevice, s) == hipSuccess
+             ? ET_OK
+             : ET_EHIP;
+}
+
+}  // extern "C"

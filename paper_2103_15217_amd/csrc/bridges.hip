@@ -1,0 +1,568 @@
+// Bridges by the Tarjan-Vishkin method (Section 4.1) on a symmetric CSR.
+//
+//  1. Spanning forest (the paper uses the connectivity code of Jaiganesh and
+//     Burtscher, which yields a spanning tree as a by-product): union-find
+//     hooking over every edge {u, w}, u < w, taken at its first slot in row
+//     u. Roots only ever link to smaller roots with a compare-and-swap, so a
+//     successful swap joins two different trees and its edge is a forest
+//     edge; both of its slots are marked in a bitmask. Parallel copies of an
+//     edge are never forest edges and self-loops are skipped.
+//  2. Euler tour of the forest as the paper's DCEL (Section 2.1) read from
+//     the CSR: the forest slots of a row, in row order, are the sorted run
+//     of B for that vertex, next() wraps inside the run, twin() is found by
+//     a search in the neighbour's run, succ = next(twin). The tours of all
+//     components are chained into one list (component roots in id order).
+//  3. One list ranking; a half-edge goes down iff it precedes its twin
+//     (Section 2), which gives every vertex its parent edge and subtree
+//     size. The preorder comes from an array scan over tour order of
+//     (down + starts-a-component) weights (Section 2.2).
+//  4. For every vertex the minimum and maximum preorder over itself and its
+//     non-forest neighbours (the paper's segreduce); stored by preorder.
+//  5. low(v) / high(v) = range minimum / maximum of those over v's subtree
+//     interval, with a sparse table over 32-element blocks plus in-block
+//     prefix / suffix extremes (the paper uses a segment tree).
+//  6. The forest edge above v is a bridge iff low(v) and high(v) both lie
+//     inside [pre(v), pre(v) + size(v)) (Tarjan 1974; including pre(v)
+//     itself makes the test two equalities). Both slots get their bit.
+#include "et_internal.hpp"
+
+namespace et {
+namespace {
+
+constexpr int kB = 256;
+constexpr int kRowsPerBlock = 256;
+constexpr int kRmqLog = 5;  // 32-element RMQ blocks
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_iota(int32_t* __restrict__ p, int32_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+
+__device__ __forceinline__ int32_t ld(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// root of x; cc[v] <= v always, so the walk strictly decreases; halves the path
+__device__ int32_t cc_find(int32_t* cc, int32_t x) {
+  int32_t cur = ld(cc + x);
+  if (cur != x) {
+    int32_t prev = x, next;
+    while (cur > (next = ld(cc + cur))) {
+      st(cc + prev, next);
+      prev = cur;
+      cur = next;
+    }
+  }
+  return cur;
+}
+
+__device__ __forceinline__ int32_t clampi(int32_t x, int32_t lo, int32_t hi) { return min(max(x, lo), hi); }
+
+// row_ptr must be monotone from 0 to nnz; anything else is flagged
+__global__ void k_check_csr(const int32_t* __restrict__ row_ptr, int32_t n, int32_t nnz,
+                            uint32_t* __restrict__ status) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t a = row_ptr[v], b = row_ptr[v + 1];
+  bool bad = a > b || a < 0 || b > nnz;
+  if (v == 0 && a != 0) bad = true;
+  if (v == n - 1 && b != nnz) bad = true;
+  if (bad) flag(status, ST_BAD_CSR);
+}
+
+// rows [b*256, b*256+256) of the CSR; lane-strided over their slots
+__device__ __forceinline__ int row_of(const int32_t* rp_lds, int cnt, int32_t k) {
+  int lo = 0, hi = cnt;  // largest i in [0, cnt) with rp[i] <= k
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (rp_lds[mid] <= k) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kB) void k_hook(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                            int32_t n, int32_t nnz, int32_t* cc, uint32_t* __restrict__ tbits,
+                                            uint32_t* __restrict__ status) {
+  __shared__ int32_t rp[kRowsPerBlock + 1];
+  const int32_t r0 = blockIdx.x * kRowsPerBlock;
+  const int cnt = min(kRowsPerBlock, n - r0);
+  for (int i = threadIdx.x; i <= cnt; i += kB) rp[i] = clampi(row_ptr[r0 + i], 0, nnz);
+  __syncthreads();
+  const int32_t kbeg = rp[0], kend = rp[cnt];
+  bool bad = false, over = false;
+  for (int32_t k = kbeg + threadIdx.x; k < kend; k += kB) {
+    const int ri = row_of(rp, cnt, k);
+    const int32_t u = r0 + ri;
+    const int32_t w = col[k];
+    if ((uint32_t)w >= (uint32_t)n) {
+      bad = true;
+      continue;
+    }
+    if (u >= w) continue;
+    if (k > rp[ri] && col[k - 1] == w) continue;  // a parallel copy
+    bool linked = false;
+    for (int it = 0; it < (1 << 22); ++it) {
+      const int32_t ru = cc_find(cc, u), rw = cc_find(cc, w);
+      if (ru == rw) break;
+      const int32_t hi = max(ru, rw), lo = min(ru, rw);
+      if (atomicCAS(cc + hi, hi, lo) == hi) {
+        linked = true;
+        break;
+      }
+      if (it == (1 << 22) - 1) over = true;
+    }
+    if (!linked) continue;
+    atomicOr(tbits + (k >> 5), 1u << (k & 31));
+    // twin slot: first (w, u) slot in row w
+    const int32_t wbeg = clampi(row_ptr[w], 0, nnz);
+    const int32_t wend = clampi(row_ptr[w + 1], wbeg, nnz);
+    int32_t lo = wbeg, hi = wend;
+    while (lo < hi) {
+      const int32_t mid = lo + ((hi - lo) >> 1);
+      if (col[mid] < u) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < wend && col[lo] == u) atomicOr(tbits + (lo >> 5), 1u << (lo & 31));
+    else bad = true;
+  }
+  if (bad) flag(status, ST_BAD_CSR);
+  if (over) flag(status, ST_OVERFLOW);
+}
+
+__device__ __forceinline__ uint32_t bits_in(const uint32_t* tbits, int32_t a, int32_t b, int32_t wd) {
+  // forest bits of slots [a, b) that fall into word wd
+  uint32_t x = tbits[wd];
+  const int32_t base = wd << 5;
+  if (a > base) x &= ~0u << (a - base);
+  if (b < base + 32) x &= (b - base <= 0) ? 0u : (~0u >> (32 - (b - base)));
+  return x;
+}
+
+__global__ void k_tree_deg(const int32_t* __restrict__ row_ptr, const uint32_t* __restrict__ tbits, int32_t n,
+                           int32_t nnz, uint32_t* __restrict__ tdeg) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int32_t a = clampi(row_ptr[u], 0, nnz), b = clampi(row_ptr[u + 1], a, nnz);
+  uint32_t d = 0;
+  if (a < b)
+    for (int32_t wd = a >> 5; wd <= (b - 1) >> 5; ++wd) d += __popc(bits_in(tbits, a, b, wd));
+  tdeg[u] = d;
+}
+
+__global__ void k_tree_fill(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                            const uint32_t* __restrict__ tbits, const uint32_t* __restrict__ tptr, int32_t n,
+                            int32_t nnz, int32_t Lcap, int32_t* __restrict__ tslot, int32_t* __restrict__ tnbr,
+                            int32_t* __restrict__ tsrc) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int32_t a = clampi(row_ptr[u], 0, nnz), b = clampi(row_ptr[u + 1], a, nnz);
+  uint32_t j = tptr[u];
+  if (a >= b) return;
+  for (int32_t wd = a >> 5; wd <= (b - 1) >> 5; ++wd) {
+    uint32_t x = bits_in(tbits, a, b, wd);
+    while (x) {
+      const int bit = __ffs((int)x) - 1;
+      x &= x - 1;
+      const int32_t k = (wd << 5) + bit;
+      if (j >= (uint32_t)Lcap) return;  // only with a malformed CSR (flagged)
+      tslot[j] = k;
+      tnbr[j] = col[k];
+      tsrc[j] = (int32_t)u;
+      ++j;
+    }
+  }
+}
+
+// scalars: [0] = L (forest half-edges), [1] = global head, [2] = reach
+// twin and cyclic-next successor of every forest half-edge; ids >= L unused
+__global__ void k_succ_csr(const int32_t* __restrict__ tnbr, const int32_t* __restrict__ tsrc,
+                           const uint32_t* __restrict__ tptr, int32_t n, int32_t Lcap,
+                           const int32_t* __restrict__ sc, int32_t* __restrict__ ttwin, int32_t* __restrict__ succ,
+                           uint32_t* __restrict__ status) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= Lcap) return;
+  const int32_t L = sc[0];
+  if (h >= L) {
+    succ[h] = -2;
+    return;
+  }
+  const int32_t u = tsrc[h], w = tnbr[h];
+  if ((uint32_t)u >= (uint32_t)n || (uint32_t)w >= (uint32_t)n) {  // malformed CSR only
+    flag(status, ST_BAD_CSR);
+    ttwin[h] = (int32_t)h;
+    succ[h] = -1;
+    return;
+  }
+  const int32_t beg = min((int32_t)tptr[w], L);
+  const int32_t end = clampi((int32_t)tptr[w + 1], beg, L);
+  int32_t lo = beg, hi = end;
+  while (lo < hi) {
+    const int32_t mid = lo + ((hi - lo) >> 1);
+    if (tnbr[mid] < u) lo = mid + 1;
+    else hi = mid;
+  }
+  int32_t t = lo;
+  if (t >= end || tnbr[t] != u) {
+    flag(status, ST_BAD_CSR);
+    t = (int32_t)h;
+  }
+  ttwin[h] = t;
+  succ[h] = (t + 1 < end) ? t + 1 : beg;  // next() wraps to the run start
+}
+
+// component roots in id order: root u has cc[u] == u and forest degree > 0.
+// rflag[u] = 1 for roots (scanned afterwards into rpos).
+__global__ void k_root_flags(const int32_t* __restrict__ cc, const uint32_t* __restrict__ tdeg, int32_t n,
+                             uint32_t* __restrict__ rflag) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  rflag[u] = (ld(cc + u) == (int32_t)u && tdeg[u] > 0) ? 1u : 0u;
+}
+
+__global__ void k_root_list(const uint32_t* __restrict__ rflag, const uint32_t* __restrict__ rpos, int32_t n,
+                            int32_t* __restrict__ roots) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  if (rflag[u]) roots[rpos[u]] = (int32_t)u;
+}
+
+__global__ void k_set_len(const uint32_t* __restrict__ tptr, int32_t n, int32_t* __restrict__ sc) {
+  const int32_t L = (int32_t)min(tptr[n], (uint32_t)(2 * (n - 1)));
+  sc[0] = L;    // forest half-edges
+  sc[1] = -1;   // head, set by k_link_roots
+  sc[2] = L;    // elements the head must reach
+}
+
+// tail of component i (the half-edge into its root from the root's last
+// forest neighbour) links to the head of component i+1
+__global__ void k_link_roots(const int32_t* __restrict__ roots, const uint32_t* __restrict__ rpos,
+                             const uint32_t* __restrict__ rflag, const uint32_t* __restrict__ tptr,
+                             const int32_t* __restrict__ ttwin, int32_t n, int32_t* __restrict__ succ,
+                             int32_t* __restrict__ sc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t nroots = (int32_t)(rpos[n - 1] + rflag[n - 1]);
+  const int32_t L = sc[0];
+  if (i == 0) sc[1] = (nroots > 0 && (int32_t)tptr[roots[0]] < L) ? (int32_t)tptr[roots[0]] : -1;
+  if (i >= nroots) return;
+  const int32_t r = roots[i];
+  const int32_t last = (int32_t)tptr[r + 1] - 1;
+  if (last < 0 || last >= L) return;  // only with a malformed CSR (flagged)
+  const int32_t tail = ttwin[last];
+  int32_t nxt = -1;
+  if (i + 1 < nroots) nxt = min((int32_t)tptr[roots[i + 1]], L - 1);
+  succ[tail] = nxt;
+}
+
+__global__ void k_rank_of(const uint64_t* __restrict__ packed, const int2* __restrict__ off, int32_t nsub,
+                          int32_t Lcap, const int32_t* __restrict__ sc, int32_t* __restrict__ rank,
+                          uint32_t* __restrict__ status) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= Lcap) return;
+  if (h >= sc[0]) return;
+  const uint64_t p = packed[h];
+  uint32_t s = (uint32_t)p;
+  if (s >= (uint32_t)nsub) {
+    flag(status, ST_BAD_INDEX);
+    s = 0;
+  }
+  rank[h] = off[s].x + (int32_t)((p >> 32) & 0xffffu);
+}
+
+// per forest half-edge: direction, parent edge and subtree size of the
+// child, and the scan weight in tour order
+__global__ void k_direction(const int32_t* __restrict__ rank, const int32_t* __restrict__ ttwin,
+                            const int32_t* __restrict__ tsrc, const int32_t* __restrict__ tnbr,
+                            const int32_t* __restrict__ tslot, const uint32_t* __restrict__ tptr,
+                            const int32_t* cc, int32_t n, int32_t Lcap, const int32_t* __restrict__ sc,
+                            uint32_t* __restrict__ dw, int32_t* __restrict__ vR, int32_t* __restrict__ vsize,
+                            int32_t* __restrict__ vpslot, int32_t* __restrict__ vuslot,
+                            uint32_t* __restrict__ status) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t L = sc[0];
+  if (h >= L) {
+    if (h < Lcap) dw[h] = 0u;
+    return;
+  }
+  const int32_t r = rank[h];
+  const int32_t t = ttwin[h];
+  const int32_t u = tsrc[h], w = tnbr[h];
+  if ((uint32_t)t >= (uint32_t)L || (uint32_t)u >= (uint32_t)n || (uint32_t)w >= (uint32_t)n) {
+    flag(status, ST_BAD_INDEX);
+    return;
+  }
+  const int32_t rt = rank[t];
+  const bool down = r < rt;
+  const bool head = (h == (int64_t)tptr[u]) && (ld(cc + u) == u);
+  if ((uint32_t)r >= (uint32_t)L) {
+    flag(status, ST_BAD_INDEX);
+    return;
+  }
+  dw[r] = (uint32_t)down + (uint32_t)head;
+  if (down) {
+    vR[w] = r;
+    vsize[w] = (rt - r + 1) >> 1;
+    vpslot[w] = tslot[h];
+    vuslot[w] = tslot[t];
+  }
+  if (head) {
+    const int32_t tail = ttwin[clampi((int32_t)tptr[u + 1] - 1, 0, L - 1)];
+    vR[u] = r;
+    vsize[u] = ((rank[tail] - r + 1) >> 1) + 1;
+    vpslot[u] = -1;
+    vuslot[u] = -1;
+  }
+}
+
+__global__ void k_preorder(const int32_t* __restrict__ vR, const int32_t* __restrict__ vpslot,
+                           const uint32_t* __restrict__ I, int32_t n, int32_t Lcap, int32_t* __restrict__ pre) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t r = vR[v];
+  if (r < 0 || r >= Lcap) {
+    pre[v] = -1;
+    return;
+  }
+  pre[v] = (int32_t)I[r] - (vpslot[v] < 0 ? 2 : 1);
+}
+
+// per vertex: min / max preorder over itself and its non-forest neighbours,
+// stored at its own preorder position
+__global__ __launch_bounds__(kB) void k_minmax(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                              const uint32_t* __restrict__ tbits, const int32_t* __restrict__ pre,
+                                              int32_t n, int32_t nnz, int32_t* __restrict__ amin,
+                                              int32_t* __restrict__ amax) {
+  __shared__ int32_t rp[kRowsPerBlock + 1];
+  __shared__ int32_t mn[kRowsPerBlock], mx[kRowsPerBlock];
+  const int32_t r0 = blockIdx.x * kRowsPerBlock;
+  const int cnt = min(kRowsPerBlock, n - r0);
+  for (int i = threadIdx.x; i <= cnt; i += kB) rp[i] = clampi(row_ptr[r0 + i], 0, nnz);
+  for (int i = threadIdx.x; i < cnt; i += kB) {
+    const int32_t p = pre[r0 + i];
+    mn[i] = p;
+    mx[i] = p;
+  }
+  __syncthreads();
+  const int32_t kbeg = rp[0], kend = rp[cnt];
+  for (int32_t k = kbeg + threadIdx.x; k < kend; k += kB) {
+    if ((tbits[k >> 5] >> (k & 31)) & 1u) continue;
+    const int32_t w = col[k];
+    if ((uint32_t)w >= (uint32_t)n) continue;
+    const int32_t pw = pre[w];
+    const int ri = row_of(rp, cnt, k);
+    atomicMin(&mn[ri], pw);
+    atomicMax(&mx[ri], pw);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < cnt; i += kB) {
+    const int32_t p = pre[r0 + i];
+    if (p >= 0 && p < n) {
+      amin[p] = mn[i];
+      amax[p] = mx[i];
+    }
+  }
+}
+
+// in-block (32) prefix / suffix extremes and block extremes
+__global__ __launch_bounds__(kB) void k_rmq_blocks(const int32_t* __restrict__ amin, const int32_t* __restrict__ amax,
+                                                  int32_t n, int32_t* __restrict__ pmin, int32_t* __restrict__ smin,
+                                                  int32_t* __restrict__ pmax, int32_t* __restrict__ smax,
+                                                  int32_t* __restrict__ bmin, int32_t* __restrict__ bmax) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool ok = i < n;
+  const int32_t vmin = ok ? amin[i] : INT32_MAX;
+  const int32_t vmax = ok ? amax[i] : INT32_MIN;
+  const int l = __lane_id() & 31;
+  int32_t a = vmin, b = vmax, c = vmin, d = vmax;
+#pragma unroll
+  for (int s = 1; s < 32; s <<= 1) {
+    const int32_t ua = __shfl_up(a, s, 32), ub = __shfl_up(b, s, 32);
+    const int32_t dc = __shfl_down(c, s, 32), dd = __shfl_down(d, s, 32);
+    if (l >= s) { a = min(a, ua); b = max(b, ub); }
+    if (l + s < 32) { c = min(c, dc); d = max(d, dd); }
+  }
+  if (ok) {
+    pmin[i] = a; pmax[i] = b; smin[i] = c; smax[i] = d;
+  }
+  if (l == 31 && (i >> kRmqLog) < ((n + 31) >> kRmqLog)) {
+    bmin[i >> kRmqLog] = a;
+    bmax[i >> kRmqLog] = b;
+  }
+}
+
+__global__ void k_sparse_level(const int32_t* __restrict__ pmn, const int32_t* __restrict__ pmx, int32_t nb,
+                               int32_t half, int32_t* __restrict__ qmn, int32_t* __restrict__ qmx) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int64_t o = b + half;
+  qmn[b] = (o < nb) ? min(pmn[b], pmn[o]) : pmn[b];
+  qmx[b] = (o < nb) ? max(pmx[b], pmx[o]) : pmx[b];
+}
+
+struct Rmq {
+  const int32_t *amin, *amax, *pmin, *smin, *pmax, *smax;
+  const int32_t* stmin;  // levels concatenated: level k at k * nb
+  const int32_t* stmax;
+  int32_t nb;
+};
+
+__device__ __forceinline__ void rmq(const Rmq& q, int32_t l, int32_t r, int32_t* lo, int32_t* hi) {
+  const int32_t bl = l >> kRmqLog, br = r >> kRmqLog;
+  int32_t mn, mx;
+  if (bl == br) {
+    mn = INT32_MAX;
+    mx = INT32_MIN;
+    for (int32_t i = l; i <= r; ++i) {
+      mn = min(mn, q.amin[i]);
+      mx = max(mx, q.amax[i]);
+    }
+  } else {
+    mn = min(q.smin[l], q.pmin[r]);
+    mx = max(q.smax[l], q.pmax[r]);
+    if (bl + 1 <= br - 1) {
+      const int32_t a = bl + 1, b = br - 1;
+      const int k = msb32((uint32_t)(b - a + 1));
+      const int64_t base = (int64_t)k * q.nb;
+      mn = min(mn, min(q.stmin[base + a], q.stmin[base + b - (1 << k) + 1]));
+      mx = max(mx, max(q.stmax[base + a], q.stmax[base + b - (1 << k) + 1]));
+    }
+  }
+  *lo = mn;
+  *hi = mx;
+}
+
+__global__ __launch_bounds__(kB) void k_bridge_test(const int32_t* __restrict__ pre, const int32_t* __restrict__ vsize,
+                                                   const int32_t* __restrict__ vpslot,
+                                                   const int32_t* __restrict__ vuslot, int32_t n, Rmq q,
+                                                   uint32_t* __restrict__ mask, int64_t* __restrict__ count) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool is_bridge = false;
+  if (v < n) {
+    const int32_t p = pre[v];
+    const int32_t ps = vpslot[v];
+    if (p >= 0 && ps >= 0) {
+      const int32_t r = p + vsize[v] - 1;
+      if (r >= p && r < n) {
+        int32_t lo, hi;
+        rmq(q, p, r, &lo, &hi);
+        if (lo == p && hi == r) {
+          is_bridge = true;
+          const int32_t us = vuslot[v];
+          atomicOr(mask + (ps >> 5), 1u << (ps & 31));
+          if (us >= 0) atomicOr(mask + (us >> 5), 1u << (us & 31));
+        }
+      }
+    }
+  }
+  const uint64_t b = __ballot(is_bridge);
+  if (__lane_id() == 0 && b) atomicAdd((unsigned long long*)count, (unsigned long long)__popcll(b));
+}
+
+__global__ void k_zero_i64(int64_t* p) { *p = 0; }
+
+}  // namespace
+
+int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t nnz, uint32_t* mask,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, s, c->d_bcount);
+  const int32_t words = (int32_t)(((int64_t)nnz + 31) >> 5);
+  if (words > 0)
+    hipLaunchKernelGGL(k_fill_i32, dim3(std::min(ceil_div(words, kB), 4096)), dim3(kB), 0, s,
+                       reinterpret_cast<int32_t*>(mask), (int64_t)words, 0);
+  if (n <= 1 || nnz == 0) return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+
+  const int32_t Lcap = 2 * (n - 1);  // forest half-edges are at most 2(n-1)
+  Scratch sc(c);
+  int32_t* cc = sc.get<int32_t>(n);
+  uint32_t* tbits = sc.get<uint32_t>(words);
+  uint32_t* tdeg = sc.get<uint32_t>((size_t)n + 1);
+  uint32_t* tptr = sc.get<uint32_t>((size_t)n + 1);
+  int32_t* tslot = sc.get<int32_t>(Lcap);
+  int32_t* tnbr = sc.get<int32_t>(Lcap);
+  int32_t* tsrc = sc.get<int32_t>(Lcap);
+  int32_t* ttwin = sc.get<int32_t>(Lcap);
+  int32_t* succ = sc.get<int32_t>(Lcap);
+  int32_t* rank = sc.get<int32_t>(Lcap);
+  uint32_t* dw = sc.get<uint32_t>(Lcap);
+  uint32_t* rflag = sc.get<uint32_t>(n);
+  uint32_t* rpos = sc.get<uint32_t>(n);
+  int32_t* roots = sc.get<int32_t>(n);
+  int32_t* vR = sc.get<int32_t>(n);
+  int32_t* vsize = sc.get<int32_t>(n);
+  int32_t* vpslot = sc.get<int32_t>(n);
+  int32_t* vuslot = sc.get<int32_t>(n);
+  int32_t* pre = sc.get<int32_t>(n);
+  int32_t* amin = sc.get<int32_t>(n);
+  int32_t* amax = sc.get<int32_t>(n);
+  int32_t* pmin = sc.get<int32_t>(n);
+  int32_t* smin = sc.get<int32_t>(n);
+  int32_t* pmax = sc.get<int32_t>(n);
+  int32_t* smax = sc.get<int32_t>(n);
+  const int32_t nb = (n + 31) >> kRmqLog;
+  int levels = 1;
+  while ((1 << levels) <= nb) ++levels;
+  int32_t* stmin = sc.get<int32_t>((size_t)levels * nb);
+  int32_t* stmax = sc.get<int32_t>((size_t)levels * nb);
+  int32_t* scal = sc.get<int32_t>(8);
+  if (sc.failed) return ET_ENOMEM;
+
+  const int gn = ceil_div(n, kB);
+  const int grows = ceil_div(n, kRowsPerBlock);
+  const int gl = ceil_div(Lcap, kB);
+  // 1. spanning forest
+  hipLaunchKernelGGL(k_check_csr, dim3(gn), dim3(kB), 0, s, row_ptr, n, nnz, c->d_status);
+  hipLaunchKernelGGL(k_iota, dim3(gn), dim3(kB), 0, s, cc, n);
+  hipLaunchKernelGGL(k_fill_i32, dim3(std::min(ceil_div(words, kB), 4096)), dim3(kB), 0, s,
+                     reinterpret_cast<int32_t*>(tbits), (int64_t)words, 0);
+  hipLaunchKernelGGL(k_hook, dim3(grows), dim3(kB), 0, s, row_ptr, col, n, nnz, cc, tbits, c->d_status);
+  // 2. forest CSR, twins, successors, component chaining
+  hipLaunchKernelGGL(k_tree_deg, dim3(gn), dim3(kB), 0, s, row_ptr, tbits, n, nnz, tdeg);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, s, reinterpret_cast<int32_t*>(tdeg + n), (int64_t)1, 0);
+  int rc = scan_u32(c, tdeg, tptr, (int64_t)n + 1, ScanOp::Add, true, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_tree_fill, dim3(gn), dim3(kB), 0, s, row_ptr, col, tbits, tptr, n, nnz, Lcap, tslot, tnbr,
+                     tsrc);
+  hipLaunchKernelGGL(k_root_flags, dim3(gn), dim3(kB), 0, s, cc, tdeg, n, rflag);
+  rc = scan_u32(c, rflag, rpos, n, ScanOp::Add, true, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_root_list, dim3(gn), dim3(kB), 0, s, rflag, rpos, n, roots);
+  hipLaunchKernelGGL(k_set_len, dim3(1), dim3(1), 0, s, tptr, n, scal);
+  hipLaunchKernelGGL(k_succ_csr, dim3(gl), dim3(kB), 0, s, tnbr, tsrc, tptr, n, Lcap, scal, ttwin, succ,
+                     c->d_status);
+  hipLaunchKernelGGL(k_link_roots, dim3(gn), dim3(kB), 0, s, roots, rpos, rflag, tptr, ttwin, n, succ, scal);
+  // 3. one list ranking, directions, preorder
+  LRResult lr;
+  rc = list_rank_core(c, sc, succ, Lcap, scal + 1, 1, false, scal + 2, &lr, s, true);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_rank_of, dim3(gl), dim3(kB), 0, s, lr.packed, lr.off, lr.nsub, Lcap, scal, rank,
+                     c->d_status);
+  hipLaunchKernelGGL(k_fill_i32, dim3(std::min(gn, 4096)), dim3(kB), 0, s, vR, (int64_t)n, -1);
+  hipLaunchKernelGGL(k_fill_i32, dim3(std::min(gn, 4096)), dim3(kB), 0, s, vpslot, (int64_t)n, -1);
+  hipLaunchKernelGGL(k_direction, dim3(gl), dim3(kB), 0, s, rank, ttwin, tsrc, tnbr, tslot, tptr, cc, n, Lcap, scal,
+                     dw, vR, vsize, vpslot, vuslot, c->d_status);
+  rc = scan_u32(c, dw, dw, Lcap, ScanOp::Add, false, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_preorder, dim3(gn), dim3(kB), 0, s, vR, vpslot, dw, n, Lcap, pre);
+  // 4. non-forest extremes by preorder
+  hipLaunchKernelGGL(k_minmax, dim3(grows), dim3(kB), 0, s, row_ptr, col, tbits, pre, n, nnz, amin, amax);
+  // 5. range extremes
+  hipLaunchKernelGGL(k_rmq_blocks, dim3(gn), dim3(kB), 0, s, amin, amax, n, pmin, smin, pmax, smax, stmin, stmax);
+  for (int k = 1; k < levels; ++k)
+    hipLaunchKernelGGL(k_sparse_level, dim3(ceil_div(nb, kB)), dim3(kB), 0, s, stmin + (size_t)(k - 1) * nb,
+                       stmax + (size_t)(k - 1) * nb, nb, 1 << (k - 1), stmin + (size_t)k * nb,
+                       stmax + (size_t)k * nb);
+  // 6. test
+  Rmq q{amin, amax, pmin, smin, pmax, smax, stmin, stmax, nb};
+  hipLaunchKernelGGL(k_bridge_test, dim3(gn), dim3(kB), 0, s, pre, vsize, vpslot, vuslot, n, q, mask, c->d_bcount);
+  return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+}
+
+}  // namespace et

@@ -1,0 +1,173 @@
+// Internal declarations of the Euler-tour library: context, scratch pool,
+// device status bits, wave64 helpers and the launchers each .hip unit
+// exports to the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstddef>
+#include <map>
+#include <vector>
+
+#include "../../include/et.h"
+
+namespace et {
+
+// ---------------------------------------------------------------- status bits
+// Kernels OR these into the context's device status word.
+enum : uint32_t {
+  ST_BAD_PARENT = 1u << 0,   // parent id out of range or self parent
+  ST_ROOTS = 1u << 1,        // zero or several roots
+  ST_UNREACHED = 1u << 2,    // an element / node is not reachable from a head (cycle)
+  ST_BAD_SUCC = 1u << 3,     // successor out of range
+  ST_BAD_HEAD = 1u << 4,     // list head out of range or unused
+  ST_OVERFLOW = 1u << 5,     // walk bound or continuation space exhausted
+  ST_BAD_QUERY = 1u << 6,    // query id out of range
+  ST_BAD_CSR = 1u << 7,      // CSR not symmetric / column out of range / rows unsorted
+  ST_BAD_INDEX = 1u << 8,    // a gathered table index failed its bounds check
+};
+
+// ---------------------------------------------------------------- context
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+struct Ctx {
+  int device = 0;
+  // kernel timing: when enabled, every instrumented launch is bracketed by
+  // a pair of events on its stream
+  bool profiling = false;
+  std::vector<ProfRec> prof;
+  std::vector<hipEvent_t> spare_events;
+  uint32_t* d_status = nullptr;      // accumulated status bits
+  int32_t* d_scalars = nullptr;      // small per-call device scalars (root, head, counters)
+  int64_t* d_bcount = nullptr;       // bridge count of the last et_bridges
+  // caching pool: free blocks by size
+  std::multimap<size_t, void*> free_blocks;
+  std::map<void*, size_t> live_blocks;
+  size_t pool_bytes = 0;
+};
+
+// scratch allocation from the context pool (stream-ordered reuse: a block
+// handed back is only reused by later work of the same context)
+void* pool_get(Ctx* c, size_t bytes);
+void pool_put(Ctx* c, void* p);
+
+hipEvent_t prof_event(Ctx* c);
+
+// Brackets the launches issued during its lifetime with events (if enabled).
+struct ProfScope {
+  Ctx* c;
+  hipStream_t s;
+  const char* name;
+  hipEvent_t a = nullptr;
+  ProfScope(Ctx* ctx, hipStream_t st, const char* nm) : c(ctx), s(st), name(nm) {
+    if (c->profiling) {
+      a = prof_event(c);
+      if (a) (void)hipEventRecord(a, s);
+    }
+  }
+  ~ProfScope() {
+    if (a) {
+      hipEvent_t b = prof_event(c);
+      if (b) {
+        (void)hipEventRecord(b, s);
+        c->prof.push_back({name, a, b});
+      }
+    }
+  }
+};
+#define ET_CAT2(a, b) a##b
+#define ET_CAT(a, b) ET_CAT2(a, b)
+#define ET_PROF(ctx, stream, name) ::et::ProfScope ET_CAT(et_prof_, __LINE__)(ctx, stream, name)
+
+struct Scratch {  // RAII helper: returns every block on scope exit
+  Ctx* c;
+  std::vector<void*> blocks;
+  bool failed = false;
+  explicit Scratch(Ctx* ctx) : c(ctx) {}
+  template <typename T>
+  T* get(size_t count) {
+    void* p = pool_get(c, count * sizeof(T) + 16);
+    if (!p) failed = true;
+    else blocks.push_back(p);
+    return static_cast<T*>(p);
+  }
+  ~Scratch() {
+    for (void* p : blocks) pool_put(c, p);
+  }
+};
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const unsigned lane = __lane_id();
+  return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+}
+
+__device__ __forceinline__ void flag(uint32_t* status, uint32_t bits) {
+  atomicOr(status, bits);
+}
+
+// 32-bit integer mixer (lowbias32 of C. Wellons); used to place splitters
+__host__ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+__device__ __forceinline__ int msb32(uint32_t x) { return 31 - __clz((int)x); }
+__device__ __forceinline__ int ctz32(uint32_t x) { return __ffs((int)x) - 1; }
+
+inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------- launchers
+// scan.hip: inclusive scan of u32 over [0, n) with + or xor
+enum class ScanOp { Add, Xor };
+int scan_u32(Ctx* c, const uint32_t* in, uint32_t* out, int64_t n, ScanOp op, bool exclusive,
+             hipStream_t s);
+
+// radix.hip: stable grouping of child ids by parent id (LSD radix sort of
+// (parent, child) pairs). keys_out / vals_out receive the sorted parents and
+// children; scalars[0] = root id, scalars[1] = number of roots; succ[2c] of
+// every non-root c is set to 2c+1 and both root ids to -2.
+int group_by_parent_impl(Ctx* c, const int32_t* parent, int32_t n, uint32_t* keys_out,
+                         int32_t* vals_out, int32_t* succ, int32_t* scalars, hipStream_t s);
+
+// listrank.hip
+struct LRResult {
+  // level-1 sublist decomposition, valid after list_rank_core
+  uint64_t* packed = nullptr;  // per element: sublist id | local rank << 32 | inclusive local down << 48
+  int2* off = nullptr;         // per level-1 sublist: {rank of its first element, down-count before it}
+  int32_t nsub = 0;            // number of level-1 sublist slots
+};
+// tree_weights: element e counts as "down" iff e is even (tree half-edges).
+// expected_reach: number of elements the heads must reach (device scalar or null)
+int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const int32_t* heads,
+                   int32_t nheads, bool tree_weights, const int32_t* expected_reach,
+                   LRResult* out, hipStream_t s, bool empty_head_ok = false);
+int list_rank_generic(Ctx* c, const int32_t* succ, int32_t len, const int32_t* heads,
+                      int32_t nheads, int32_t* rank, hipStream_t s);
+
+}  // namespace et
+
+// the public opaque types
+struct et_ctx {
+  et::Ctx impl;
+};
+
+struct et_tree {
+  et_ctx* ctx;
+  int32_t n;
+  int32_t* d_succ;     // [2n]
+  int32_t* d_rank;     // [2n]
+  int32_t* d_pre;      // [n]
+  int32_t* d_size;     // [n]
+  int4* d_rec;         // [n] {inlabel, asc, depth, pre}
+  int2* d_head;        // [n+2] by inlabel: {parent of path top, its depth}
+  int32_t* d_root;     // device scalar
+};

@@ -1,0 +1,465 @@
+// List ranking and list prefix sums (Section 2.2).
+//
+// The paper ranks the tour with the GPU sublist algorithm of Wei and JaJa
+// rather than pointer jumping. This is an MI355X design of the same idea:
+//
+//  level 1  Splitters: one pseudo-randomly placed element in every chunk of
+//           K consecutive ids (plus every list head) starts a sublist. A
+//           wavefront owns a contiguous range of sublist ids; its 64 lanes
+//           each walk one sublist, and a lane whose sublist ends takes the
+//           next id of the wave's range (ballot + popcount, no atomics), so
+//           lanes stay busy even though sublist lengths are geometric. Each
+//           visited element gets one 8-byte record {sublist, local rank,
+//           local down-count}; each sublist gets {next sublist, length,
+//           down-count}. Sublists longer than 65535 elements are split into
+//           continuation sublists so the local fields fit 16 bits.
+//  level k  The list of sublists is ranked the same way with the sublist
+//           lengths as weights, until it has at most kLdsMax elements.
+//  final    One workgroup ranks the last list in LDS by jumping predecessor
+//           pointers (Wyllie) and checks that every used element is reached
+//           from a head; offsets are then pushed back down the levels.
+//
+// Every walk is bounded and every gathered index is range checked, so a
+// malformed list (a cycle, a shared successor, an id out of range) sets a
+// status bit instead of faulting or hanging.
+#include "et_internal.hpp"
+
+namespace et {
+namespace {
+
+constexpr int kCap = 65535;        // level-1 sublist length cap (16-bit local fields)
+constexpr int kLdsMax = 4096;      // elements the final LDS kernel ranks
+constexpr int kWalkThreads = 256;
+constexpr uint32_t kSalt = 0x9e3779b9u;
+
+__device__ __forceinline__ bool is_splitter(int32_t e, int ks, uint32_t salt) {
+  const uint32_t m = (1u << ks) - 1u;
+  return ((uint32_t)e & m) == (mix32(((uint32_t)e >> ks) ^ salt) & m);
+}
+
+__device__ __forceinline__ int32_t splitter_of_chunk(int32_t i, int ks, uint32_t salt) {
+  const uint32_t m = (1u << ks) - 1u;
+  return (int32_t)(((uint32_t)i << ks) + (mix32((uint32_t)i ^ salt) & m));
+}
+
+__global__ void k_fill_int4(int4* __restrict__ p, int32_t begin, int32_t end, int4 v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + begin;
+  if (i < end) p[i] = v;
+}
+
+__global__ void k_set_scalar(int32_t* __restrict__ p, int32_t v) { *p = v; }
+
+// ------------------------------------------------------------------ level 1
+template <bool TREE>
+__global__ __launch_bounds__(kWalkThreads) void k_walk1(
+    const int32_t* __restrict__ succ, int32_t L, const int32_t* __restrict__ heads, int32_t H, int ks,
+    uint32_t salt, int32_t S, int32_t per_wave, uint64_t* __restrict__ packed, int4* __restrict__ srec,
+    int32_t* __restrict__ cont_ctr, int32_t cont_base, int32_t cont_max, bool empty_ok,
+    uint32_t* __restrict__ status) {
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int32_t total = S + H;
+  int32_t next_id = (int32_t)min<int64_t>(wave * per_wave, total);
+  const int32_t end_id = (int32_t)min<int64_t>((int64_t)next_id + per_wave, total);
+  int32_t cur = -1, sub = 0, j = 0, d = 0;
+  int64_t steps = 0;
+  for (;;) {
+    const bool idle = cur < 0;
+    const uint64_t idle_mask = __ballot(idle);
+    if (idle_mask != 0ull && next_id < end_id) {
+      if (idle) {
+        const int32_t id = next_id + __popcll(idle_mask & lanemask_lt());
+        if (id < end_id) {
+          if (id < S) {
+            const int32_t e = splitter_of_chunk(id, ks, salt);
+            if (e >= L || succ[e] == -2) {
+              srec[id] = make_int4(-3, 0, 0, 0);  // no element here
+            } else {
+              cur = e; sub = id; j = 0; d = 0;
+            }
+          } else {
+            const int32_t e = heads[id - S];
+            if (e == -1 && empty_ok) {
+              srec[id] = make_int4(-1, 0, 0, 0);  // an empty list
+            } else if (e < 0 || e >= L || succ[e] == -2) {
+              flag(status, ST_BAD_HEAD);
+              srec[id] = make_int4(-1, 0, 0, 0);
+            } else if (is_splitter(e, ks, salt)) {
+              srec[id] = make_int4(e >> ks, 0, 0, 0);  // the head's own chunk splitter walks it
+            } else {
+              cur = e; sub = id; j = 0; d = 0;
+            }
+          }
+        }
+      }
+      next_id = min(end_id, next_id + (int32_t)__popcll(idle_mask));
+    }
+    if (__ballot(cur >= 0) == 0ull) {
+      if (next_id >= end_id) break;
+      continue;
+    }
+    if (cur >= 0) {
+      const int32_t nx = succ[cur];
+      if (TREE) d += ((cur & 1) == 0);
+      packed[cur] = (uint64_t)(uint32_t)sub | ((uint64_t)(uint32_t)j << 32) | ((uint64_t)(uint32_t)d << 48);
+      ++j;
+      ++steps;
+      bool stop = true;
+      int32_t link = -1;
+      if (nx == -1) {
+        link = -1;
+      } else if (nx < 0 || nx >= L) {
+        flag(status, ST_BAD_SUCC);
+      } else if (is_splitter(nx, ks, salt)) {
+        link = nx >> ks;
+      } else if (steps > L) {
+        flag(status, ST_OVERFLOW);
+      } else if (j == kCap) {
+        const int32_t nid = atomicAdd(cont_ctr, 1);
+        if (nid >= cont_max) {
+          flag(status, ST_OVERFLOW);
+        } else {
+          srec[sub] = make_int4(cont_base + nid, j, d, 0);
+          sub = cont_base + nid;
+          j = 0;
+          d = 0;
+          stop = false;
+        }
+      } else {
+        stop = false;
+      }
+      if (stop) {
+        srec[sub] = make_int4(link, j, d, 0);
+        cur = -1;
+      } else {
+        cur = nx;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ level k >= 2
+// Input records rec[e] = {next, len, down}; next == -3 marks an unused element.
+// Output per element: el[e] = {sublist, exclusive local len, exclusive local down}.
+__global__ __launch_bounds__(kWalkThreads) void k_walkN(
+    const int4* __restrict__ rec, int32_t T, int32_t hb, int32_t H, int ks, uint32_t salt, int32_t S,
+    int32_t per_wave, int4* __restrict__ el, int4* __restrict__ srec, uint32_t* __restrict__ status) {
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int32_t total = S + H;
+  int32_t next_id = (int32_t)min<int64_t>(wave * per_wave, total);
+  const int32_t end_id = (int32_t)min<int64_t>((int64_t)next_id + per_wave, total);
+  int32_t cur = -1, sub = 0, al = 0, ad = 0;
+  int64_t steps = 0;
+  for (;;) {
+    const bool idle = cur < 0;
+    const uint64_t idle_mask = __ballot(idle);
+    if (idle_mask != 0ull && next_id < end_id) {
+      if (idle) {
+        const int32_t id = next_id + __popcll(idle_mask & lanemask_lt());
+        if (id < end_id) {
+          if (id < S) {
+            const int32_t e = splitter_of_chunk(id, ks, salt);
+            if (e >= T || rec[e].x == -3) {
+              srec[id] = make_int4(-3, 0, 0, 0);
+            } else {
+              cur = e; sub = id; al = 0; ad = 0;
+            }
+          } else {
+            const int32_t e = hb + (id - S);
+            if (e < 0 || e >= T) {
+              flag(status, ST_BAD_HEAD);
+              srec[id] = make_int4(-1, 0, 0, 0);
+            } else if (is_splitter(e, ks, salt)) {
+              srec[id] = make_int4(e >> ks, 0, 0, 0);
+            } else {
+              cur = e; sub = id; al = 0; ad = 0;
+            }
+          }
+        }
+      }
+      next_id = min(end_id, next_id + (int32_t)__popcll(idle_mask));
+    }
+    if (__ballot(cur >= 0) == 0ull) {
+      if (next_id >= end_id) break;
+      continue;
+    }
+    if (cur >= 0) {
+      const int4 r = rec[cur];
+      el[cur] = make_int4(sub, al, ad, 0);
+      al += r.y;
+      ad += r.z;
+      ++steps;
+      const int32_t nx = r.x;
+      bool stop = true;
+      int32_t link = -1;
+      if (nx == -1) {
+        link = -1;
+      } else if (nx < 0 || nx >= T) {
+        flag(status, ST_BAD_SUCC);
+      } else if (is_splitter(nx, ks, salt)) {
+        link = nx >> ks;
+      } else if (steps > T) {
+        flag(status, ST_OVERFLOW);
+      } else {
+        stop = false;
+      }
+      if (stop) {
+        srec[sub] = make_int4(link, al, ad, 0);
+        cur = -1;
+      } else {
+        cur = nx;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ final level (LDS)
+// Exclusive prefix (len, down) from each element's list head, by jumping
+// predecessor pointers in LDS. T <= kLdsMax. Elements whose predecessor
+// chain does not start at a head are unreachable (malformed input).
+constexpr int kFinalThreads = 1024;
+constexpr int kFinalPer = kLdsMax / kFinalThreads;
+
+__global__ __launch_bounds__(kFinalThreads) void k_final_lds(const int4* __restrict__ rec, int32_t T,
+                                                             int32_t hb, int32_t H, int2* __restrict__ off,
+                                                             int32_t* __restrict__ reached,
+                                                             uint32_t* __restrict__ status) {
+  __shared__ int32_t pred[kLdsMax];
+  __shared__ int32_t acl[kLdsMax];
+  __shared__ int32_t acd[kLdsMax];
+  __shared__ int32_t top[kLdsMax];
+  const int t = threadIdx.x;
+  int32_t wl[kFinalPer], wd[kFinalPer];
+  bool used[kFinalPer];
+  for (int k = 0; k < kFinalPer; ++k) pred[t + k * kFinalThreads] = -1;
+  __syncthreads();
+  bool bad = false;
+  for (int k = 0; k < kFinalPer; ++k) {
+    const int e = t + k * kFinalThreads;
+    int4 r = (e < T) ? rec[e] : make_int4(-3, 0, 0, 0);
+    used[k] = (r.x != -3);
+    wl[k] = used[k] ? r.y : 0;
+    wd[k] = used[k] ? r.z : 0;
+    acl[e] = wl[k];
+    acd[e] = wd[k];
+    top[e] = e;
+    if (used[k] && r.x >= 0) {
+      if (r.x < T) pred[r.x] = e;
+      else bad = true;
+    }
+  }
+  if (bad) flag(status, ST_BAD_SUCC);
+  __syncthreads();
+  int rounds = 1;
+  while ((1 << (rounds - 1)) < T) ++rounds;
+  for (int it = 0; it < rounds; ++it) {
+    int32_t np[kFinalPer], nl[kFinalPer], nd[kFinalPer], nt[kFinalPer];
+    for (int k = 0; k < kFinalPer; ++k) {
+      const int e = t + k * kFinalThreads;
+      const int32_t p = pred[e];
+      if (p >= 0) {
+        np[k] = pred[p];
+        nl[k] = acl[e] + acl[p];
+        nd[k] = acd[e] + acd[p];
+        nt[k] = top[p];
+      } else {
+        np[k] = p; nl[k] = acl[e]; nd[k] = acd[e]; nt[k] = top[e];
+      }
+    }
+    __syncthreads();
+    for (int k = 0; k < kFinalPer; ++k) {
+      const int e = t + k * kFinalThreads;
+      pred[e] = np[k]; acl[e] = nl[k]; acd[e] = nd[k]; top[e] = nt[k];
+    }
+    __syncthreads();
+  }
+  int32_t mine = 0;
+  bool unreached = false;
+  for (int k = 0; k < kFinalPer; ++k) {
+    const int e = t + k * kFinalThreads;
+    if (e >= T) continue;
+    const bool from_head = (top[e] >= hb && top[e] < hb + H && pred[e] < 0);
+    if (used[k] && !from_head) unreached = true;
+    if (from_head) mine += wl[k];
+    off[e] = make_int2(acl[e] - wl[k], acd[e] - wd[k]);
+  }
+  if (unreached) flag(status, ST_UNREACHED);
+  for (int dd = 32; dd >= 1; dd >>= 1) mine += __shfl_xor(mine, dd, 64);
+  if (__lane_id() == 0) atomicAdd(reached, mine);
+}
+
+// Final level when many heads keep the list above kLdsMax: one lane per
+// head walks its (short) list.
+__global__ void k_final_walk(const int4* __restrict__ rec, int32_t T, int32_t hb, int32_t H,
+                             int2* __restrict__ off, int32_t* __restrict__ reached,
+                             uint32_t* __restrict__ status) {
+  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= H) return;
+  int32_t e = hb + (int32_t)h, al = 0, ad = 0;
+  int64_t steps = 0;
+  while (e != -1) {
+    if (e < 0 || e >= T || ++steps > T) {
+      flag(status, ST_BAD_SUCC);
+      break;
+    }
+    const int4 r = rec[e];
+    off[e] = make_int2(al, ad);
+    al += r.y;
+    ad += r.z;
+    e = r.x;
+  }
+  atomicAdd(reached, al);
+}
+
+__global__ void k_check_reached(const int32_t* __restrict__ reached, const int32_t* __restrict__ expected,
+                                uint32_t* __restrict__ status) {
+  if (expected && *reached != *expected) flag(status, ST_UNREACHED);
+}
+
+// off_k[e] = off_{k+1}[el[e].sub] + (el[e].len, el[e].down) for used elements
+__global__ void k_push_down(const int4* __restrict__ rec, const int4* __restrict__ el, int32_t T,
+                            const int2* __restrict__ off_up, int32_t T_up, int2* __restrict__ off,
+                            uint32_t* __restrict__ status) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= T) return;
+  if (rec[e].x == -3) return;
+  const int4 x = el[e];
+  if ((uint32_t)x.x >= (uint32_t)T_up) {
+    flag(status, ST_BAD_INDEX);
+    off[e] = make_int2(0, 0);
+    return;
+  }
+  const int2 o = off_up[x.x];
+  off[e] = make_int2(o.x + x.y, o.y + x.z);
+}
+
+// generic rank: rank[e] = off[sub] + local rank, -1 for unused slots
+__global__ void k_rank_fix(const int32_t* __restrict__ succ, const uint64_t* __restrict__ packed, int32_t L,
+                           const int2* __restrict__ off, int32_t T1, int32_t* __restrict__ rank,
+                           uint32_t* __restrict__ status) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= L) return;
+  if (succ[e] == -2) {
+    rank[e] = -1;
+    return;
+  }
+  const uint64_t p = packed[e];
+  const uint32_t sub = (uint32_t)p;
+  if (sub >= (uint32_t)T1) {
+    flag(status, ST_BAD_INDEX);
+    rank[e] = -1;
+    return;
+  }
+  rank[e] = off[sub].x + (int32_t)((p >> 32) & 0xffffu);
+}
+
+__global__ void k_count_used(const int32_t* __restrict__ succ, int32_t L, int32_t* __restrict__ count) {
+  __shared__ int32_t part[4];
+  int32_t c = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < L; e += (int64_t)gridDim.x * blockDim.x)
+    c += (succ[e] != -2);
+  for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+  if (__lane_id() == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(count, part[0] + part[1] + part[2] + part[3]);
+}
+
+int walk_grid(int32_t total, int32_t per_wave) {
+  const int64_t waves = (total + (int64_t)per_wave - 1) / per_wave;
+  return (int)((waves * 64 + kWalkThreads - 1) / kWalkThreads);
+}
+
+}  // namespace
+
+int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const int32_t* heads,
+                   int32_t nheads, bool tree_weights, const int32_t* expected_reach, LRResult* out,
+                   hipStream_t s, bool empty_head_ok) {
+  const int32_t L = len, H = nheads;
+  // level-1 splitter spacing: K = 16 (a sublist averages 16 elements)
+  const int ks1 = (L >= (1 << 12)) ? 4 : 2;
+  const int32_t S1 = (int32_t)(((int64_t)L + (1 << ks1) - 1) >> ks1);
+  const int32_t cont_max = L / kCap + H + 64;
+  const int32_t T1 = S1 + H + cont_max;
+  uint64_t* packed = sc.get<uint64_t>((size_t)L);
+  int4* rec1 = sc.get<int4>((size_t)T1);
+  int32_t* ctr = sc.get<int32_t>(4);
+  if (sc.failed) return ET_ENOMEM;
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, ctr, 0);
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, ctr + 1, 0);
+  hipLaunchKernelGGL(k_fill_int4, dim3(ceil_div(cont_max, 256)), dim3(256), 0, s, rec1, S1 + H, T1,
+                     make_int4(-3, 0, 0, 0));
+  const int32_t per_wave1 = 256;
+  if (tree_weights)
+    hipLaunchKernelGGL(k_walk1<true>, dim3(walk_grid(S1 + H, per_wave1)), dim3(kWalkThreads), 0, s, succ, L,
+                       heads, H, ks1, kSalt, S1, per_wave1, packed, rec1, ctr, S1 + H, cont_max,
+                       empty_head_ok, c->d_status);
+  else
+    hipLaunchKernelGGL(k_walk1<false>, dim3(walk_grid(S1 + H, per_wave1)), dim3(kWalkThreads), 0, s, succ,
+                       L, heads, H, ks1, kSalt, S1, per_wave1, packed, rec1, ctr, S1 + H, cont_max,
+                       empty_head_ok, c->d_status);
+
+  // upper levels: (records, element outputs) per level
+  struct Lvl {
+    const int4* rec;
+    int32_t T, hb;
+    int4* el;
+    int2* off;
+  };
+  std::vector<Lvl> lv;
+  lv.push_back({rec1, T1, S1, nullptr, nullptr});
+  for (;;) {
+    Lvl& cur = lv.back();
+    if (cur.T <= kLdsMax) break;
+    const int ks = 3;  // K = 8
+    const int32_t S = (int32_t)(((int64_t)cur.T + 7) >> ks);
+    const int32_t Tn = S + H;
+    if ((int64_t)Tn * 2 > cur.T) break;  // many heads: shrinking stalls
+    int4* el = sc.get<int4>((size_t)cur.T);
+    int4* rec = sc.get<int4>((size_t)Tn);
+    if (sc.failed) return ET_ENOMEM;
+    const int32_t per_wave = 128;
+    hipLaunchKernelGGL(k_walkN, dim3(walk_grid(Tn, per_wave)), dim3(kWalkThreads), 0, s, cur.rec, cur.T,
+                       cur.hb, H, ks, kSalt ^ (uint32_t)lv.size(), S, per_wave, el, rec, c->d_status);
+    cur.el = el;
+    lv.push_back({rec, Tn, S, nullptr, nullptr});
+  }
+  for (auto& l : lv) {
+    l.off = sc.get<int2>((size_t)l.T);
+  }
+  if (sc.failed) return ET_ENOMEM;
+  Lvl& top = lv.back();
+  if (top.T <= kLdsMax) {
+    hipLaunchKernelGGL(k_final_lds, dim3(1), dim3(kFinalThreads), 0, s, top.rec, top.T, top.hb, H, top.off,
+                       ctr + 1, c->d_status);
+  } else {
+    hipLaunchKernelGGL(k_final_walk, dim3(ceil_div(H, 256)), dim3(256), 0, s, top.rec, top.T, top.hb, H,
+                       top.off, ctr + 1, c->d_status);
+  }
+  hipLaunchKernelGGL(k_check_reached, dim3(1), dim3(1), 0, s, ctr + 1, expected_reach, c->d_status);
+  for (int k = (int)lv.size() - 2; k >= 0; --k) {
+    hipLaunchKernelGGL(k_push_down, dim3(ceil_div(lv[k].T, 256)), dim3(256), 0, s, lv[k].rec, lv[k].el,
+                       lv[k].T, lv[k + 1].off, lv[k + 1].T, lv[k].off, c->d_status);
+  }
+  out->packed = packed;
+  out->off = lv[0].off;
+  out->nsub = T1;
+  return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+}
+
+int list_rank_generic(Ctx* c, const int32_t* succ, int32_t len, const int32_t* heads, int32_t nheads,
+                      int32_t* rank, hipStream_t s) {
+  if (len == 0) return ET_OK;
+  Scratch sc(c);
+  int32_t* expected = sc.get<int32_t>(1);
+  if (sc.failed) return ET_ENOMEM;
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, expected, 0);
+  hipLaunchKernelGGL(k_count_used, dim3(std::min(ceil_div(len, 256), 2048)), dim3(256), 0, s, succ, len,
+                     expected);
+  LRResult r;
+  int rc = list_rank_core(c, sc, succ, len, heads, nheads, false, expected, &r, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_rank_fix, dim3(ceil_div(len, 256)), dim3(256), 0, s, succ, r.packed, len, r.off,
+                     r.nsub, rank, c->d_status);
+  return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+}
+
+}  // namespace et

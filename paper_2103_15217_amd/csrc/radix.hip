@@ -1,0 +1,190 @@
+// Stable grouping of the children of every node by parent id.
+//
+// The paper builds the DCEL by lexicographically sorting half-edges
+// (Section 2.1) and remarks that this sort dominates construction. With a
+// parent array as input the half-edges of node x are its children, and a
+// stable sort of the child ids by parent id puts every node's children next
+// to each other in ascending id order, which is all the successor step
+// needs. This is an LSD radix sort with 8-bit digits over the
+// ceil(log2 n) key bits (3 passes at n = 2^24):
+//
+//   upsweep    per 4096-element tile, a digit histogram (one LDS histogram
+//              per wavefront), stored digit-major so that one exclusive scan
+//              gives every (digit, tile) its output offset;
+//   scan       the array scan of scan.hip;
+//   downsweep  each wavefront ranks its 16 rounds of 64 keys stably: 8
+//              ballots find the lanes that share a digit, the lowest such
+//              lane bumps the wavefront's LDS counter for that digit, and
+//              the four wavefront counters are chained per digit.
+//
+// The first pass reads the parent array directly (the root's -1 becomes the
+// all-ones key and sorts last), validates it, finds the root, and writes
+// the successor of every down half-edge of a leaf (2c -> 2c+1).
+#include "et_internal.hpp"
+
+namespace et {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kRounds = 16;
+constexpr int kTile = kThreads * kRounds;  // 4096 keys per tile
+
+__device__ __forceinline__ uint32_t parent_key(int32_t p, int32_t n) {
+  return (p >= 0 && p < n) ? (uint32_t)p : 0xffffffffu;
+}
+
+// scalars[0] = root id, scalars[1] = number of roots
+template <bool FIRST>
+__global__ __launch_bounds__(kThreads) void k_upsweep(const void* __restrict__ keys_in, int32_t n, int shift,
+                                                      int nbits, int32_t ntiles, uint32_t* __restrict__ hist,
+                                                      int32_t* __restrict__ succ, int32_t* __restrict__ scalars,
+                                                      uint32_t* __restrict__ status) {
+  __shared__ uint32_t h[kWaves][256];
+  const int wave = threadIdx.x >> 6;
+  const uint32_t mask = (1u << nbits) - 1u;
+  for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&h[0][0])[i] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  bool bad = false;
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t idx = base + r * kThreads + threadIdx.x;
+    if (idx >= n) break;
+    uint32_t key;
+    if (FIRST) {
+      const int32_t p = static_cast<const int32_t*>(keys_in)[idx];
+      key = parent_key(p, n);
+      if (p == -1) {
+        atomicAdd(&scalars[1], 1);
+        scalars[0] = (int32_t)idx;
+        succ[2 * idx] = -2;
+        succ[2 * idx + 1] = -2;
+      } else {
+        if (p < 0 || p >= n || p == idx) bad = true;
+        succ[2 * idx] = (int32_t)(2 * idx + 1);  // leaf unless overwritten by the successor step
+      }
+    } else {
+      key = static_cast<const uint32_t*>(keys_in)[idx];
+    }
+    atomicAdd(&h[wave][(key >> shift) & mask], 1u);
+  }
+  if (bad) flag(status, ST_BAD_PARENT);
+  __syncthreads();
+  for (int d = threadIdx.x; d <= (int)mask; d += kThreads)
+    hist[(int64_t)d * ntiles + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+}
+
+template <bool FIRST>
+__global__ __launch_bounds__(kThreads) void k_downsweep(const void* __restrict__ keys_in,
+                                                        const int32_t* __restrict__ vals_in, int32_t n, int shift,
+                                                        int nbits, int32_t ntiles,
+                                                        const uint32_t* __restrict__ offsets,
+                                                        uint32_t* __restrict__ keys_out,
+                                                        int32_t* __restrict__ vals_out) {
+  __shared__ uint32_t cnt[kWaves][256];
+  __shared__ uint32_t base_off[kWaves][256];
+  const int wave = threadIdx.x >> 6;
+  const uint32_t mask = (1u << nbits) - 1u;
+  for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&cnt[0][0])[i] = 0;
+  __syncthreads();
+  const int64_t wbase = (int64_t)blockIdx.x * kTile + (int64_t)wave * (64 * kRounds) + __lane_id();
+  const uint64_t below = lanemask_lt();
+  uint32_t key[kRounds];
+  int32_t val[kRounds];
+  uint32_t rnk[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t idx = wbase + r * 64;
+    const bool valid = idx < n;
+    if (FIRST) {
+      key[r] = valid ? parent_key(static_cast<const int32_t*>(keys_in)[idx], n) : 0u;
+      val[r] = (int32_t)idx;
+    } else {
+      key[r] = valid ? static_cast<const uint32_t*>(keys_in)[idx] : 0u;
+      val[r] = valid ? vals_in[idx] : 0;
+    }
+    const uint32_t dg = (key[r] >> shift) & mask;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+      const bool bit = (dg >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const uint32_t lower = (uint32_t)__popcll(peers & below);
+    const uint32_t c0 = cnt[wave][dg];
+    rnk[r] = c0 + lower;
+    if (valid && lower == 0) cnt[wave][dg] = c0 + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d <= (int)mask; d += kThreads) {
+    uint32_t run = offsets[(int64_t)d * ntiles + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      base_off[w][d] = run;
+      run += cnt[w][d];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t idx = wbase + r * 64;
+    if (idx < n) {
+      const uint32_t dg = (key[r] >> shift) & mask;
+      const uint32_t pos = base_off[wave][dg] + rnk[r];
+      keys_out[pos] = key[r];
+      vals_out[pos] = val[r];
+    }
+  }
+}
+
+__global__ void k_reset_root(int32_t* __restrict__ scalars) {
+  scalars[0] = -1;
+  scalars[1] = 0;
+}
+
+}  // namespace
+
+// keys_out / vals_out receive the stable order; scalars[0] = root, scalars[1]
+// = number of roots; succ[2c] of every non-root c is set to 2c+1 and both
+// root ids to -2.
+int group_by_parent_impl(Ctx* c, const int32_t* parent, int32_t n, uint32_t* keys_out, int32_t* vals_out,
+                         int32_t* succ, int32_t* scalars, hipStream_t s) {
+  int bits = 1;
+  while (bits < 31 && (1ll << bits) < n) ++bits;
+  const int passes = (bits + 7) / 8;
+  const int32_t ntiles = ceil_div(n, kTile);
+  Scratch sc(c);
+  uint32_t* hist = sc.get<uint32_t>((size_t)256 * ntiles);
+  uint32_t* tk = sc.get<uint32_t>((size_t)n);
+  int32_t* tv = sc.get<int32_t>((size_t)n);
+  if (sc.failed) return ET_ENOMEM;
+  hipLaunchKernelGGL(k_reset_root, dim3(1), dim3(1), 0, s, scalars);
+  const void* kin = parent;
+  const int32_t* vin = nullptr;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    const int nbits = std::min(8, bits - shift);
+    const bool to_out = ((passes - 1 - p) % 2) == 0;
+    uint32_t* kout = to_out ? keys_out : tk;
+    int32_t* vout = to_out ? vals_out : tv;
+    if (p == 0)
+      hipLaunchKernelGGL(k_upsweep<true>, dim3(ntiles), dim3(kThreads), 0, s, kin, n, shift, nbits, ntiles, hist,
+                         succ, scalars, c->d_status);
+    else
+      hipLaunchKernelGGL(k_upsweep<false>, dim3(ntiles), dim3(kThreads), 0, s, kin, n, shift, nbits, ntiles,
+                         hist, succ, scalars, c->d_status);
+    int rc = scan_u32(c, hist, hist, (int64_t)(1 << nbits) * ntiles, ScanOp::Add, true, s);
+    if (rc) return rc;
+    if (p == 0)
+      hipLaunchKernelGGL(k_downsweep<true>, dim3(ntiles), dim3(kThreads), 0, s, kin, vin, n, shift, nbits, ntiles,
+                         hist, kout, vout);
+    else
+      hipLaunchKernelGGL(k_downsweep<false>, dim3(ntiles), dim3(kThreads), 0, s, kin, vin, n, shift, nbits,
+                         ntiles, hist, kout, vout);
+    kin = kout;
+    vin = vout;
+  }
+  return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+}
+
+}  // namespace et

@@ -1,0 +1,291 @@
+// Euler tour of a rooted tree, node statistics and the Inlabel tables
+// (Sections 2.1, 2.2 and 3.1), and the LCA query kernel (Section 3.1).
+//
+// Build, for a parent array of n nodes:
+//   1. group_by_parent: children of every node, ascending (radix.hip).
+//   2. k_succ: over the grouped order, succ(2c+1) = 2 * next sibling of c,
+//      or 2 * parent(c) + 1 after the last sibling (-1 below the root), and
+//      succ(2p) = 2 * first child of p; leaves keep succ(2c) = 2c+1. This is
+//      next(twin(e)) of the paper's DCEL with the children of a node in
+//      ascending order and the tour split before the root's first child.
+//   3. one list ranking of the 2n half-edges, carrying the number of down
+//      half-edges (Section 2: weights on the tour give preorder and level).
+//   4. k_node: rank(2c) = R0, number of down half-edges up to it = D; then
+//      pre(c) = D, depth(c) = 2D - R0 - 1, size(c) = (rank(2c+1) - R0 + 1)/2,
+//      and inlabel(c) = the member of [pre+1, pre+size] with the most
+//      trailing zeros, in closed form (j >> k) << k with j = pre + size and
+//      k the highest bit in which pre and j differ.
+//   5. k_head: a node is the top of its inlabel path iff it is the root or
+//      its parent's inlabel differs; head[inlabel] = {parent, depth - 1}.
+//      Each path top c puts 2^h(inlabel c) on both of its half-edges in tour
+//      order (every other half-edge gets 0).
+//   6. an xor array scan over the tour (the paper's one-ranking-then-scans
+//      optimisation, Section 2.2): at rank(2v) the prefix xor holds the bits
+//      of exactly the path tops above or at v, whose levels are distinct, so
+//      xor = or = ascendant(v) without the root's bit (added by k_asc).
+#include "et_internal.hpp"
+
+namespace et {
+namespace {
+
+constexpr int kB = 256;
+
+enum { SC_ROOT = 0, SC_NROOTS = 1, SC_HEAD = 2, SC_EXPECT = 3 };
+
+__global__ void k_succ(const uint32_t* __restrict__ keys, const int32_t* __restrict__ vals, int32_t n,
+                       int32_t* __restrict__ sc, int32_t* __restrict__ succ, uint32_t* __restrict__ status) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int32_t root = sc[SC_ROOT];
+  if (k == 0) {
+    if (sc[SC_NROOTS] != 1) flag(status, ST_ROOTS);
+    sc[SC_EXPECT] = 2 * (n - 1);
+  }
+  const int32_t c = vals[k];
+  if (c == root) return;
+  const uint32_t p = keys[k];
+  if (p >= (uint32_t)n) return;  // invalid parent, already flagged
+  int64_t k2 = k + 1;
+  if (k2 < n && vals[k2] == root) ++k2;
+  int32_t nxt;
+  if (k2 < n && keys[k2] == p) nxt = 2 * vals[k2];
+  else nxt = ((int32_t)p == root) ? -1 : (int32_t)(2 * p + 1);
+  succ[2 * c + 1] = nxt;
+  int64_t k0 = k - 1;
+  if (k0 >= 0 && vals[k0] == root) --k0;
+  if (k0 < 0 || keys[k0] != p) {
+    if ((int32_t)p == root) sc[SC_HEAD] = 2 * c;
+    else succ[2 * p] = 2 * c;
+  }
+}
+
+__device__ __forceinline__ uint32_t inlabel_of(int32_t pre, int32_t size) {
+  const uint32_t j = (uint32_t)pre + (uint32_t)size;          // pre+1 .. pre+size, 1-based
+  const int k = msb32((uint32_t)pre ^ j);                      // (p-1) xor j with p = pre+1
+  return (j >> k) << k;
+}
+
+__global__ void k_node(const uint64_t* __restrict__ packed, const int2* __restrict__ off, int32_t nsub,
+                       int32_t n, const int32_t* __restrict__ sc, int32_t* __restrict__ rank,
+                       int32_t* __restrict__ pre_out, int32_t* __restrict__ size_out, int4* __restrict__ rec,
+                       uint32_t* __restrict__ status) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int32_t root = sc[SC_ROOT];
+  int32_t depth, pre, size, r0, r1;
+  if (c == root) {
+    depth = 0; pre = 0; size = n; r0 = -1; r1 = -1;
+  } else {
+    const ulonglong2 pk = reinterpret_cast<const ulonglong2*>(packed)[c];
+    uint32_t s0 = (uint32_t)pk.x, s1 = (uint32_t)pk.y;
+    if (s0 >= (uint32_t)nsub || s1 >= (uint32_t)nsub) {
+      flag(status, ST_BAD_INDEX);
+      s0 = 0; s1 = 0;
+    }
+    const int2 o0 = off[s0];
+    const int2 o1 = off[s1];
+    r0 = o0.x + (int32_t)((pk.x >> 32) & 0xffffu);
+    const int32_t dn = o0.y + (int32_t)(pk.x >> 48);
+    r1 = o1.x + (int32_t)((pk.y >> 32) & 0xffffu);
+    pre = dn;
+    depth = 2 * dn - r0 - 1;
+    size = (r1 - r0 + 1) >> 1;
+  }
+  reinterpret_cast<int2*>(rank)[c] = make_int2(r0, r1);
+  pre_out[c] = pre;
+  size_out[c] = size;
+  rec[c] = make_int4((int32_t)inlabel_of(pre, size), 0, depth, pre);
+}
+
+__global__ void k_head(const int32_t* __restrict__ parent, const int4* __restrict__ rec,
+                       const int32_t* __restrict__ rank, int32_t n, const int32_t* __restrict__ sc,
+                       int2* __restrict__ head, uint32_t* __restrict__ xw, int32_t L,
+                       uint32_t* __restrict__ status) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t root = sc[SC_ROOT];
+  const int4 rv = rec[v];
+  const uint32_t inl = (uint32_t)rv.x;
+  const int32_t p = parent[v];
+  bool top;
+  if (v == root) {
+    top = true;
+  } else if ((uint32_t)p < (uint32_t)n) {
+    top = (uint32_t)rec[p].x != inl;
+  } else {
+    top = true;
+    flag(status, ST_BAD_INDEX);
+  }
+  if (top) {
+    if (inl >= 1u && inl <= (uint32_t)n) head[inl] = make_int2(v == root ? -1 : p, rv.z - 1);
+    else flag(status, ST_BAD_INDEX);
+  }
+  if (v != root) {
+    const uint32_t w = (top && inl) ? (1u << ctz32(inl)) : 0u;
+    const int2 r = reinterpret_cast<const int2*>(rank)[v];
+    if ((uint32_t)r.x < (uint32_t)L && (uint32_t)r.y < (uint32_t)L) {
+      xw[r.x] = w;
+      xw[r.y] = w;
+    } else {
+      flag(status, ST_BAD_INDEX);
+    }
+  }
+}
+
+__global__ void k_asc(int4* __restrict__ rec, const int32_t* __restrict__ rank, const uint32_t* __restrict__ X,
+                      int32_t n, int32_t L, const int32_t* __restrict__ sc, uint32_t* __restrict__ status) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t root = sc[SC_ROOT];
+  uint32_t rootbit = 1u;
+  if ((uint32_t)root < (uint32_t)n) {
+    const uint32_t ri = (uint32_t)rec[root].x;
+    rootbit = ri ? (1u << ctz32(ri)) : 1u;
+  }
+  uint32_t asc = rootbit;
+  if (v != root) {
+    const int32_t r0 = rank[2 * v];
+    if ((uint32_t)r0 < (uint32_t)L) asc ^= X[r0];
+    else flag(status, ST_BAD_INDEX);
+  }
+  reinterpret_cast<int32_t*>(rec)[4 * v + 1] = (int32_t)asc;
+}
+
+// n == 1: the root is the only node
+__global__ void k_single(const int32_t* __restrict__ parent, int32_t* __restrict__ sc, int32_t* __restrict__ succ,
+                         int32_t* __restrict__ rank, int32_t* __restrict__ pre, int32_t* __restrict__ size,
+                         int4* __restrict__ rec, int2* __restrict__ head, uint32_t* __restrict__ status) {
+  if (parent[0] != -1) flag(status, ST_ROOTS);
+  sc[SC_ROOT] = 0;
+  succ[0] = succ[1] = -2;
+  rank[0] = rank[1] = -1;
+  pre[0] = 0;
+  size[0] = 1;
+  rec[0] = make_int4(1, 1, 0, 0);
+  head[1] = make_int2(-1, -1);
+}
+
+__global__ void k_export_rec(const int4* __restrict__ rec, int32_t n, int32_t* __restrict__ depth,
+                             uint32_t* __restrict__ inl, uint32_t* __restrict__ asc) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int4 r = rec[v];
+  if (depth) depth[v] = r.z;
+  if (inl) inl[v] = (uint32_t)r.x;
+  if (asc) asc[v] = (uint32_t)r.y;
+}
+
+// Schieber-Vishkin query, one lane per query. a = inlabel(x), b = inlabel(y).
+//  - a == b: x and y lie on one path; the shallower one is the LCA.
+//  - otherwise the LCA of a and b in the binary tree has height
+//    i = max(h(a), h(b), msb(a xor b)); the LCA's inlabel has height
+//    j = the lowest common ascendant bit at or above i; on each side the
+//    node closest to it on the LCA's path is the side itself (if its own
+//    label has height j) or the parent of the top of the path entered
+//    below it, whose label keeps the bits above the highest ascendant bit
+//    k < j and sets bit k; the shallower of the two is the LCA.
+__global__ __launch_bounds__(kB) void k_lca(const int4* __restrict__ rec, const int2* __restrict__ head, int32_t n,
+                                           const int32_t* __restrict__ qx, const int32_t* __restrict__ qy,
+                                           int64_t q, int32_t* __restrict__ out, uint32_t* __restrict__ status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= q) return;
+  const int32_t x = qx[i], y = qy[i];
+  if ((uint32_t)x >= (uint32_t)n || (uint32_t)y >= (uint32_t)n) {
+    flag(status, ST_BAD_QUERY);
+    out[i] = -1;
+    return;
+  }
+  const int4 rx = rec[x];
+  const int4 ry = rec[y];
+  const uint32_t a = (uint32_t)rx.x, b = (uint32_t)ry.x;
+  int32_t res;
+  if (a == b) {
+    res = (rx.z <= ry.z) ? x : y;
+  } else {
+    const int ha = ctz32(a), hb = ctz32(b);
+    const int i0 = max(max(ha, hb), msb32(a ^ b));
+    const uint32_t ax = (uint32_t)rx.y, ay = (uint32_t)ry.y;
+    const uint32_t common = ax & ay & (~0u << i0);
+    if (common == 0u) {
+      flag(status, ST_BAD_INDEX);
+      out[i] = -1;
+      return;
+    }
+    const int j = ctz32(common);
+    const uint32_t low = (1u << j) - 1u;
+    int32_t xv = x, xd = rx.z, yv = y, yd = ry.z;
+    if (ha != j) {
+      const int k = msb32(ax & low);
+      const uint32_t w = ((a >> (k + 1)) << (k + 1)) | (1u << k);
+      const int2 h = head[min(w, (uint32_t)n)];
+      xv = h.x; xd = h.y;
+    }
+    if (hb != j) {
+      const int k = msb32(ay & low);
+      const uint32_t w = ((b >> (k + 1)) << (k + 1)) | (1u << k);
+      const int2 h = head[min(w, (uint32_t)n)];
+      yv = h.x; yd = h.y;
+    }
+    res = (xd <= yd) ? xv : yv;
+  }
+  out[i] = res;
+}
+
+}  // namespace
+
+int tree_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
+  const int32_t n = t->n;
+  int32_t* sc = t->d_root;
+  if (n == 1) {
+    hipLaunchKernelGGL(k_single, dim3(1), dim3(1), 0, s, parent, sc, t->d_succ, t->d_rank, t->d_pre, t->d_size,
+                       t->d_rec, t->d_head, c->d_status);
+    return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+  }
+  const int32_t L2 = 2 * n;          // half-edge id space
+  const int32_t L = 2 * (n - 1);     // tour length
+  Scratch scr(c);
+  uint32_t* kv = scr.get<uint32_t>((size_t)L2);  // sorted parents | children, later the xor weights
+  if (scr.failed) return ET_ENOMEM;
+  uint32_t* keys = kv;
+  int32_t* vals = reinterpret_cast<int32_t*>(kv + n);
+  int rc = group_by_parent_impl(c, parent, n, keys, vals, t->d_succ, sc, s);
+  if (rc) return rc;
+  const int gn = ceil_div(n, kB);
+  hipLaunchKernelGGL(k_succ, dim3(gn), dim3(kB), 0, s, keys, vals, n, sc, t->d_succ, c->d_status);
+  LRResult lr;
+  rc = list_rank_core(c, scr, t->d_succ, L2, sc + SC_HEAD, 1, true, sc + SC_EXPECT, &lr, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_node, dim3(gn), dim3(kB), 0, s, lr.packed, lr.off, lr.nsub, n, sc, t->d_rank, t->d_pre,
+                     t->d_size, t->d_rec, c->d_status);
+  uint32_t* xw = kv;
+  hipLaunchKernelGGL(k_head, dim3(gn), dim3(kB), 0, s, parent, t->d_rec, t->d_rank, n, sc, t->d_head, xw, L,
+                     c->d_status);
+  rc = scan_u32(c, xw, xw, L, ScanOp::Xor, false, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_asc, dim3(gn), dim3(kB), 0, s, t->d_rec, t->d_rank, xw, n, L, sc, c->d_status);
+  return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+}
+
+int tree_export(const et_tree* t, int32_t* succ, int32_t* rank, int32_t* depth, int32_t* pre, int32_t* size,
+                uint32_t* inl, uint32_t* asc, hipStream_t s) {
+  const int32_t n = t->n;
+  const size_t b = (size_t)n * sizeof(int32_t);
+  if (succ && hipMemcpyAsync(succ, t->d_succ, 2 * b, hipMemcpyDeviceToDevice, s) != hipSuccess) return ET_EHIP;
+  if (rank && hipMemcpyAsync(rank, t->d_rank, 2 * b, hipMemcpyDeviceToDevice, s) != hipSuccess) return ET_EHIP;
+  if (pre && hipMemcpyAsync(pre, t->d_pre, b, hipMemcpyDeviceToDevice, s) != hipSuccess) return ET_EHIP;
+  if (size && hipMemcpyAsync(size, t->d_size, b, hipMemcpyDeviceToDevice, s) != hipSuccess) return ET_EHIP;
+  if (depth || inl || asc)
+    hipLaunchKernelGGL(k_export_rec, dim3(ceil_div(n, kB)), dim3(kB), 0, s, t->d_rec, n, depth, inl, asc);
+  return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+}
+
+int tree_lca(Ctx* c, const et_tree* t, const int32_t* qx, const int32_t* qy, int64_t q, int32_t* out,
+             hipStream_t s) {
+  if (q == 0) return ET_OK;
+  const int64_t blocks = (q + kB - 1) / kB;
+  hipLaunchKernelGGL(k_lca, dim3((unsigned)blocks), dim3(kB), 0, s, t->d_rec, t->d_head, t->n, qx, qy, q, out,
+                     c->d_status);
+  return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+}
+
+}  // namespace et

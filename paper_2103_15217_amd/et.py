@@ -1,0 +1,227 @@
+"""Thin Python binding of ``libet.so`` (the C ABI in ``include/et.h``).
+
+Argument marshalling only: every step runs in the HIP kernels of the
+library. Tensors must be contiguous int32 / uint32 device tensors on the
+context's device; the HIP stream is torch's current stream. If the library
+is not built this module raises on import: there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libet.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_2103_15217_amd/build.py "
+                      "(or __graft_entry__.build()); there is no fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_P = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_SIG = {
+    "et_version": ([], ctypes.c_int),
+    "et_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "et_ctx_create": ([ctypes.POINTER(_P)], ctypes.c_int),
+    "et_ctx_destroy": ([_P], None),
+    "et_ctx_status": ([_P, _P], ctypes.c_int),
+    "et_ctx_status_bits": ([_P, _P, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
+    "et_list_rank": ([_P, _P, _i32, _P, _i32, _P, _P], ctypes.c_int),
+    "et_tree_build": ([_P, _P, _i32, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "et_tree_size": ([_P], _i32),
+    "et_tree_export": ([_P, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "et_tree_free": ([_P, _P], None),
+    "et_lca": ([_P, _P, _P, _i64, _P, _P], ctypes.c_int),
+    "et_bridges": ([_P, _P, _P, _i32, _i32, _P, ctypes.POINTER(_i64), _P], ctypes.c_int),
+    "et_bridges_count": ([_P, _P, _P], ctypes.c_int),
+}
+for _name, (_args, _res) in _SIG.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+
+ET_OK, ET_EINVAL, ET_ENOMEM, ET_EHIP, ET_EINPUT = 0, -1, -2, -3, -4
+
+STATUS_BITS = {
+    1 << 0: "bad parent", 1 << 1: "root count", 1 << 2: "unreached element",
+    1 << 3: "bad successor", 1 << 4: "bad head", 1 << 5: "walk bound exceeded",
+    1 << 6: "bad query", 1 << 7: "bad CSR", 1 << 8: "table index out of range",
+}
+
+
+class EtError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {_lib.et_strerror(code).decode()} ({code})")
+
+
+def _check(rc, what):
+    if rc != ET_OK:
+        raise EtError(rc, what)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def version():
+    return _lib.et_version()
+
+
+class Context:
+    """An ``et_ctx``: scratch pool and device status word on the current device."""
+
+    def __init__(self):
+        h = _P()
+        _check(_lib.et_ctx_create(ctypes.byref(h)), "et_ctx_create")
+        self._h = h
+        self.device = torch.cuda.current_device()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def status_bits(self):
+        bits = ctypes.c_uint32(0)
+        _check(_lib.et_ctx_status_bits(self._h, _stream(), ctypes.byref(bits)), "et_ctx_status_bits")
+        return int(bits.value)
+
+    def check(self):
+        """Wait for the stream and raise EtError(ET_EINPUT) if a kernel flagged bad input."""
+        bits = self.status_bits()
+        if bits:
+            names = [v for k, v in STATUS_BITS.items() if bits & k]
+            raise EtError(ET_EINPUT, "device status: " + ", ".join(names))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.et_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default = None
+
+
+def default_context():
+    global _default
+    if _default is None:
+        _default = Context()
+    return _default
+
+
+# ------------------------------------------------------------------ list ranking
+
+def et_list_rank(succ, heads, rank=None, ctx=None):
+    """Rank of every element of the lists starting at ``heads`` (head = 0);
+    ``succ[e] == -1`` ends a list and ``-2`` marks an unused slot (rank -1)."""
+    ctx = ctx or default_context()
+    succ = _dev(succ, torch.int32, "succ")
+    heads = _dev(heads, torch.int32, "heads")
+    if rank is None:
+        rank = torch.empty_like(succ)
+    _check(_lib.et_list_rank(ctx.handle, _ptr(succ), succ.numel(), _ptr(heads), heads.numel(),
+                             _ptr(rank), _stream()), "et_list_rank")
+    return rank
+
+
+# ------------------------------------------------------------------ trees and LCA
+
+class Tree:
+    """A built tree (``et_tree``): Euler tour, node statistics, Inlabel tables."""
+
+    def __init__(self, handle, n, ctx):
+        self._h = handle
+        self.n = n
+        self.ctx = ctx
+
+    def export(self):
+        n = self.n
+        dev = torch.device("cuda", self.ctx.device)
+        out = {
+            "succ": torch.empty(2 * n, dtype=torch.int32, device=dev),
+            "rank": torch.empty(2 * n, dtype=torch.int32, device=dev),
+            "depth": torch.empty(n, dtype=torch.int32, device=dev),
+            "pre": torch.empty(n, dtype=torch.int32, device=dev),
+            "size": torch.empty(n, dtype=torch.int32, device=dev),
+            "inlabel": torch.empty(n, dtype=torch.int32, device=dev),
+            "asc": torch.empty(n, dtype=torch.int32, device=dev),
+        }
+        _check(_lib.et_tree_export(self._h, *[_ptr(out[k]) for k in
+                                              ("succ", "rank", "depth", "pre", "size", "inlabel", "asc")],
+                                   _stream()), "et_tree_export")
+        return out
+
+    def lca(self, qx, qy, out=None):
+        qx = _dev(qx, torch.int32, "qx")
+        qy = _dev(qy, torch.int32, "qy")
+        if qx.numel() != qy.numel():
+            raise ValueError("qx and qy differ in length")
+        if out is None:
+            out = torch.empty_like(qx)
+        _check(_lib.et_lca(self._h, _ptr(qx), _ptr(qy), qx.numel(), _ptr(out), _stream()), "et_lca")
+        return out
+
+    def free(self):
+        if self._h:
+            _lib.et_tree_free(self._h, _stream())
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def et_tree_build(parent, ctx=None):
+    ctx = ctx or default_context()
+    parent = _dev(parent, torch.int32, "parent")
+    h = _P()
+    _check(_lib.et_tree_build(ctx.handle, _ptr(parent), parent.numel(), _stream(), ctypes.byref(h)),
+           "et_tree_build")
+    return Tree(h, parent.numel(), ctx)
+
+
+def et_lca(tree, qx, qy, out=None):
+    return tree.lca(qx, qy, out)
+
+
+# ------------------------------------------------------------------ bridges
+
+def et_bridges(row_ptr, col, mask=None, ctx=None, count=True):
+    """Per-slot bridge bitmask (int32 words, bit k of word k//32 = slot k)
+    and, with ``count``, the number of bridges (waits for the stream)."""
+    ctx = ctx or default_context()
+    row_ptr = _dev(row_ptr, torch.int32, "row_ptr")
+    col = _dev(col, torch.int32, "col")
+    n = row_ptr.numel() - 1
+    nnz = col.numel()
+    if mask is None:
+        mask = torch.empty(max((nnz + 31) // 32, 1), dtype=torch.int32, device=col.device)
+    c = _i64(0)
+    _check(_lib.et_bridges(ctx.handle, _ptr(row_ptr), _ptr(col), n, nnz, _ptr(mask),
+                           ctypes.byref(c) if count else None, _stream()), "et_bridges")
+    return mask, (int(c.value) if count else None)

@@ -1,0 +1,93 @@
+"""GPU parity: et_bridges per-slot bitmask against the Tarjan DFS oracle
+(bit-exact; the bridge set is unique whatever spanning forest the GPU
+hooking picks)."""
+import numpy as np
+import pytest
+
+import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    import paper_2103_15217_amd as et
+    assert torch.cuda.is_available()
+    return et
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
+
+
+def compare(lib, oracle_mod, row_ptr, col):
+    ctx = lib.default_context()
+    mask, cnt = lib.et_bridges(_dev(row_ptr), _dev(col))
+    ctx.check()
+    ref_mask, ref_cnt = oracle_mod.bridges(row_ptr, col)
+    got = mask.cpu().numpy().view(np.uint32)[: len(ref_mask)]
+    assert np.array_equal(got, ref_mask), "bridge mask"
+    assert cnt == ref_cnt
+    return cnt
+
+
+def test_tiny_multigraphs(lib, oracle_mod):
+    for seed in range(300):
+        rng = np.random.default_rng(1000 + seed)
+        n = int(rng.integers(1, 14))
+        m = int(rng.integers(0, 20))
+        rp, col = gen.random_multigraph(n, m, seed=seed, loops=True, multi=True)
+        compare(lib, oracle_mod, rp, col)
+
+
+@pytest.mark.parametrize("kind", ["tree", "path", "cycle", "complete", "doubled_tree", "empty", "isolated"])
+def test_special_graphs(lib, oracle_mod, kind):
+    if kind == "tree":
+        rp, col = gen.tree_graph(gen.random_tree(100003, None, seed=1))
+    elif kind == "path":
+        rp, col = gen.tree_graph(gen.path_tree(70001, seed=2))
+    elif kind == "cycle":
+        rp, col = gen.cycle_graph(50000)
+    elif kind == "complete":
+        rp, col = gen.complete_graph(300)
+    elif kind == "doubled_tree":
+        p = gen.random_tree(20000, None, seed=3)
+        c = np.nonzero(p >= 0)[0]
+        rp, col = gen.csr_from_pairs(20000, np.concatenate([c, c]), np.concatenate([p[c], p[c]]))
+    elif kind == "empty":
+        rp, col = gen.csr_from_pairs(1000, np.array([], np.int64), np.array([], np.int64))
+    else:
+        rp, col = gen.csr_from_pairs(1000, np.array([3, 7, 7]), np.array([4, 8, 9]))
+    compare(lib, oracle_mod, rp, col)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_random_sparse(lib, oracle_mod, seed):
+    n = 200000
+    rp, col = gen.random_multigraph(n, int(1.2 * n), seed=seed, loops=True, multi=True)
+    compare(lib, oracle_mod, rp, col)
+
+
+def test_planted_medium(lib, oracle_mod):
+    rp, col, info = gen.planted_bridge_graph(n=1 << 18, m=1 << 21, chains=256, max_chain=64, seed=4)
+    cnt = compare(lib, oracle_mod, rp, col)
+    assert cnt >= len(info["chain_edges"])
+
+
+def test_planted_full_size(lib, oracle_mod):
+    # 2^22 vertices, ~2^25 edges, 4096 planted chains of length 1..512
+    rp, col, info = gen.planted_bridge_graph(seed=0)
+    cnt = compare(lib, oracle_mod, rp, col)
+    assert cnt >= len(info["chain_edges"])
+
+
+def test_asymmetric_csr_flagged(lib):
+    rp = np.array([0, 1, 1], dtype=np.int32)   # 0 -> 1 without 1 -> 0
+    col = np.array([1], dtype=np.int32)
+    ctx = lib.Context()
+    lib.et_bridges(_dev(rp), _dev(col), ctx=ctx)
+    with pytest.raises(lib.EtError):
+        ctx.check()
+    ctx.close()
