@@ -1,0 +1,265 @@
+"""Benchmark of the Euler-tour hot path on one MI355X.
+
+One step = the whole path over one batch of synthetic input:
+  for each grasp g in {n, 1000, 1}: et_tree_build of a 2^24-node grasp tree
+  (grouping, successor, list ranking, depth / preorder / size, Inlabel
+  tables) and et_lca over 2^24 uniform query pairs; then et_bridges on a
+  2^22-vertex, ~2^25-edge sparse graph with 4096 planted bridge chains.
+Inputs are generated on the host, copied to HBM before timing, and stay
+resident. W untimed warmup steps, then K timed steps between two device
+synchronisations. Prints one JSON line.
+
+value = (sum over the three trees of (nodes + queries) + graph edges) per
+second of step time. Per-component rates, per-kernel times (HIP events on
+the library's stream, recorded during the timed steps), the roofline of the
+dominant kernel and the CPU oracle on a bounded sample are reported beside it.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LCA queries/s + tour nodes/s at 2^24; bridges edges/s; batched vs plain p99"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per unit for the kernels that can dominate a step.
+# (bytes per unit, what a unit is, how many units one launch processes)
+ALG_BYTES = {
+    # list ranking: read the successor (4 B) and write the rank (4 B) of every half-edge
+    "k_walk1<true>": (8, "half-edge", lambda w: 2 * w["n"]),
+    "k_walk1<false>": (8, "half-edge", lambda w: 2 * (w["graph_n"] - 1)),
+    # LCA: 12 B streamed (x, y, out) + 4 gathers of 16-B records per query
+    "k_lca": (76, "query", lambda w: w["q"]),
+    # CC hooking: read each CSR slot once (4 B) plus the row pointer per vertex
+    "k_hook": (4, "CSR slot", lambda w: w["graph_nnz"]),
+    # non-forest min/max: column (4 B) + gathered preorder (4 B) per slot
+    "k_minmax": (8, "CSR slot", lambda w: w["graph_nnz"]),
+    # radix passes: key + value read and written
+    "k_downsweep<false>": (16, "key", lambda w: w["n"]),
+    "k_downsweep<true>": (12, "key", lambda w: w["n"]),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--log2n", type=int, default=24, help="tree size (2^k nodes and queries)")
+    ap.add_argument("--graph-log2n", type=int, default=22)
+    ap.add_argument("--graph-log2m", type=int, default=25)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-times", action="store_true",
+                    help="do not bracket kernels with events during the timed steps")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              "(this path runs on a single MI355X; see DESIGN.md for how it would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import gen
+    import paper_2103_15217_amd as et
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    n = 1 << args.log2n
+    q = n
+    grasps = [None, 1000, 1]
+    t0 = time.time()
+    trees, queries = [], []
+    for i, g in enumerate(grasps):
+        trees.append(gen.random_tree(n, g, seed=args.seed + i))
+    qx, qy = gen.random_queries(n, q, seed=args.seed)
+    log(f"trees generated in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    gn, gm = 1 << args.graph_log2n, 1 << args.graph_log2m
+    chains = 4096 if args.graph_log2n >= 16 else 16
+    rp, col, ginfo = gen.planted_bridge_graph(n=gn, m=gm, chains=chains,
+                                              max_chain=min(512, max(2, gn >> 13)), seed=args.seed)
+    log(f"graph generated in {time.time() - t0:.1f}s: V={gn} m={ginfo['m']} nnz={len(col)}")
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(dev)
+
+    d_parent = [d(p) for p in trees]
+    d_qx, d_qy = d(qx), d(qy)
+    d_rp, d_col = d(rp), d(col)
+    d_out = torch.empty(q, dtype=torch.int32, device=dev)
+    d_mask = torch.empty(max((len(col) + 31) // 32, 1), dtype=torch.int32, device=dev)
+    ctx = et.default_context()
+    work = {"n": n, "q": q, "graph_n": gn, "graph_nnz": len(col), "graph_m": ginfo["m"]}
+
+    stream = torch.cuda.current_stream()
+    marks = {}
+
+    def ev(name):
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        marks.setdefault(name, []).append(e)
+
+    def step(record):
+        for i in range(len(grasps)):
+            if record:
+                ev(f"build{i}.start")
+            t = et.et_tree_build(d_parent[i], ctx=ctx)
+            if record:
+                ev(f"build{i}.end")
+            t.lca(d_qx, d_qy, out=d_out)
+            if record:
+                ev(f"lca{i}.end")
+            t.free()
+        if record:
+            ev("bridges.start")
+        et.et_bridges(d_rp, d_col, mask=d_mask, ctx=ctx, count=False)
+        if record:
+            ev("bridges.end")
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    ctx.check()
+    ctx.profile_read()
+    if not args.no_kernel_times:
+        ctx.profile(True)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(args.steps):
+        step(True)
+    end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(end)
+    kernels = ctx.profile_read() if not args.no_kernel_times else {}
+    ctx.profile(False)
+    ctx.check()
+    ms_per_step = total_ms / args.steps
+
+    def span(a, b):
+        return sum(x.elapsed_time(y) for x, y in zip(marks[a], marks[b])) / args.steps
+
+    build_ms = [span(f"build{i}.start", f"build{i}.end") for i in range(len(grasps))]
+    lca_ms = [span(f"build{i}.end", f"lca{i}.end") for i in range(len(grasps))]
+    bridges_ms = span("bridges.start", "bridges.end")
+    elements = len(grasps) * (n + q) + ginfo["m"]
+    gname = ["n", "1000", "1"]
+    components = {
+        "lca_preprocess_nodes_per_s": {gname[i]: n / (build_ms[i] * 1e-3) for i in range(3)},
+        "lca_queries_per_s": {gname[i]: q / (lca_ms[i] * 1e-3) for i in range(3)},
+        "lca_total_queries_per_s": {gname[i]: q / ((build_ms[i] + lca_ms[i]) * 1e-3) for i in range(3)},
+        "bridges_edges_per_s": ginfo["m"] / (bridges_ms * 1e-3),
+        "ms": {"build": dict(zip(gname, build_ms)), "lca": dict(zip(gname, lca_ms)), "bridges": bridges_ms},
+    }
+    if "phase:tour" in kernels:
+        tour_ms = kernels["phase:tour"][1] / kernels["phase:tour"][0]
+        components["tour_nodes_per_s"] = n / (tour_ms * 1e-3)
+
+    # dominant kernel and its roofline
+    per_step = {k: (v[0] / args.steps, v[1] / args.steps, v[1] / v[0]) for k, v in kernels.items()
+                if not k.startswith("phase:")}
+    roofline = None
+    if per_step:
+        dom = max(per_step, key=lambda k: per_step[k][1])
+        launches, ms_step, avg_ms = per_step[dom]
+        if dom in ALG_BYTES:
+            bpu, unit, units = ALG_BYTES[dom]
+            units_per_launch = units(work)
+            achieved = bpu * units_per_launch / (avg_ms * 1e-3) / 1e9
+            roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "alg_bytes_per_unit": bpu, "unit_name": unit, "units_per_launch": units_per_launch,
+                        "avg_launch_ms": avg_ms, "launches_per_step": launches}
+        else:
+            roofline = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": None, "traffic": None, "avg_launch_ms": avg_ms}
+
+    result = {
+        "metric": METRIC,
+        "value": elements / (ms_per_step * 1e-3),
+        "unit": "elements/s (tree nodes + LCA queries + graph edges)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"3 grasp trees (g=n,1000,1) of 2^{args.log2n} nodes, each built and queried with "
+                         f"2^{args.log2n} uniform LCA pairs; bridges on a {gn}-vertex {ginfo['m']}-edge graph "
+                         f"with {chains} planted chains"),
+            "tree_nodes": n, "queries_per_tree": q, "grasps": ["n", 1000, 1],
+            "graph_vertices": gn, "graph_edges": ginfo["m"], "graph_csr_slots": len(col),
+            "seed": args.seed,
+        },
+        "components": components,
+        "kernels_ms_per_step": {k: round(v[1], 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1][1])},
+        "roofline": roofline,
+    }
+
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on the sample")
+        result["cpu_baseline"], result["parity"] = cpu_baseline(trees[0], qx, qy, rp, col, ginfo, et, d, ctx,
+                                                                d_parent[0], d_qx, d_qy, d_rp, d_col)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(parent, qx, qy, rp, col, ginfo, et, d, ctx, d_parent, d_qx, d_qy, d_rp, d_col):
+    """The oracle (single-threaded C) on one sample: the grasp-n tree (tour,
+    statistics, Inlabel tables, all 2^24 LCA queries) and the bridges graph.
+    Also checks the GPU's outputs on that sample against it."""
+    import oracle
+    n, q = len(parent), len(qx)
+    t0 = time.perf_counter()
+    t = oracle.euler_tour(parent)
+    oracle.sv_tables(parent, t["depth"], t["pre"], t["size"])
+    lca_ref = oracle.lca_offline(parent, qx, qy)
+    t1 = time.perf_counter()
+    mask_ref, cnt_ref = oracle.bridges(rp, col)
+    t2 = time.perf_counter()
+    secs = t2 - t0
+    elements = n + q + ginfo["m"]
+    tree = et.et_tree_build(d_parent, ctx=ctx)
+    got = tree.lca(d_qx, d_qy).cpu().numpy()
+    tree.free()
+    mask, cnt = et.et_bridges(d_rp, d_col, ctx=ctx)
+    ctx.check()
+    parity = {
+        "lca_grasp_n_2e24": bool(np.array_equal(got, lca_ref)),
+        "bridges_mask": bool(np.array_equal(mask.cpu().numpy().view(np.uint32)[: len(mask_ref)], mask_ref)),
+        "bridges_count": int(cnt), "bridges_count_oracle": int(cnt_ref),
+    }
+    base = {"value": elements / secs, "unit": "elements/s (tree nodes + LCA queries + graph edges)",
+            "cores": 1, "kind": "oracle",
+            "sample": (f"grasp-n tree of {n} nodes (Euler tour, depth/preorder/size, Inlabel tables) + {q} "
+                       f"offline LCA queries ({t1 - t0:.1f}s), and Tarjan bridges on the {len(rp) - 1}-vertex "
+                       f"{ginfo['m']}-edge graph ({t2 - t1:.1f}s)"),
+            "seconds": secs}
+    return base, parity
+
+
+if __name__ == "__main__":
+    main()

@@ -1,6 +1,7 @@
 // C-ABI entry points of the Euler-tour library (declared in include/et.h),
 // the per-context scratch pool and the device status word.
 #include <cstdio>
+#include <cstring>
 #include <map>
 #include <new>
 #include <string>
@@ -167,7 +168,7 @@ int et_ctx_profile_read(et_ctx* ctx, hipStream_t s, char* h_buf, int32_t buflen)
   }
   out += "}";
   if ((int64_t)out.size() + 1 > buflen) return ET_EINVAL;
-  memcpy(h_buf, out.c_str(), out.size() + 1);
+  std::memcpy(h_buf, out.c_str(), out.size() + 1);
   for (auto& r : c->prof) {
     c->spare_events.push_back(r.a);
     c->spare_events.push_back(r.b);

@@ -518,50 +518,95 @@ int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, i
   const int grows = ceil_div(n, kRowsPerBlock);
   const int gl = ceil_div(Lcap, kB);
   // 1. spanning forest
-  hipLaunchKernelGGL(k_check_csr, dim3(gn), dim3(kB), 0, s, row_ptr, n, nnz, c->d_status);
+  ET_PROF(c, s, "phase:bridges");
+  {
+    ET_PROF(c, s, "k_check_csr");
+    hipLaunchKernelGGL(k_check_csr, dim3(gn), dim3(kB), 0, s, row_ptr, n, nnz, c->d_status);
+  }
   hipLaunchKernelGGL(k_iota, dim3(gn), dim3(kB), 0, s, cc, n);
   hipLaunchKernelGGL(k_fill_i32, dim3(std::min(ceil_div(words, kB), 4096)), dim3(kB), 0, s,
                      reinterpret_cast<int32_t*>(tbits), (int64_t)words, 0);
-  hipLaunchKernelGGL(k_hook, dim3(grows), dim3(kB), 0, s, row_ptr, col, n, nnz, cc, tbits, c->d_status);
+  {
+    ET_PROF(c, s, "k_hook");
+    hipLaunchKernelGGL(k_hook, dim3(grows), dim3(kB), 0, s, row_ptr, col, n, nnz, cc, tbits, c->d_status);
+  }
   // 2. forest CSR, twins, successors, component chaining
-  hipLaunchKernelGGL(k_tree_deg, dim3(gn), dim3(kB), 0, s, row_ptr, tbits, n, nnz, tdeg);
+  {
+    ET_PROF(c, s, "k_tree_deg");
+    hipLaunchKernelGGL(k_tree_deg, dim3(gn), dim3(kB), 0, s, row_ptr, tbits, n, nnz, tdeg);
+  }
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, s, reinterpret_cast<int32_t*>(tdeg + n), (int64_t)1, 0);
   int rc = scan_u32(c, tdeg, tptr, (int64_t)n + 1, ScanOp::Add, true, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_tree_fill, dim3(gn), dim3(kB), 0, s, row_ptr, col, tbits, tptr, n, nnz, Lcap, tslot, tnbr,
-                     tsrc);
-  hipLaunchKernelGGL(k_root_flags, dim3(gn), dim3(kB), 0, s, cc, tdeg, n, rflag);
+  {
+    ET_PROF(c, s, "k_tree_fill");
+    hipLaunchKernelGGL(k_tree_fill, dim3(gn), dim3(kB), 0, s, row_ptr, col, tbits, tptr, n, nnz, Lcap, tslot, tnbr,
+                       tsrc);
+  }
+  {
+    ET_PROF(c, s, "k_root_flags");
+    hipLaunchKernelGGL(k_root_flags, dim3(gn), dim3(kB), 0, s, cc, tdeg, n, rflag);
+  }
   rc = scan_u32(c, rflag, rpos, n, ScanOp::Add, true, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_root_list, dim3(gn), dim3(kB), 0, s, rflag, rpos, n, roots);
+  {
+    ET_PROF(c, s, "k_root_list");
+    hipLaunchKernelGGL(k_root_list, dim3(gn), dim3(kB), 0, s, rflag, rpos, n, roots);
+  }
   hipLaunchKernelGGL(k_set_len, dim3(1), dim3(1), 0, s, tptr, n, scal);
-  hipLaunchKernelGGL(k_succ_csr, dim3(gl), dim3(kB), 0, s, tnbr, tsrc, tptr, n, Lcap, scal, ttwin, succ,
-                     c->d_status);
-  hipLaunchKernelGGL(k_link_roots, dim3(gn), dim3(kB), 0, s, roots, rpos, rflag, tptr, ttwin, n, succ, scal);
+  {
+    ET_PROF(c, s, "k_succ_csr");
+    hipLaunchKernelGGL(k_succ_csr, dim3(gl), dim3(kB), 0, s, tnbr, tsrc, tptr, n, Lcap, scal, ttwin, succ,
+                       c->d_status);
+  }
+  {
+    ET_PROF(c, s, "k_link_roots");
+    hipLaunchKernelGGL(k_link_roots, dim3(gn), dim3(kB), 0, s, roots, rpos, rflag, tptr, ttwin, n, succ, scal);
+  }
   // 3. one list ranking, directions, preorder
   LRResult lr;
   rc = list_rank_core(c, sc, succ, Lcap, scal + 1, 1, false, scal + 2, &lr, s, true);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_rank_of, dim3(gl), dim3(kB), 0, s, lr.packed, lr.off, lr.nsub, Lcap, scal, rank,
-                     c->d_status);
+  {
+    ET_PROF(c, s, "k_rank_of");
+    hipLaunchKernelGGL(k_rank_of, dim3(gl), dim3(kB), 0, s, lr.packed, lr.off, lr.nsub, Lcap, scal, rank,
+                       c->d_status);
+  }
   hipLaunchKernelGGL(k_fill_i32, dim3(std::min(gn, 4096)), dim3(kB), 0, s, vR, (int64_t)n, -1);
   hipLaunchKernelGGL(k_fill_i32, dim3(std::min(gn, 4096)), dim3(kB), 0, s, vpslot, (int64_t)n, -1);
-  hipLaunchKernelGGL(k_direction, dim3(gl), dim3(kB), 0, s, rank, ttwin, tsrc, tnbr, tslot, tptr, cc, n, Lcap, scal,
-                     dw, vR, vsize, vpslot, vuslot, c->d_status);
+  {
+    ET_PROF(c, s, "k_direction");
+    hipLaunchKernelGGL(k_direction, dim3(gl), dim3(kB), 0, s, rank, ttwin, tsrc, tnbr, tslot, tptr, cc, n, Lcap, scal,
+                       dw, vR, vsize, vpslot, vuslot, c->d_status);
+  }
   rc = scan_u32(c, dw, dw, Lcap, ScanOp::Add, false, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_preorder, dim3(gn), dim3(kB), 0, s, vR, vpslot, dw, n, Lcap, pre);
+  {
+    ET_PROF(c, s, "k_preorder");
+    hipLaunchKernelGGL(k_preorder, dim3(gn), dim3(kB), 0, s, vR, vpslot, dw, n, Lcap, pre);
+  }
   // 4. non-forest extremes by preorder
-  hipLaunchKernelGGL(k_minmax, dim3(grows), dim3(kB), 0, s, row_ptr, col, tbits, pre, n, nnz, amin, amax);
+  {
+    ET_PROF(c, s, "k_minmax");
+    hipLaunchKernelGGL(k_minmax, dim3(grows), dim3(kB), 0, s, row_ptr, col, tbits, pre, n, nnz, amin, amax);
+  }
   // 5. range extremes
-  hipLaunchKernelGGL(k_rmq_blocks, dim3(gn), dim3(kB), 0, s, amin, amax, n, pmin, smin, pmax, smax, stmin, stmax);
-  for (int k = 1; k < levels; ++k)
+  {
+    ET_PROF(c, s, "k_rmq_blocks");
+    hipLaunchKernelGGL(k_rmq_blocks, dim3(gn), dim3(kB), 0, s, amin, amax, n, pmin, smin, pmax, smax, stmin, stmax);
+  }
+  for (int k = 1; k < levels; ++k) {
+    ET_PROF(c, s, "k_sparse_level");
     hipLaunchKernelGGL(k_sparse_level, dim3(ceil_div(nb, kB)), dim3(kB), 0, s, stmin + (size_t)(k - 1) * nb,
                        stmax + (size_t)(k - 1) * nb, nb, 1 << (k - 1), stmin + (size_t)k * nb,
                        stmax + (size_t)k * nb);
+  }
   // 6. test
   Rmq q{amin, amax, pmin, smin, pmax, smax, stmin, stmax, nb};
-  hipLaunchKernelGGL(k_bridge_test, dim3(gn), dim3(kB), 0, s, pre, vsize, vpslot, vuslot, n, q, mask, c->d_bcount);
+  {
+    ET_PROF(c, s, "k_bridge_test");
+    hipLaunchKernelGGL(k_bridge_test, dim3(gn), dim3(kB), 0, s, pre, vsize, vpslot, vuslot, n, q, mask, c->d_bcount);
+  }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }
 

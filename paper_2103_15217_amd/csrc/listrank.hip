@@ -388,14 +388,17 @@ int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const 
   hipLaunchKernelGGL(k_fill_int4, dim3(ceil_div(cont_max, 256)), dim3(256), 0, s, rec1, S1 + H, T1,
                      make_int4(-3, 0, 0, 0));
   const int32_t per_wave1 = 256;
-  if (tree_weights)
+  if (tree_weights) {
+    ET_PROF(c, s, "k_walk1<true>");
     hipLaunchKernelGGL(k_walk1<true>, dim3(walk_grid(S1 + H, per_wave1)), dim3(kWalkThreads), 0, s, succ, L,
                        heads, H, ks1, kSalt, S1, per_wave1, packed, rec1, ctr, S1 + H, cont_max,
                        empty_head_ok, c->d_status);
-  else
+  } else {
+    ET_PROF(c, s, "k_walk1<false>");
     hipLaunchKernelGGL(k_walk1<false>, dim3(walk_grid(S1 + H, per_wave1)), dim3(kWalkThreads), 0, s, succ,
                        L, heads, H, ks1, kSalt, S1, per_wave1, packed, rec1, ctr, S1 + H, cont_max,
                        empty_head_ok, c->d_status);
+  }
 
   // upper levels: (records, element outputs) per level
   struct Lvl {
@@ -417,8 +420,11 @@ int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const 
     int4* rec = sc.get<int4>((size_t)Tn);
     if (sc.failed) return ET_ENOMEM;
     const int32_t per_wave = 128;
-    hipLaunchKernelGGL(k_walkN, dim3(walk_grid(Tn, per_wave)), dim3(kWalkThreads), 0, s, cur.rec, cur.T,
-                       cur.hb, H, ks, kSalt ^ (uint32_t)lv.size(), S, per_wave, el, rec, c->d_status);
+    {
+      ET_PROF(c, s, "k_walkN");
+      hipLaunchKernelGGL(k_walkN, dim3(walk_grid(Tn, per_wave)), dim3(kWalkThreads), 0, s, cur.rec, cur.T,
+                         cur.hb, H, ks, kSalt ^ (uint32_t)lv.size(), S, per_wave, el, rec, c->d_status);
+    }
     cur.el = el;
     lv.push_back({rec, Tn, S, nullptr, nullptr});
   }
@@ -428,16 +434,25 @@ int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const 
   if (sc.failed) return ET_ENOMEM;
   Lvl& top = lv.back();
   if (top.T <= kLdsMax) {
-    hipLaunchKernelGGL(k_final_lds, dim3(1), dim3(kFinalThreads), 0, s, top.rec, top.T, top.hb, H, top.off,
-                       ctr + 1, c->d_status);
+    {
+      ET_PROF(c, s, "k_final_lds");
+      hipLaunchKernelGGL(k_final_lds, dim3(1), dim3(kFinalThreads), 0, s, top.rec, top.T, top.hb, H, top.off,
+                         ctr + 1, c->d_status);
+    }
   } else {
-    hipLaunchKernelGGL(k_final_walk, dim3(ceil_div(H, 256)), dim3(256), 0, s, top.rec, top.T, top.hb, H,
-                       top.off, ctr + 1, c->d_status);
+    {
+      ET_PROF(c, s, "k_final_walk");
+      hipLaunchKernelGGL(k_final_walk, dim3(ceil_div(H, 256)), dim3(256), 0, s, top.rec, top.T, top.hb, H,
+                         top.off, ctr + 1, c->d_status);
+    }
   }
   hipLaunchKernelGGL(k_check_reached, dim3(1), dim3(1), 0, s, ctr + 1, expected_reach, c->d_status);
   for (int k = (int)lv.size() - 2; k >= 0; --k) {
-    hipLaunchKernelGGL(k_push_down, dim3(ceil_div(lv[k].T, 256)), dim3(256), 0, s, lv[k].rec, lv[k].el,
-                       lv[k].T, lv[k + 1].off, lv[k + 1].T, lv[k].off, c->d_status);
+    {
+      ET_PROF(c, s, "k_push_down");
+      hipLaunchKernelGGL(k_push_down, dim3(ceil_div(lv[k].T, 256)), dim3(256), 0, s, lv[k].rec, lv[k].el,
+                         lv[k].T, lv[k + 1].off, lv[k + 1].T, lv[k].off, c->d_status);
+    }
   }
   out->packed = packed;
   out->off = lv[0].off;
@@ -452,13 +467,19 @@ int list_rank_generic(Ctx* c, const int32_t* succ, int32_t len, const int32_t* h
   int32_t* expected = sc.get<int32_t>(1);
   if (sc.failed) return ET_ENOMEM;
   hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, expected, 0);
-  hipLaunchKernelGGL(k_count_used, dim3(std::min(ceil_div(len, 256), 2048)), dim3(256), 0, s, succ, len,
-                     expected);
+  {
+    ET_PROF(c, s, "k_count_used");
+    hipLaunchKernelGGL(k_count_used, dim3(std::min(ceil_div(len, 256), 2048)), dim3(256), 0, s, succ, len,
+                       expected);
+  }
   LRResult r;
   int rc = list_rank_core(c, sc, succ, len, heads, nheads, false, expected, &r, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_rank_fix, dim3(ceil_div(len, 256)), dim3(256), 0, s, succ, r.packed, len, r.off,
-                     r.nsub, rank, c->d_status);
+  {
+    ET_PROF(c, s, "k_rank_fix");
+    hipLaunchKernelGGL(k_rank_fix, dim3(ceil_div(len, 256)), dim3(256), 0, s, succ, r.packed, len, r.off,
+                       r.nsub, rank, c->d_status);
+  }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }
 

@@ -167,20 +167,26 @@ int group_by_parent_impl(Ctx* c, const int32_t* parent, int32_t n, uint32_t* key
     const bool to_out = ((passes - 1 - p) % 2) == 0;
     uint32_t* kout = to_out ? keys_out : tk;
     int32_t* vout = to_out ? vals_out : tv;
-    if (p == 0)
+    if (p == 0) {
+      ET_PROF(c, s, "k_upsweep<true>");
       hipLaunchKernelGGL(k_upsweep<true>, dim3(ntiles), dim3(kThreads), 0, s, kin, n, shift, nbits, ntiles, hist,
                          succ, scalars, c->d_status);
-    else
+    } else {
+      ET_PROF(c, s, "k_upsweep<false>");
       hipLaunchKernelGGL(k_upsweep<false>, dim3(ntiles), dim3(kThreads), 0, s, kin, n, shift, nbits, ntiles,
                          hist, succ, scalars, c->d_status);
+    }
     int rc = scan_u32(c, hist, hist, (int64_t)(1 << nbits) * ntiles, ScanOp::Add, true, s);
     if (rc) return rc;
-    if (p == 0)
+    if (p == 0) {
+      ET_PROF(c, s, "k_downsweep<true>");
       hipLaunchKernelGGL(k_downsweep<true>, dim3(ntiles), dim3(kThreads), 0, s, kin, vin, n, shift, nbits, ntiles,
                          hist, kout, vout);
-    else
+    } else {
+      ET_PROF(c, s, "k_downsweep<false>");
       hipLaunchKernelGGL(k_downsweep<false>, dim3(ntiles), dim3(kThreads), 0, s, kin, vin, n, shift, nbits,
                          ntiles, hist, kout, vout);
+    }
     kin = kout;
     vin = vout;
   }

@@ -170,14 +170,23 @@ int scan_impl(Ctx* c, const uint32_t* in, uint32_t* out, int64_t n, bool exclusi
   Scratch sc(c);
   uint32_t* partial = sc.get<uint32_t>(nranges);
   if (sc.failed) return ET_ENOMEM;
-  hipLaunchKernelGGL(k_range_reduce<OP>, dim3(nranges), dim3(kThreads), 0, s, in, n, per, partial);
-  hipLaunchKernelGGL(k_scan_partials<OP>, dim3(1), dim3(1024), 0, s, partial, nranges);
-  if (exclusive)
+  {
+    ET_PROF(c, s, OP == ScanOp::Add ? "k_range_reduce<add>" : "k_range_reduce<xor>");
+    hipLaunchKernelGGL(k_range_reduce<OP>, dim3(nranges), dim3(kThreads), 0, s, in, n, per, partial);
+  }
+  {
+    ET_PROF(c, s, OP == ScanOp::Add ? "k_scan_partials<add>" : "k_scan_partials<xor>");
+    hipLaunchKernelGGL(k_scan_partials<OP>, dim3(1), dim3(1024), 0, s, partial, nranges);
+  }
+  if (exclusive) {
+    ET_PROF(c, s, OP == ScanOp::Add ? "k_range_scan<add,excl>" : "k_range_scan<xor,excl>");
     hipLaunchKernelGGL((k_range_scan<OP, true>), dim3(nranges), dim3(kThreads), 0, s, in, out, n, per,
                        partial);
-  else
+  } else {
+    ET_PROF(c, s, OP == ScanOp::Add ? "k_range_scan<add,incl>" : "k_range_scan<xor,incl>");
     hipLaunchKernelGGL((k_range_scan<OP, false>), dim3(nranges), dim3(kThreads), 0, s, in, out, n, per,
                        partial);
+  }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }
 

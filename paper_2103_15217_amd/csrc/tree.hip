@@ -248,21 +248,38 @@ int tree_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
   if (scr.failed) return ET_ENOMEM;
   uint32_t* keys = kv;
   int32_t* vals = reinterpret_cast<int32_t*>(kv + n);
-  int rc = group_by_parent_impl(c, parent, n, keys, vals, t->d_succ, sc, s);
-  if (rc) return rc;
   const int gn = ceil_div(n, kB);
-  hipLaunchKernelGGL(k_succ, dim3(gn), dim3(kB), 0, s, keys, vals, n, sc, t->d_succ, c->d_status);
   LRResult lr;
-  rc = list_rank_core(c, scr, t->d_succ, L2, sc + SC_HEAD, 1, true, sc + SC_EXPECT, &lr, s);
-  if (rc) return rc;
-  hipLaunchKernelGGL(k_node, dim3(gn), dim3(kB), 0, s, lr.packed, lr.off, lr.nsub, n, sc, t->d_rank, t->d_pre,
-                     t->d_size, t->d_rec, c->d_status);
+  int rc;
+  {
+    ET_PROF(c, s, "phase:tour");
+    rc = group_by_parent_impl(c, parent, n, keys, vals, t->d_succ, sc, s);
+    if (rc) return rc;
+    {
+      ET_PROF(c, s, "k_succ");
+      hipLaunchKernelGGL(k_succ, dim3(gn), dim3(kB), 0, s, keys, vals, n, sc, t->d_succ, c->d_status);
+    }
+    rc = list_rank_core(c, scr, t->d_succ, L2, sc + SC_HEAD, 1, true, sc + SC_EXPECT, &lr, s);
+    if (rc) return rc;
+    {
+      ET_PROF(c, s, "k_node");
+      hipLaunchKernelGGL(k_node, dim3(gn), dim3(kB), 0, s, lr.packed, lr.off, lr.nsub, n, sc, t->d_rank, t->d_pre,
+                         t->d_size, t->d_rec, c->d_status);
+    }
+  }
+  ET_PROF(c, s, "phase:inlabel");
   uint32_t* xw = kv;
-  hipLaunchKernelGGL(k_head, dim3(gn), dim3(kB), 0, s, parent, t->d_rec, t->d_rank, n, sc, t->d_head, xw, L,
-                     c->d_status);
+  {
+    ET_PROF(c, s, "k_head");
+    hipLaunchKernelGGL(k_head, dim3(gn), dim3(kB), 0, s, parent, t->d_rec, t->d_rank, n, sc, t->d_head, xw, L,
+                       c->d_status);
+  }
   rc = scan_u32(c, xw, xw, L, ScanOp::Xor, false, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_asc, dim3(gn), dim3(kB), 0, s, t->d_rec, t->d_rank, xw, n, L, sc, c->d_status);
+  {
+    ET_PROF(c, s, "k_asc");
+    hipLaunchKernelGGL(k_asc, dim3(gn), dim3(kB), 0, s, t->d_rec, t->d_rank, xw, n, L, sc, c->d_status);
+  }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }
 
@@ -283,8 +300,11 @@ int tree_lca(Ctx* c, const et_tree* t, const int32_t* qx, const int32_t* qy, int
              hipStream_t s) {
   if (q == 0) return ET_OK;
   const int64_t blocks = (q + kB - 1) / kB;
-  hipLaunchKernelGGL(k_lca, dim3((unsigned)blocks), dim3(kB), 0, s, t->d_rec, t->d_head, t->n, qx, qy, q, out,
-                     c->d_status);
+  {
+    ET_PROF(c, s, "k_lca");
+    hipLaunchKernelGGL(k_lca, dim3((unsigned)blocks), dim3(kB), 0, s, t->d_rec, t->d_head, t->n, qx, qy, q, out,
+                       c->d_status);
+  }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }
 

@@ -29,6 +29,8 @@ _SIG = {
     "et_ctx_destroy": ([_P], None),
     "et_ctx_status": ([_P, _P], ctypes.c_int),
     "et_ctx_status_bits": ([_P, _P, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
+    "et_ctx_profile": ([_P, ctypes.c_int], ctypes.c_int),
+    "et_ctx_profile_read": ([_P, _P, ctypes.c_char_p, _i32], ctypes.c_int),
     "et_list_rank": ([_P, _P, _i32, _P, _i32, _P, _P], ctypes.c_int),
     "et_tree_build": ([_P, _P, _i32, _P, ctypes.POINTER(_P)], ctypes.c_int),
     "et_tree_size": ([_P], _i32),
@@ -109,6 +111,24 @@ class Context:
         if bits:
             names = [v for k, v in STATUS_BITS.items() if bits & k]
             raise EtError(ET_EINPUT, "device status: " + ", ".join(names))
+
+    def profile(self, enable=True):
+        """Bracket every later kernel launch on this context with HIP events."""
+        _check(_lib.et_ctx_profile(self._h, 1 if enable else 0), "et_ctx_profile")
+
+    def profile_read(self):
+        """Wait for the stream; return {kernel: (launches, total_ms, max_ms)}
+        over the launches timed since the previous read."""
+        import json
+        size = 1 << 16
+        while True:
+            buf = ctypes.create_string_buffer(size)
+            rc = _lib.et_ctx_profile_read(self._h, _stream(), buf, size)
+            if rc == ET_EINVAL and size < (1 << 24):
+                size *= 4
+                continue
+            _check(rc, "et_ctx_profile_read")
+            return {k: tuple(v) for k, v in json.loads(buf.value.decode()).items()}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -76,10 +76,14 @@ def test_planted_medium(lib, oracle_mod):
     assert cnt >= len(info["chain_edges"])
 
 
-def test_planted_full_size(lib, oracle_mod):
+def test_full_size_planted(lib, oracle_mod):
     # 2^22 vertices, ~2^25 edges, 4096 planted chains of length 1..512
+    import time
+    t0 = time.time()
     rp, col, info = gen.planted_bridge_graph(seed=0)
+    print(f"\n[full-size bridges] graph {time.time() - t0:.1f}s", flush=True)
     cnt = compare(lib, oracle_mod, rp, col)
+    print(f"[full-size bridges] compared in {time.time() - t0:.1f}s, {cnt} bridges", flush=True)
     assert cnt >= len(info["chain_edges"])
 
 
