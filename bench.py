@@ -58,7 +58,23 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-times", action="store_true",
                     help="do not bracket kernels with events during the timed steps")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain elementwise copy of MIB MiB (int32 negate: reads and writes MIB MiB) "
+                         "five times, to calibrate HBM byte counters against a known size")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.arange(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4,
+                      "launches": 5}), flush=True)
 
 
 def log(msg):
@@ -67,6 +83,9 @@ def log(msg):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
               "(this path runs on a single MI355X; see DESIGN.md for how it would shard)",
@@ -181,17 +200,18 @@ def main():
     if per_step:
         dom = max(per_step, key=lambda k: per_step[k][1])
         launches, ms_step, avg_ms = per_step[dom]
+        traffic = measured_traffic(dom)
         if dom in ALG_BYTES:
             bpu, unit, units = ALG_BYTES[dom]
             units_per_launch = units(work)
             achieved = bpu * units_per_launch / (avg_ms * 1e-3) / 1e9
             roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                         "alg_bytes_per_unit": bpu, "unit_name": unit, "units_per_launch": units_per_launch,
                         "avg_launch_ms": avg_ms, "launches_per_step": launches}
         else:
             roofline = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": None, "traffic": None, "avg_launch_ms": avg_ms}
+                        "unit": "GB/s", "frac": None, "traffic": traffic, "avg_launch_ms": avg_ms}
 
     result = {
         "metric": METRIC,
@@ -225,6 +245,22 @@ def main():
         result["cpu_baseline"], result["parity"] = cpu_baseline(trees[0], qx, qy, rp, col, ginfo, et, d, ctx,
                                                                 d_parent[0], d_qx, d_qy, d_rp, d_col)
     print(json.dumps(result), flush=True)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when none was taken or the kernel's source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_2e24.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))["kernels"].get(kernel)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
+        return None
+    return rec["fetch_kib"] * 1024 * rec["fetch_factor"] + rec["write_kib"] * 1024 * rec["write_factor"]
 
 
 def cpu_baseline(parent, qx, qy, rp, col, ginfo, et, d, ctx, d_parent, d_qx, d_qy, d_rp, d_col):
