@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--graph-log2n", type=int, default=22)
     ap.add_argument("--graph-log2m", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 4096-tree batched vs plain comparison")
+    ap.add_argument("--batch-trees", type=int, default=4096)
     ap.add_argument("--no-kernel-times", action="store_true",
                     help="do not bracket kernels with events during the timed steps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -240,11 +242,68 @@ def main():
     }
 
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
+    if not args.no_batch:
+        log("batched forest: generating")
+        result["components"]["batched"] = batched_vs_plain(args, et, ctx, d, dev)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on the sample")
         result["cpu_baseline"], result["parity"] = cpu_baseline(trees[0], qx, qy, rp, col, ginfo, et, d, ctx,
                                                                 d_parent[0], d_qx, d_qy, d_rp, d_col)
     print(json.dumps(result), flush=True)
+
+
+def batched_vs_plain(args, et, ctx, d, dev):
+    """4096 trees of log-uniform size in [2^6, 2^18] (grasp 1, 64 or n) with
+    2^10..2^14 queries each: one batched build + one batched query launch
+    versus building and querying every tree on its own, same stream."""
+    import torch
+    import gen
+    t0 = time.time()
+    b = gen.forest_batch(args.batch_trees, seed=args.seed)
+    log(f"batched forest: {int(b['offsets'][-1])} nodes generated in {time.time() - t0:.1f}s")
+    T = len(b["sizes"])
+    d_parent = d(b["parent"])
+    d_off = torch.from_numpy(b["offsets"].astype(np.int64)).to(dev)
+    d_qt, d_qx, d_qy = d(b["qtree"]), d(b["qx"]), d(b["qy"])
+    d_out = torch.empty_like(d_qx)
+    off = b["offsets"]
+    qs = np.searchsorted(b["qtree"], np.arange(T + 1))
+    parts = [(d_parent[int(off[t]):int(off[t + 1])], d_qx[int(qs[t]):int(qs[t + 1])],
+              d_qy[int(qs[t]):int(qs[t + 1])], d_out[int(qs[t]):int(qs[t + 1])]) for t in range(T)]
+    stream = torch.cuda.current_stream()
+
+    def batched():
+        tr = et.et_tree_build_batch(d_parent, d_off, ctx=ctx)
+        tr.lca_batch(d_qt, d_qx, d_qy, out=d_out)
+        tr.free()
+
+    def plain():
+        for p, x, y, o in parts:
+            tr = et.et_tree_build(p, ctx=ctx)
+            tr.lca(x, y, out=o)
+            tr.free()
+
+    res = {}
+    for name, fn, reps in (("batched", batched, 5), ("plain", plain, 1)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = {"gpu_ms": e0.elapsed_time(e1) / reps, "wall_ms": (time.perf_counter() - w0) * 1e3 / reps}
+    ctx.check()
+    nodes, q = int(off[-1]), len(b["qx"])
+    return {"trees": T, "nodes": nodes, "queries": q,
+            "batched_ms": res["batched"]["gpu_ms"], "plain_ms": res["plain"]["gpu_ms"],
+            "plain_wall_ms": res["plain"]["wall_ms"],
+            "batched_nodes_per_s": nodes / (res["batched"]["gpu_ms"] * 1e-3),
+            "plain_nodes_per_s": nodes / (res["plain"]["gpu_ms"] * 1e-3),
+            "batched_queries_per_s": q / (res["batched"]["gpu_ms"] * 1e-3),
+            "speedup": res["plain"]["gpu_ms"] / res["batched"]["gpu_ms"]}
 
 
 def measured_traffic(kernel):

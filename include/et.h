@@ -118,8 +118,37 @@ int et_list_rank(et_ctx* ctx, const int32_t* d_succ, int32_t len, const int32_t*
 int et_tree_build(et_ctx* ctx, const int32_t* d_parent, int32_t n, hipStream_t s,
                   et_tree** out);
 
-/* Number of nodes of a built tree (host value). */
+/*
+ * Batch of independent rooted trees, built in one pass (Section 3.3, batched
+ * queries; the C4 workload of thousands of trees of uneven size).
+ *   d_parent[n_total]        the trees' parent arrays concatenated; ids are
+ *                            local to each tree (0-based), its root has -1
+ *   d_offsets[n_trees + 1]   device int64: tree t is [offsets[t], offsets[t+1]);
+ *                            offsets[0] = 0, offsets[n_trees] = n_total
+ * All trees hang below one virtual root, so one tour, one list ranking and
+ * one set of Inlabel tables serve the whole batch; the LCA of two nodes of
+ * one tree is unchanged. n_total + 1 < 2^30. A tree without exactly one
+ * root or with a bad id sets ET_EINPUT in ctx's status.
+ * et_tree_export on a batch accepts only depth / pre / size (per-tree
+ * values, n_total entries); et_lca on a batch is ET_EINVAL (use
+ * et_lca_batch).
+ */
+int et_tree_build_batch(et_ctx* ctx, const int32_t* d_parent, const int64_t* d_offsets,
+                        int32_t n_trees, int64_t n_total, hipStream_t s, et_tree** out);
+
+/*
+ * LCA queries on a batch: query i asks for the LCA of the local nodes
+ * d_qx[i], d_qy[i] of tree d_qtree[i]; d_out[i] is a local id, or -1 for a
+ * query with an id out of range (which also sets ET_EINPUT).
+ */
+int et_lca_batch(const et_tree* tree, const int32_t* d_qtree, const int32_t* d_qx,
+                 const int32_t* d_qy, int64_t q, int32_t* d_out, hipStream_t s);
+
+/* Number of nodes of a built tree or batch (host value). */
 int32_t et_tree_size(const et_tree* tree);
+
+/* Number of trees of a batch (0 for a single tree). */
+int32_t et_tree_batch_size(const et_tree* tree);
 
 /*
  * Copy tables of a built tree into caller-owned device arrays; any output

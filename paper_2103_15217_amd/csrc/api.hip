@@ -15,6 +15,9 @@ int tree_export(const et_tree* t, int32_t* succ, int32_t* rank, int32_t* depth, 
                 uint32_t* inl, uint32_t* asc, hipStream_t s);
 int tree_lca(Ctx* c, const et_tree* t, const int32_t* qx, const int32_t* qy, int64_t q, int32_t* out,
              hipStream_t s);
+int tree_build_batch(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s);
+int tree_lca_batch(Ctx* c, const et_tree* t, const int32_t* qt, const int32_t* qx, const int32_t* qy, int64_t q,
+                   int32_t* out, hipStream_t s);
 int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t nnz, uint32_t* mask,
                 hipStream_t s);
 
@@ -204,15 +207,13 @@ int et_list_rank(et_ctx* ctx, const int32_t* d_succ, int32_t len, const int32_t*
   return et::list_rank_generic(&ctx->impl, d_succ, len, d_heads, n_heads, d_rank, s);
 }
 
-int et_tree_build(et_ctx* ctx, const int32_t* d_parent, int32_t n, hipStream_t s, et_tree** out) {
-  if (!out) return ET_EINVAL;
-  *out = nullptr;
-  if (!ctx || !d_parent || n < 1 || n >= (1 << 30)) return ET_EINVAL;
+static et_tree* tree_alloc(et_ctx* ctx, int32_t n, int32_t batch) {
   Ctx* c = &ctx->impl;
   et_tree* t = new (std::nothrow) et_tree();
-  if (!t) return ET_ENOMEM;
+  if (!t) return nullptr;
   t->ctx = ctx;
   t->n = n;
+  t->batch = batch;
   const size_t N = (size_t)n;
   t->d_succ = static_cast<int32_t*>(et::pool_get(c, 2 * N * sizeof(int32_t)));
   t->d_rank = static_cast<int32_t*>(et::pool_get(c, 2 * N * sizeof(int32_t)));
@@ -221,11 +222,26 @@ int et_tree_build(et_ctx* ctx, const int32_t* d_parent, int32_t n, hipStream_t s
   t->d_rec = static_cast<int4*>(et::pool_get(c, N * sizeof(int4)));
   t->d_head = static_cast<int2*>(et::pool_get(c, (N + 2) * sizeof(int2)));
   t->d_root = static_cast<int32_t*>(et::pool_get(c, 64));
-  if (!t->d_succ || !t->d_rank || !t->d_pre || !t->d_size || !t->d_rec || !t->d_head || !t->d_root) {
-    et_tree_free(t, s);
-    return ET_ENOMEM;
+  bool ok = t->d_succ && t->d_rank && t->d_pre && t->d_size && t->d_rec && t->d_head && t->d_root;
+  if (batch) {
+    t->d_off = static_cast<int64_t*>(et::pool_get(c, ((size_t)batch + 1) * sizeof(int64_t)));
+    t->d_root_of = static_cast<int32_t*>(et::pool_get(c, (size_t)batch * sizeof(int32_t)));
+    ok = ok && t->d_off && t->d_root_of;
   }
-  int rc = et::tree_build(c, t, d_parent, s);
+  if (!ok) {
+    et_tree_free(t, nullptr);
+    return nullptr;
+  }
+  return t;
+}
+
+int et_tree_build(et_ctx* ctx, const int32_t* d_parent, int32_t n, hipStream_t s, et_tree** out) {
+  if (!out) return ET_EINVAL;
+  *out = nullptr;
+  if (!ctx || !d_parent || n < 1 || n >= (1 << 30)) return ET_EINVAL;
+  et_tree* t = tree_alloc(ctx, n, 0);
+  if (!t) return ET_ENOMEM;
+  int rc = et::tree_build(&ctx->impl, t, d_parent, s);
   if (rc) {
     et_tree_free(t, s);
     return rc;
@@ -234,7 +250,41 @@ int et_tree_build(et_ctx* ctx, const int32_t* d_parent, int32_t n, hipStream_t s
   return ET_OK;
 }
 
-int32_t et_tree_size(const et_tree* tree) { return tree ? tree->n : -1; }
+int et_tree_build_batch(et_ctx* ctx, const int32_t* d_parent, const int64_t* d_offsets, int32_t n_trees,
+                        int64_t n_total, hipStream_t s, et_tree** out) {
+  if (!out) return ET_EINVAL;
+  *out = nullptr;
+  if (!ctx || !d_parent || !d_offsets || n_trees < 1 || n_total < n_trees || n_total + 1 >= (1 << 30))
+    return ET_EINVAL;
+  et_tree* t = tree_alloc(ctx, (int32_t)(n_total + 1), n_trees);
+  if (!t) return ET_ENOMEM;
+  if (hipMemcpyAsync(t->d_off, d_offsets, ((size_t)n_trees + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s) !=
+      hipSuccess) {
+    et_tree_free(t, s);
+    return ET_EHIP;
+  }
+  int rc = et::tree_build_batch(&ctx->impl, t, d_parent, s);
+  if (rc) {
+    et_tree_free(t, s);
+    return rc;
+  }
+  *out = t;
+  return ET_OK;
+}
+
+int et_lca_batch(const et_tree* tree, const int32_t* d_qtree, const int32_t* d_qx, const int32_t* d_qy, int64_t q,
+                 int32_t* d_out, hipStream_t s) {
+  if (!tree || !tree->batch || q < 0 || q > (int64_t)0x7fffffff * 64) return ET_EINVAL;
+  if (q > 0 && (!d_qtree || !d_qx || !d_qy || !d_out)) return ET_EINVAL;
+  return et::tree_lca_batch(&tree->ctx->impl, tree, d_qtree, d_qx, d_qy, q, d_out, s);
+}
+
+int32_t et_tree_batch_size(const et_tree* tree) { return tree ? tree->batch : -1; }
+
+int32_t et_tree_size(const et_tree* tree) {
+  if (!tree) return -1;
+  return tree->batch ? tree->n - 1 : tree->n;
+}
 
 int et_tree_export(const et_tree* tree, int32_t* d_succ, int32_t* d_rank, int32_t* d_depth, int32_t* d_pre,
                    int32_t* d_size, uint32_t* d_inlabel, uint32_t* d_asc, hipStream_t s) {
@@ -246,7 +296,8 @@ void et_tree_free(et_tree* tree, hipStream_t s) {
   (void)s;
   if (!tree) return;
   Ctx* c = &tree->ctx->impl;
-  void* blocks[] = {tree->d_succ, tree->d_rank, tree->d_pre, tree->d_size, tree->d_rec, tree->d_head, tree->d_root};
+  void* blocks[] = {tree->d_succ, tree->d_rank, tree->d_pre, tree->d_size, tree->d_rec,
+                    tree->d_head, tree->d_root, tree->d_off, tree->d_root_of};
   for (void* p : blocks)
     if (p) et::pool_put(c, p);
   delete tree;
@@ -254,7 +305,7 @@ void et_tree_free(et_tree* tree, hipStream_t s) {
 
 int et_lca(const et_tree* tree, const int32_t* d_qx, const int32_t* d_qy, int64_t q, int32_t* d_out,
            hipStream_t s) {
-  if (!tree || q < 0 || q > (int64_t)0x7fffffff * 64) return ET_EINVAL;
+  if (!tree || tree->batch || q < 0 || q > (int64_t)0x7fffffff * 64) return ET_EINVAL;
   if (q > 0 && (!d_qx || !d_qy || !d_out)) return ET_EINVAL;
   return et::tree_lca(&tree->ctx->impl, tree, d_qx, d_qy, q, d_out, s);
 }

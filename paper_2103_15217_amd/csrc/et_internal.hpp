@@ -162,7 +162,10 @@ struct et_ctx {
 
 struct et_tree {
   et_ctx* ctx;
-  int32_t n;
+  int32_t n;           // nodes in the tables (a batch adds one virtual root)
+  int32_t batch;       // 0 for one tree, else the number of trees of a batch
+  int64_t* d_off;      // batch: node offsets of the trees [batch+1]
+  int32_t* d_root_of;  // batch: root id of every tree [batch]
   int32_t* d_succ;     // [2n]
   int32_t* d_rank;     // [2n]
   int32_t* d_pre;      // [n]

@@ -165,6 +165,11 @@ __global__ void k_single(const int32_t* __restrict__ parent, int32_t* __restrict
   head[1] = make_int2(-1, -1);
 }
 
+__global__ void k_fill_zero(int32_t* __restrict__ p, int32_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 __global__ void k_export_rec(const int4* __restrict__ rec, int32_t n, int32_t* __restrict__ depth,
                              uint32_t* __restrict__ inl, uint32_t* __restrict__ asc) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -184,6 +189,40 @@ __global__ void k_export_rec(const int4* __restrict__ rec, int32_t n, int32_t* _
 //    label has height j) or the parent of the top of the path entered
 //    below it, whose label keeps the bits above the highest ascendant bit
 //    k < j and sets bit k; the shallower of the two is the LCA.
+__device__ __forceinline__ int32_t sv_query(const int4* __restrict__ rec, const int2* __restrict__ head,
+                                            uint32_t n, int32_t x, int32_t y, bool* bad) {
+  const int4 rx = rec[x];
+  const int4 ry = rec[y];
+  const uint32_t a = (uint32_t)rx.x, b = (uint32_t)ry.x;
+  if (a == b) return (rx.z <= ry.z) ? x : y;
+  const int ha = ctz32(a), hb = ctz32(b);
+  const int i0 = max(max(ha, hb), msb32(a ^ b));
+  const uint32_t ax = (uint32_t)rx.y, ay = (uint32_t)ry.y;
+  const uint32_t common = ax & ay & (~0u << i0);
+  if (common == 0u) {
+    *bad = true;
+    return -1;
+  }
+  const int j = ctz32(common);
+  const uint32_t low = (1u << j) - 1u;
+  int32_t xv = x, xd = rx.z, yv = y, yd = ry.z;
+  if (ha != j) {
+    const int k = msb32(ax & low);
+    const uint32_t w = ((a >> (k + 1)) << (k + 1)) | (1u << k);
+    const int2 h = head[min(w, n)];
+    xv = h.x;
+    xd = h.y;
+  }
+  if (hb != j) {
+    const int k = msb32(ay & low);
+    const uint32_t w = ((b >> (k + 1)) << (k + 1)) | (1u << k);
+    const int2 h = head[min(w, n)];
+    yv = h.x;
+    yd = h.y;
+  }
+  return (xd <= yd) ? xv : yv;
+}
+
 __global__ __launch_bounds__(kB) void k_lca(const int4* __restrict__ rec, const int2* __restrict__ head, int32_t n,
                                            const int32_t* __restrict__ qx, const int32_t* __restrict__ qy,
                                            int64_t q, int32_t* __restrict__ out, uint32_t* __restrict__ status) {
@@ -195,40 +234,103 @@ __global__ __launch_bounds__(kB) void k_lca(const int4* __restrict__ rec, const 
     out[i] = -1;
     return;
   }
-  const int4 rx = rec[x];
-  const int4 ry = rec[y];
-  const uint32_t a = (uint32_t)rx.x, b = (uint32_t)ry.x;
-  int32_t res;
-  if (a == b) {
-    res = (rx.z <= ry.z) ? x : y;
-  } else {
-    const int ha = ctz32(a), hb = ctz32(b);
-    const int i0 = max(max(ha, hb), msb32(a ^ b));
-    const uint32_t ax = (uint32_t)rx.y, ay = (uint32_t)ry.y;
-    const uint32_t common = ax & ay & (~0u << i0);
-    if (common == 0u) {
-      flag(status, ST_BAD_INDEX);
-      out[i] = -1;
-      return;
-    }
-    const int j = ctz32(common);
-    const uint32_t low = (1u << j) - 1u;
-    int32_t xv = x, xd = rx.z, yv = y, yd = ry.z;
-    if (ha != j) {
-      const int k = msb32(ax & low);
-      const uint32_t w = ((a >> (k + 1)) << (k + 1)) | (1u << k);
-      const int2 h = head[min(w, (uint32_t)n)];
-      xv = h.x; xd = h.y;
-    }
-    if (hb != j) {
-      const int k = msb32(ay & low);
-      const uint32_t w = ((b >> (k + 1)) << (k + 1)) | (1u << k);
-      const int2 h = head[min(w, (uint32_t)n)];
-      yv = h.x; yd = h.y;
-    }
-    res = (xd <= yd) ? xv : yv;
+  bool bad = false;
+  const int32_t r = sv_query(rec, head, (uint32_t)n, x, y, &bad);
+  if (bad) flag(status, ST_BAD_INDEX);
+  out[i] = r;
+}
+
+// Batched trees: tree t's nodes are the global ids [off[t], off[t+1]); all
+// trees hang below a virtual root (global id N), so the LCA of two nodes of
+// one tree is the LCA in the combined tree.
+__device__ __forceinline__ int32_t tree_of(const int64_t* __restrict__ off, int32_t T, int64_t v) {
+  int32_t lo = 0, hi = T;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= v) lo = mid;
+    else hi = mid;
   }
-  out[i] = res;
+  return lo;
+}
+
+__global__ __launch_bounds__(kB) void k_lca_batch(const int4* __restrict__ rec, const int2* __restrict__ head,
+                                                 int32_t n, const int64_t* __restrict__ off, int32_t T,
+                                                 const int32_t* __restrict__ qt, const int32_t* __restrict__ qx,
+                                                 const int32_t* __restrict__ qy, int64_t q, int32_t* __restrict__ out,
+                                                 uint32_t* __restrict__ status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= q) return;
+  const int32_t t = qt[i];
+  if ((uint32_t)t >= (uint32_t)T) {
+    flag(status, ST_BAD_QUERY);
+    out[i] = -1;
+    return;
+  }
+  const int64_t base = off[t];
+  const int64_t nt = off[t + 1] - base;
+  const int32_t x = qx[i], y = qy[i];
+  if ((int64_t)(uint32_t)x >= nt || (int64_t)(uint32_t)y >= nt || base + nt > n) {
+    flag(status, ST_BAD_QUERY);
+    out[i] = -1;
+    return;
+  }
+  bool bad = false;
+  const int32_t r = sv_query(rec, head, (uint32_t)n, (int32_t)(base + x), (int32_t)(base + y), &bad);
+  if (bad || r < base || r >= base + nt) {
+    flag(status, ST_BAD_INDEX);
+    out[i] = -1;
+    return;
+  }
+  out[i] = (int32_t)(r - base);
+}
+
+// combined parent array: roots of the trees hang below the virtual root N
+__global__ void k_batch_parent(const int32_t* __restrict__ parent, const int64_t* __restrict__ off, int32_t T,
+                               int32_t N, int32_t* __restrict__ gp, int32_t* __restrict__ nroots,
+                               int32_t* __restrict__ root_of, uint32_t* __restrict__ status) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v > N) return;
+  if (v == N) {
+    gp[N] = -1;
+    if (off[0] != 0 || off[T] != N) flag(status, ST_BAD_PARENT);
+    return;
+  }
+  const int32_t t = tree_of(off, T, v);
+  const int64_t base = off[t], nt = off[t + 1] - base;
+  const int32_t p = parent[v];
+  if (p == -1) {
+    gp[v] = N;
+    atomicAdd(nroots + t, 1);
+    root_of[t] = (int32_t)v;
+  } else if (p >= 0 && p < nt && base + p != v) {
+    gp[v] = (int32_t)(base + p);
+  } else {
+    flag(status, ST_BAD_PARENT);
+    gp[v] = N;
+  }
+}
+
+__global__ void k_batch_check(const int64_t* __restrict__ off, int32_t T, const int32_t* __restrict__ nroots,
+                              uint32_t* __restrict__ status) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  if (nroots[t] != 1 || off[t + 1] <= off[t]) flag(status, ST_ROOTS);
+}
+
+// per-tree statistics of a batch: preorder and depth relative to the tree's root
+__global__ void k_export_batch(const int4* __restrict__ rec, const int32_t* __restrict__ size_in,
+                               const int64_t* __restrict__ off, int32_t T, int32_t N,
+                               const int32_t* __restrict__ root_of, int32_t* __restrict__ depth,
+                               int32_t* __restrict__ pre, int32_t* __restrict__ size) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const int32_t t = tree_of(off, T, v);
+  const int32_t r = root_of[t];
+  const int4 rv = rec[v];
+  const int32_t rp = ((uint32_t)r < (uint32_t)N) ? rec[r].w : 0;
+  if (depth) depth[v] = rv.z - 1;
+  if (pre) pre[v] = rv.w - rp;
+  if (size) size[v] = size_in[v];
 }
 
 }  // namespace
@@ -285,6 +387,14 @@ int tree_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
 
 int tree_export(const et_tree* t, int32_t* succ, int32_t* rank, int32_t* depth, int32_t* pre, int32_t* size,
                 uint32_t* inl, uint32_t* asc, hipStream_t s) {
+  if (t->batch) {
+    if (succ || rank || inl || asc) return ET_EINVAL;  // global tables of a batch are internal
+    const int32_t N = t->n - 1;
+    if (depth || pre || size)
+      hipLaunchKernelGGL(k_export_batch, dim3(ceil_div(N, kB)), dim3(kB), 0, s, t->d_rec, t->d_size, t->d_off,
+                         t->batch, N, t->d_root_of, depth, pre, size);
+    return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+  }
   const int32_t n = t->n;
   const size_t b = (size_t)n * sizeof(int32_t);
   if (succ && hipMemcpyAsync(succ, t->d_succ, 2 * b, hipMemcpyDeviceToDevice, s) != hipSuccess) return ET_EHIP;
@@ -294,6 +404,34 @@ int tree_export(const et_tree* t, int32_t* succ, int32_t* rank, int32_t* depth, 
   if (depth || inl || asc)
     hipLaunchKernelGGL(k_export_rec, dim3(ceil_div(n, kB)), dim3(kB), 0, s, t->d_rec, n, depth, inl, asc);
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+}
+
+int tree_lca_batch(Ctx* c, const et_tree* t, const int32_t* qt, const int32_t* qx, const int32_t* qy, int64_t q,
+                   int32_t* out, hipStream_t s) {
+  if (q == 0) return ET_OK;
+  const int64_t blocks = (q + kB - 1) / kB;
+  {
+    ET_PROF(c, s, "k_lca_batch");
+    hipLaunchKernelGGL(k_lca_batch, dim3((unsigned)blocks), dim3(kB), 0, s, t->d_rec, t->d_head, t->n, t->d_off,
+                       t->batch, qt, qx, qy, q, out, c->d_status);
+  }
+  return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+}
+
+int tree_build_batch(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
+  const int32_t N = t->n - 1, T = t->batch;
+  Scratch scr(c);
+  int32_t* gp = scr.get<int32_t>((size_t)N + 1);
+  int32_t* nroots = scr.get<int32_t>((size_t)T);
+  if (scr.failed) return ET_ENOMEM;
+  hipLaunchKernelGGL(k_fill_zero, dim3(ceil_div(T, kB)), dim3(kB), 0, s, nroots, T);
+  {
+    ET_PROF(c, s, "k_batch_parent");
+    hipLaunchKernelGGL(k_batch_parent, dim3(ceil_div((int64_t)N + 1, kB)), dim3(kB), 0, s, parent, t->d_off, T, N,
+                       gp, nroots, t->d_root_of, c->d_status);
+  }
+  hipLaunchKernelGGL(k_batch_check, dim3(ceil_div(T, kB)), dim3(kB), 0, s, t->d_off, T, nroots, c->d_status);
+  return tree_build(c, t, gp, s);
 }
 
 int tree_lca(Ctx* c, const et_tree* t, const int32_t* qx, const int32_t* qy, int64_t q, int32_t* out,

@@ -34,6 +34,9 @@ _SIG = {
     "et_list_rank": ([_P, _P, _i32, _P, _i32, _P, _P], ctypes.c_int),
     "et_tree_build": ([_P, _P, _i32, _P, ctypes.POINTER(_P)], ctypes.c_int),
     "et_tree_size": ([_P], _i32),
+    "et_tree_batch_size": ([_P], _i32),
+    "et_tree_build_batch": ([_P, _P, _P, _i32, _i64, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "et_lca_batch": ([_P, _P, _P, _P, _i64, _P, _P], ctypes.c_int),
     "et_tree_export": ([_P, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "et_tree_free": ([_P, _P], None),
     "et_lca": ([_P, _P, _P, _i64, _P, _P], ctypes.c_int),
@@ -170,16 +173,23 @@ def et_list_rank(succ, heads, rank=None, ctx=None):
 # ------------------------------------------------------------------ trees and LCA
 
 class Tree:
-    """A built tree (``et_tree``): Euler tour, node statistics, Inlabel tables."""
+    """A built tree or batch of trees (``et_tree``): Euler tour, node
+    statistics, Inlabel tables."""
 
-    def __init__(self, handle, n, ctx):
+    def __init__(self, handle, n, ctx, batch=0):
         self._h = handle
         self.n = n
         self.ctx = ctx
+        self.batch = batch
 
     def export(self):
         n = self.n
         dev = torch.device("cuda", self.ctx.device)
+        if self.batch:
+            out = {k: torch.empty(n, dtype=torch.int32, device=dev) for k in ("depth", "pre", "size")}
+            _check(_lib.et_tree_export(self._h, None, None, _ptr(out["depth"]), _ptr(out["pre"]),
+                                       _ptr(out["size"]), None, None, _stream()), "et_tree_export")
+            return out
         out = {
             "succ": torch.empty(2 * n, dtype=torch.int32, device=dev),
             "rank": torch.empty(2 * n, dtype=torch.int32, device=dev),
@@ -192,6 +202,19 @@ class Tree:
         _check(_lib.et_tree_export(self._h, *[_ptr(out[k]) for k in
                                               ("succ", "rank", "depth", "pre", "size", "inlabel", "asc")],
                                    _stream()), "et_tree_export")
+        return out
+
+    def lca_batch(self, qtree, qx, qy, out=None):
+        """LCA of local nodes qx[i], qy[i] of tree qtree[i] (local ids out)."""
+        qt = _dev(qtree, torch.int32, "qtree")
+        qx = _dev(qx, torch.int32, "qx")
+        qy = _dev(qy, torch.int32, "qy")
+        if not (qx.numel() == qy.numel() == qt.numel()):
+            raise ValueError("query arrays differ in length")
+        if out is None:
+            out = torch.empty_like(qx)
+        _check(_lib.et_lca_batch(self._h, _ptr(qt), _ptr(qx), _ptr(qy), qx.numel(), _ptr(out), _stream()),
+               "et_lca_batch")
         return out
 
     def lca(self, qx, qy, out=None):
@@ -227,6 +250,23 @@ def et_tree_build(parent, ctx=None):
 
 def et_lca(tree, qx, qy, out=None):
     return tree.lca(qx, qy, out)
+
+
+def et_tree_build_batch(parent, offsets, ctx=None):
+    """Build a batch of trees: ``parent`` holds each tree's local parent
+    array back to back, ``offsets`` (int64, T+1) the tree boundaries."""
+    ctx = ctx or default_context()
+    parent = _dev(parent, torch.int32, "parent")
+    offsets = _dev(offsets, torch.int64, "offsets")
+    T = offsets.numel() - 1
+    h = _P()
+    _check(_lib.et_tree_build_batch(ctx.handle, _ptr(parent), _ptr(offsets), T, parent.numel(), _stream(),
+                                    ctypes.byref(h)), "et_tree_build_batch")
+    return Tree(h, parent.numel(), ctx, batch=T)
+
+
+def et_lca_batch(tree, qtree, qx, qy, out=None):
+    return tree.lca_batch(qtree, qx, qy, out)
 
 
 # ------------------------------------------------------------------ bridges
