@@ -76,6 +76,14 @@ int et_ctx_status(et_ctx* ctx, hipStream_t s);
  * diagnostics; same waiting semantics). */
 int et_ctx_status_bits(et_ctx* ctx, hipStream_t s, uint32_t* h_bits);
 
+/* Tunable launch parameters of this context (used by later calls):
+ *   "lr_k1_log2"    list ranking, level 1: one splitter per 2^v ids (1..10, default 4)
+ *   "lr_per_wave1"  level 1: sublists owned by one wavefront (64..65536, default 256)
+ *   "lr_kn_log2"    upper levels: one splitter per 2^v elements (1..10, default 3)
+ *   "lr_per_waven"  upper levels: sublists per wavefront (64..65536, default 128)
+ * Results never depend on them. ET_EINVAL for an unknown name or value. */
+int et_ctx_set_param(et_ctx* ctx, const char* name, int64_t value);
+
 /* Kernel timing. With enable != 0 every kernel launch of later calls on
  * this context is bracketed by a pair of HIP events on its stream. */
 int et_ctx_profile(et_ctx* ctx, int enable);

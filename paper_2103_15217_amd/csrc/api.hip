@@ -136,6 +136,18 @@ void et_ctx_destroy(et_ctx* ctx) {
   delete ctx;
 }
 
+int et_ctx_set_param(et_ctx* ctx, const char* name, int64_t value) {
+  if (!ctx || !name) return ET_EINVAL;
+  et::LrShape& lr = ctx->impl.lr;
+  const std::string k(name);
+  if (k == "lr_k1_log2" && value >= 1 && value <= 10) lr.k1_log2 = (int)value;
+  else if (k == "lr_per_wave1" && value >= 64 && value <= 65536) lr.per_wave1 = (int)value;
+  else if (k == "lr_kn_log2" && value >= 1 && value <= 10) lr.kn_log2 = (int)value;
+  else if (k == "lr_per_waven" && value >= 64 && value <= 65536) lr.per_waven = (int)value;
+  else return ET_EINVAL;
+  return ET_OK;
+}
+
 int et_ctx_profile(et_ctx* ctx, int enable) {
   if (!ctx) return ET_EINVAL;
   ctx->impl.profiling = enable != 0;

@@ -2,11 +2,13 @@
 //
 //  1. Spanning forest (the paper uses the connectivity code of Jaiganesh and
 //     Burtscher, which yields a spanning tree as a by-product): union-find
-//     hooking over every edge {u, w}, u < w, taken at its first slot in row
-//     u. Roots only ever link to smaller roots with a compare-and-swap, so a
-//     successful swap joins two different trees and its edge is a forest
-//     edge; both of its slots are marked in a bitmask. Parallel copies of an
-//     edge are never forest edges and self-loops are skipped.
+//     hooking where a successful compare-and-swap of a root joins two
+//     different trees, so its edge is a forest edge; both of its slots are
+//     marked in a bitmask. Parallel copies of an edge are never forest edges
+//     and self-loops are skipped. Every vertex first hooks its first two
+//     distinct neighbours; then the most frequent root of a sample names the
+//     big component, and only rows of vertices outside it hook all their
+//     edges (an edge inside the big component joins nothing new).
 //  2. Euler tour of the forest as the paper's DCEL (Section 2.1) read from
 //     the CSR: the forest slots of a row, in row order, are the sorted run
 //     of B for that vertex, next() wraps inside the run, twin() is found by
@@ -19,8 +21,8 @@
 //  4. For every vertex the minimum and maximum preorder over itself and its
 //     non-forest neighbours (the paper's segreduce); stored by preorder.
 //  5. low(v) / high(v) = range minimum / maximum of those over v's subtree
-//     interval, with a sparse table over 32-element blocks plus in-block
-//     prefix / suffix extremes (the paper uses a segment tree).
+//     interval, with a sparse table over 32-element blocks and per-position
+//     suffix-extreme bitmasks inside a block (the paper uses a segment tree).
 //  6. The forest edge above v is a bridge iff low(v) and high(v) both lie
 //     inside [pre(v), pre(v) + size(v)) (Tarjan 1974; including pre(v)
 //     itself makes the test two equalities). Both slots get their bit.
@@ -50,18 +52,72 @@ __device__ __forceinline__ void st(int32_t* p, int32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// root of x; cc[v] <= v always, so the walk strictly decreases; halves the path
+// Union-find over cc[]: roots satisfy cc[r] == r. A link always hangs the
+// root with the larger key under the one with the smaller key, where the
+// key is the vertex id except that the designated big component's root
+// (if any) counts as smallest; keys therefore strictly decrease towards the
+// root, so the forest stays acyclic under concurrent links, and every
+// successful compare-and-swap joins two different trees: its edge is a
+// spanning-forest edge.
+//
+// Finds use ordinary cached loads, which may return an out-of-date parent
+// (each XCD has its own L2); an out-of-date view is still a chain of
+// ancestors. Only the device-scope compare-and-swap decides a link: if the
+// node it targets is no longer a root it fails and returns the node's
+// current parent, and the hook continues from there, so every failure moves
+// strictly up. Two nodes of one tree can never be linked: the one with the
+// larger key is never that tree's root, and the swap is always on it.
+__device__ __forceinline__ int32_t ldc(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void stc(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// an ancestor-or-self of x that looked like a root; halves the path on the way
 __device__ int32_t cc_find(int32_t* cc, int32_t x) {
-  int32_t cur = ld(cc + x);
-  if (cur != x) {
-    int32_t prev = x, next;
-    while (cur > (next = ld(cc + cur))) {
-      st(cc + prev, next);
-      prev = cur;
-      cur = next;
-    }
+  int32_t cur = x;
+  for (;;) {
+    const int32_t p = ldc(cc + cur);
+    if (p == cur) return cur;
+    const int32_t gp = ldc(cc + p);
+    if (gp != p) stc(cc + cur, gp);
+    cur = gp;
   }
-  return cur;
+}
+
+__device__ __forceinline__ int64_t cc_key(int32_t v, int32_t big) { return v == big ? -1 : (int64_t)v; }
+
+// true iff this call linked the trees of u and w (its edge joins the forest)
+__device__ bool cc_hook(int32_t* cc, int32_t u, int32_t w, int32_t big, bool* over) {
+  int32_t ru = cc_find(cc, u), rw = cc_find(cc, w);
+  for (int it = 0; it < (1 << 22); ++it) {
+    if (ru == rw) return false;
+    const bool u_up = cc_key(ru, big) > cc_key(rw, big);
+    const int32_t hi = u_up ? ru : rw, lo = u_up ? rw : ru;
+    const int32_t old = atomicCAS(cc + hi, hi, lo);
+    if (old == hi) return true;
+    if (u_up) ru = cc_find(cc, old);
+    else rw = cc_find(cc, old);
+  }
+  *over = true;
+  return false;
+}
+
+// mark slot k = (u, w) and its twin, the first (w, u) slot of row w
+__device__ void mark_forest(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, int32_t nnz,
+                            uint32_t* __restrict__ tbits, int32_t k, int32_t u, int32_t w, bool* bad) {
+  atomicOr(tbits + (k >> 5), 1u << (k & 31));
+  const int32_t wbeg = min(max(row_ptr[w], 0), nnz);
+  const int32_t wend = min(max(row_ptr[w + 1], wbeg), nnz);
+  int32_t lo = wbeg, hi = wend;
+  while (lo < hi) {
+    const int32_t mid = lo + ((hi - lo) >> 1);
+    if (col[mid] < u) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo < wend && col[lo] == u) atomicOr(tbits + (lo >> 5), 1u << (lo & 31));
+  else *bad = true;
 }
 
 __device__ __forceinline__ int32_t clampi(int32_t x, int32_t lo, int32_t hi) { return min(max(x, lo), hi); }
@@ -89,50 +145,103 @@ __device__ __forceinline__ int row_of(const int32_t* rp_lds, int cnt, int32_t k)
   return lo;
 }
 
-__global__ __launch_bounds__(kB) void k_hook(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                                            int32_t n, int32_t nnz, int32_t* cc, uint32_t* __restrict__ tbits,
-                                            uint32_t* __restrict__ status) {
+// Sampling phase: every vertex hooks its first kSample distinct neighbours.
+constexpr int kSample = 2;
+
+__global__ void k_hook_sample(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, int32_t n,
+                              int32_t nnz, int32_t* cc, uint32_t* __restrict__ tbits, uint32_t* __restrict__ status) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int32_t a = clampi(row_ptr[u], 0, nnz), b = clampi(row_ptr[u + 1], a, nnz);
+  bool bad = false, over = false;
+  int taken = 0;
+  for (int32_t k = a; k < b && taken < kSample; ++k) {
+    const int32_t w = col[k];
+    if ((uint32_t)w >= (uint32_t)n) {
+      bad = true;
+      continue;
+    }
+    if (w == u || (k > a && col[k - 1] == w)) continue;  // self-loop or a parallel copy
+    ++taken;
+    if (cc_hook(cc, (int32_t)u, w, -1, &over)) mark_forest(row_ptr, col, nnz, tbits, k, (int32_t)u, w, &bad);
+  }
+  if (bad) flag(status, ST_BAD_CSR);
+  if (over) flag(status, ST_OVERFLOW);
+}
+
+__global__ void k_cc_compress(int32_t* cc, int32_t n) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) st(cc + v, cc_find(cc, (int32_t)v));
+}
+
+// The most frequent root among 1024 sampled vertices: the big component.
+constexpr int kBigSample = 1024;
+
+__global__ __launch_bounds__(kBigSample) void k_big_component(const int32_t* cc, int32_t n, int32_t* __restrict__ big) {
+  __shared__ int32_t r[kBigSample];
+  __shared__ int32_t best, best_count;
+  const int t = threadIdx.x;
+  const uint32_t v = mix32(0x2545f491u + (uint32_t)t) % (uint32_t)n;
+  r[t] = ld(cc + v);
+  if (t == 0) {
+    best = INT32_MAX;
+    best_count = 0;
+  }
+  __syncthreads();
+  for (int k = 2; k <= kBigSample; k <<= 1) {  // bitonic sort
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int o = t ^ j;
+      if (o > t) {
+        const bool up = (t & k) == 0;
+        const int32_t x = r[t], y = r[o];
+        if ((x > y) == up) {
+          r[t] = y;
+          r[o] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // the longest run of equal roots wins (smallest root on a tie)
+  int len = 0;
+  if (t == 0 || r[t - 1] != r[t]) {
+    len = 1;
+    while (t + len < kBigSample && r[t + len] == r[t]) ++len;
+    atomicMax(&best_count, len);
+  }
+  __syncthreads();
+  if (len > 0 && len == best_count) atomicMin(&best, r[t]);
+  __syncthreads();
+  if (t == 0) *big = best;
+}
+
+// Remaining phase: rows of vertices outside the big component hook every
+// distinct neighbour. An edge between two vertices of the big component is
+// already inside one tree; any other edge is seen from an endpoint outside.
+__global__ __launch_bounds__(kB) void k_hook_rest(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                                 int32_t n, int32_t nnz, int32_t* cc, const int32_t* __restrict__ bigp,
+                                                 uint32_t* __restrict__ tbits, uint32_t* __restrict__ status) {
   __shared__ int32_t rp[kRowsPerBlock + 1];
+  __shared__ uint8_t skip[kRowsPerBlock];
   const int32_t r0 = blockIdx.x * kRowsPerBlock;
   const int cnt = min(kRowsPerBlock, n - r0);
+  const int32_t big = *bigp;
   for (int i = threadIdx.x; i <= cnt; i += kB) rp[i] = clampi(row_ptr[r0 + i], 0, nnz);
+  for (int i = threadIdx.x; i < cnt; i += kB) skip[i] = (cc_find(cc, r0 + i) == big);
   __syncthreads();
   const int32_t kbeg = rp[0], kend = rp[cnt];
   bool bad = false, over = false;
   for (int32_t k = kbeg + threadIdx.x; k < kend; k += kB) {
     const int ri = row_of(rp, cnt, k);
+    if (skip[ri]) continue;
     const int32_t u = r0 + ri;
     const int32_t w = col[k];
     if ((uint32_t)w >= (uint32_t)n) {
       bad = true;
       continue;
     }
-    if (u >= w) continue;
-    if (k > rp[ri] && col[k - 1] == w) continue;  // a parallel copy
-    bool linked = false;
-    for (int it = 0; it < (1 << 22); ++it) {
-      const int32_t ru = cc_find(cc, u), rw = cc_find(cc, w);
-      if (ru == rw) break;
-      const int32_t hi = max(ru, rw), lo = min(ru, rw);
-      if (atomicCAS(cc + hi, hi, lo) == hi) {
-        linked = true;
-        break;
-      }
-      if (it == (1 << 22) - 1) over = true;
-    }
-    if (!linked) continue;
-    atomicOr(tbits + (k >> 5), 1u << (k & 31));
-    // twin slot: first (w, u) slot in row w
-    const int32_t wbeg = clampi(row_ptr[w], 0, nnz);
-    const int32_t wend = clampi(row_ptr[w + 1], wbeg, nnz);
-    int32_t lo = wbeg, hi = wend;
-    while (lo < hi) {
-      const int32_t mid = lo + ((hi - lo) >> 1);
-      if (col[mid] < u) lo = mid + 1;
-      else hi = mid;
-    }
-    if (lo < wend && col[lo] == u) atomicOr(tbits + (lo >> 5), 1u << (lo & 31));
-    else bad = true;
+    if (w == u || (k > rp[ri] && col[k - 1] == w)) continue;
+    if (cc_hook(cc, u, w, big, &over)) mark_forest(row_ptr, col, nnz, tbits, k, u, w, &bad);
   }
   if (bad) flag(status, ST_BAD_CSR);
   if (over) flag(status, ST_OVERFLOW);
@@ -322,8 +431,12 @@ __global__ void k_direction(const int32_t* __restrict__ rank, const int32_t* __r
   }
 }
 
-__global__ void k_preorder(const int32_t* __restrict__ vR, const int32_t* __restrict__ vpslot,
-                           const uint32_t* __restrict__ I, int32_t n, int32_t Lcap, int32_t* __restrict__ pre) {
+// preorder of every vertex (-1 if isolated), and the vertex's subtree size
+// and forest-edge slots stored by preorder for the bridge test
+__global__ void k_preorder(const int32_t* __restrict__ vR, const int32_t* __restrict__ vsize,
+                           const int32_t* __restrict__ vpslot, const int32_t* __restrict__ vuslot,
+                           const uint32_t* __restrict__ I, int32_t n, int32_t Lcap, int32_t* __restrict__ pre,
+                           int4* __restrict__ byp) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int32_t r = vR[v];
@@ -331,70 +444,86 @@ __global__ void k_preorder(const int32_t* __restrict__ vR, const int32_t* __rest
     pre[v] = -1;
     return;
   }
-  pre[v] = (int32_t)I[r] - (vpslot[v] < 0 ? 2 : 1);
+  const int32_t ps = vpslot[v];
+  const int32_t p = (int32_t)I[r] - (ps < 0 ? 2 : 1);
+  pre[v] = p;
+  if ((uint32_t)p < (uint32_t)n) byp[p] = make_int4(vsize[v], ps, vuslot[v], 0);
 }
 
 // per vertex: min / max preorder over itself and its non-forest neighbours,
-// stored at its own preorder position
+// stored at its own preorder position (the paper's segreduce). 16 lanes
+// share a row: they read its slots side by side and combine with shuffles.
+constexpr int kRowLanes = 16;
+
 __global__ __launch_bounds__(kB) void k_minmax(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                               const uint32_t* __restrict__ tbits, const int32_t* __restrict__ pre,
                                               int32_t n, int32_t nnz, int32_t* __restrict__ amin,
                                               int32_t* __restrict__ amax) {
-  __shared__ int32_t rp[kRowsPerBlock + 1];
-  __shared__ int32_t mn[kRowsPerBlock], mx[kRowsPerBlock];
-  const int32_t r0 = blockIdx.x * kRowsPerBlock;
-  const int cnt = min(kRowsPerBlock, n - r0);
-  for (int i = threadIdx.x; i <= cnt; i += kB) rp[i] = clampi(row_ptr[r0 + i], 0, nnz);
-  for (int i = threadIdx.x; i < cnt; i += kB) {
-    const int32_t p = pre[r0 + i];
-    mn[i] = p;
-    mx[i] = p;
-  }
-  __syncthreads();
-  const int32_t kbeg = rp[0], kend = rp[cnt];
-  for (int32_t k = kbeg + threadIdx.x; k < kend; k += kB) {
+  const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes;
+  const int sub = threadIdx.x & (kRowLanes - 1);
+  if (u >= n) return;                 // whole row group leaves together
+  const int32_t p = pre[u];
+  if (p < 0 || p >= n) return;        // isolated vertex
+  const int32_t a = clampi(row_ptr[u], 0, nnz), b = clampi(row_ptr[u + 1], a, nnz);
+  int32_t mn = p, mx = p;
+  for (int32_t k = a + sub; k < b; k += kRowLanes) {
     if ((tbits[k >> 5] >> (k & 31)) & 1u) continue;
     const int32_t w = col[k];
     if ((uint32_t)w >= (uint32_t)n) continue;
     const int32_t pw = pre[w];
-    const int ri = row_of(rp, cnt, k);
-    atomicMin(&mn[ri], pw);
-    atomicMax(&mx[ri], pw);
+    mn = min(mn, pw);
+    mx = max(mx, pw);
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < cnt; i += kB) {
-    const int32_t p = pre[r0 + i];
-    if (p >= 0 && p < n) {
-      amin[p] = mn[i];
-      amax[p] = mx[i];
-    }
+#pragma unroll
+  for (int o = kRowLanes / 2; o > 0; o >>= 1) {
+    mn = min(mn, __shfl_xor(mn, o, kRowLanes));
+    mx = max(mx, __shfl_xor(mx, o, kRowLanes));
+  }
+  if (sub == 0) {
+    amin[p] = mn;
+    amax[p] = mx;
   }
 }
 
-// in-block (32) prefix / suffix extremes and block extremes
+// In-block RMQ by suffix-extreme bitmasks: for position o of a 32-element
+// block, bit j <= o of mmin[o] is set iff element j is smaller than every
+// element after it up to o. The minimum of [l, o] is then the element at the
+// lowest set bit at or above l: that element is a suffix minimum and no
+// suffix minimum between l and it can be smaller. Likewise for maxima.
+// Lane o of each 32-lane group builds its two masks; lane 31 also yields
+// the block's extremes (level 0 of the sparse table).
 __global__ __launch_bounds__(kB) void k_rmq_blocks(const int32_t* __restrict__ amin, const int32_t* __restrict__ amax,
-                                                  int32_t n, int32_t* __restrict__ pmin, int32_t* __restrict__ smin,
-                                                  int32_t* __restrict__ pmax, int32_t* __restrict__ smax,
+                                                  int32_t n, uint32_t* __restrict__ mmin, uint32_t* __restrict__ mmax,
                                                   int32_t* __restrict__ bmin, int32_t* __restrict__ bmax) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool ok = i < n;
   const int32_t vmin = ok ? amin[i] : INT32_MAX;
   const int32_t vmax = ok ? amax[i] : INT32_MIN;
-  const int l = __lane_id() & 31;
-  int32_t a = vmin, b = vmax, c = vmin, d = vmax;
+  const int o = __lane_id() & 31;
+  uint32_t fmin = 0, fmax = 0;
+  int32_t rmin = INT32_MAX, rmax = INT32_MIN;
 #pragma unroll
-  for (int s = 1; s < 32; s <<= 1) {
-    const int32_t ua = __shfl_up(a, s, 32), ub = __shfl_up(b, s, 32);
-    const int32_t dc = __shfl_down(c, s, 32), dd = __shfl_down(d, s, 32);
-    if (l >= s) { a = min(a, ua); b = max(b, ub); }
-    if (l + s < 32) { c = min(c, dc); d = max(d, dd); }
+  for (int j = 31; j >= 0; --j) {
+    const int32_t x = __shfl(vmin, j, 32);
+    const int32_t y = __shfl(vmax, j, 32);
+    if (j <= o) {
+      if (x < rmin) {
+        fmin |= 1u << j;
+        rmin = x;
+      }
+      if (y > rmax) {
+        fmax |= 1u << j;
+        rmax = y;
+      }
+    }
   }
   if (ok) {
-    pmin[i] = a; pmax[i] = b; smin[i] = c; smax[i] = d;
+    mmin[i] = fmin;
+    mmax[i] = fmax;
   }
-  if (l == 31 && (i >> kRmqLog) < ((n + 31) >> kRmqLog)) {
-    bmin[i >> kRmqLog] = a;
-    bmax[i >> kRmqLog] = b;
+  if (o == 31 && (i >> kRmqLog) < ((n + 31) >> kRmqLog)) {
+    bmin[i >> kRmqLog] = rmin;
+    bmax[i >> kRmqLog] = rmax;
   }
 }
 
@@ -408,25 +537,32 @@ __global__ void k_sparse_level(const int32_t* __restrict__ pmn, const int32_t* _
 }
 
 struct Rmq {
-  const int32_t *amin, *amax, *pmin, *smin, *pmax, *smax;
-  const int32_t* stmin;  // levels concatenated: level k at k * nb
+  const int32_t *amin, *amax;
+  const uint32_t *mmin, *mmax;
+  const int32_t* stmin;  // sparse table levels concatenated: level k at k * nb
   const int32_t* stmax;
   int32_t nb;
 };
+
+// extremes of [l, r] inside one 32-element block, r's block
+__device__ __forceinline__ void rmq_in_block(const Rmq& q, int32_t l, int32_t r, int32_t* mn, int32_t* mx) {
+  const int32_t base = r & ~31;
+  const uint32_t keep = ~0u << (l - base);
+  *mn = q.amin[base + ctz32(q.mmin[r] & keep)];
+  *mx = q.amax[base + ctz32(q.mmax[r] & keep)];
+}
 
 __device__ __forceinline__ void rmq(const Rmq& q, int32_t l, int32_t r, int32_t* lo, int32_t* hi) {
   const int32_t bl = l >> kRmqLog, br = r >> kRmqLog;
   int32_t mn, mx;
   if (bl == br) {
-    mn = INT32_MAX;
-    mx = INT32_MIN;
-    for (int32_t i = l; i <= r; ++i) {
-      mn = min(mn, q.amin[i]);
-      mx = max(mx, q.amax[i]);
-    }
+    rmq_in_block(q, l, r, &mn, &mx);
   } else {
-    mn = min(q.smin[l], q.pmin[r]);
-    mx = max(q.smax[l], q.pmax[r]);
+    int32_t a0, a1, b0, b1;
+    rmq_in_block(q, l, (bl << kRmqLog) + 31, &a0, &a1);
+    rmq_in_block(q, br << kRmqLog, r, &b0, &b1);
+    mn = min(a0, b0);
+    mx = max(a1, b1);
     if (bl + 1 <= br - 1) {
       const int32_t a = bl + 1, b = br - 1;
       const int k = msb32((uint32_t)(b - a + 1));
@@ -439,31 +575,30 @@ __device__ __forceinline__ void rmq(const Rmq& q, int32_t l, int32_t r, int32_t*
   *hi = mx;
 }
 
-__global__ __launch_bounds__(kB) void k_bridge_test(const int32_t* __restrict__ pre, const int32_t* __restrict__ vsize,
-                                                   const int32_t* __restrict__ vpslot,
-                                                   const int32_t* __restrict__ vuslot, int32_t n, Rmq q,
-                                                   uint32_t* __restrict__ mask, int64_t* __restrict__ count) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// one lane per preorder position i < (number of non-isolated vertices, the
+// last value of the preorder scan): the subtree interval starts at i, so
+// neighbouring lanes read neighbouring RMQ entries
+__global__ __launch_bounds__(kB) void k_bridge_test(const int4* __restrict__ byp, const uint32_t* __restrict__ I,
+                                                   int32_t Lcap, int32_t n, Rmq q, uint32_t* __restrict__ mask,
+                                                   int64_t* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t npre = min((int32_t)I[Lcap - 1], n);
   bool is_bridge = false;
-  if (v < n) {
-    const int32_t p = pre[v];
-    const int32_t ps = vpslot[v];
-    if (p >= 0 && ps >= 0) {
-      const int32_t r = p + vsize[v] - 1;
-      if (r >= p && r < n) {
-        int32_t lo, hi;
-        rmq(q, p, r, &lo, &hi);
-        if (lo == p && hi == r) {
-          is_bridge = true;
-          const int32_t us = vuslot[v];
-          atomicOr(mask + (ps >> 5), 1u << (ps & 31));
-          if (us >= 0) atomicOr(mask + (us >> 5), 1u << (us & 31));
-        }
+  if (i < npre) {
+    const int4 b = byp[i];
+    const int32_t l = (int32_t)i, r = l + b.x - 1;
+    if (b.y >= 0 && r >= l && r < npre) {
+      int32_t lo, hi;
+      rmq(q, l, r, &lo, &hi);
+      if (lo == l && hi == r) {
+        is_bridge = true;
+        atomicOr(mask + (b.y >> 5), 1u << (b.y & 31));
+        if (b.z >= 0) atomicOr(mask + (b.z >> 5), 1u << (b.z & 31));
       }
     }
   }
-  const uint64_t b = __ballot(is_bridge);
-  if (__lane_id() == 0 && b) atomicAdd((unsigned long long*)count, (unsigned long long)__popcll(b));
+  const uint64_t bb = __ballot(is_bridge);
+  if (__lane_id() == 0 && bb) atomicAdd((unsigned long long*)count, (unsigned long long)__popcll(bb));
 }
 
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
@@ -500,12 +635,11 @@ int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, i
   int32_t* vpslot = sc.get<int32_t>(n);
   int32_t* vuslot = sc.get<int32_t>(n);
   int32_t* pre = sc.get<int32_t>(n);
+  int4* byp = sc.get<int4>(n);
   int32_t* amin = sc.get<int32_t>(n);
   int32_t* amax = sc.get<int32_t>(n);
-  int32_t* pmin = sc.get<int32_t>(n);
-  int32_t* smin = sc.get<int32_t>(n);
-  int32_t* pmax = sc.get<int32_t>(n);
-  int32_t* smax = sc.get<int32_t>(n);
+  uint32_t* mmin = sc.get<uint32_t>(n);
+  uint32_t* mmax = sc.get<uint32_t>(n);
   const int32_t nb = (n + 31) >> kRmqLog;
   int levels = 1;
   while ((1 << levels) <= nb) ++levels;
@@ -527,8 +661,21 @@ int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, i
   hipLaunchKernelGGL(k_fill_i32, dim3(std::min(ceil_div(words, kB), 4096)), dim3(kB), 0, s,
                      reinterpret_cast<int32_t*>(tbits), (int64_t)words, 0);
   {
-    ET_PROF(c, s, "k_hook");
-    hipLaunchKernelGGL(k_hook, dim3(grows), dim3(kB), 0, s, row_ptr, col, n, nnz, cc, tbits, c->d_status);
+    ET_PROF(c, s, "k_hook_sample");
+    hipLaunchKernelGGL(k_hook_sample, dim3(gn), dim3(kB), 0, s, row_ptr, col, n, nnz, cc, tbits, c->d_status);
+  }
+  {
+    ET_PROF(c, s, "k_cc_compress");
+    hipLaunchKernelGGL(k_cc_compress, dim3(gn), dim3(kB), 0, s, cc, n);
+  }
+  {
+    ET_PROF(c, s, "k_big_component");
+    hipLaunchKernelGGL(k_big_component, dim3(1), dim3(kBigSample), 0, s, cc, n, scal + 4);
+  }
+  {
+    ET_PROF(c, s, "k_hook_rest");
+    hipLaunchKernelGGL(k_hook_rest, dim3(grows), dim3(kB), 0, s, row_ptr, col, n, nnz, cc, scal + 4, tbits,
+                       c->d_status);
   }
   // 2. forest CSR, twins, successors, component chaining
   {
@@ -583,17 +730,18 @@ int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, i
   if (rc) return rc;
   {
     ET_PROF(c, s, "k_preorder");
-    hipLaunchKernelGGL(k_preorder, dim3(gn), dim3(kB), 0, s, vR, vpslot, dw, n, Lcap, pre);
+    hipLaunchKernelGGL(k_preorder, dim3(gn), dim3(kB), 0, s, vR, vsize, vpslot, vuslot, dw, n, Lcap, pre, byp);
   }
   // 4. non-forest extremes by preorder
   {
     ET_PROF(c, s, "k_minmax");
-    hipLaunchKernelGGL(k_minmax, dim3(grows), dim3(kB), 0, s, row_ptr, col, tbits, pre, n, nnz, amin, amax);
+    hipLaunchKernelGGL(k_minmax, dim3(ceil_div((int64_t)n * kRowLanes, kB)), dim3(kB), 0, s, row_ptr, col, tbits, pre,
+                       n, nnz, amin, amax);
   }
   // 5. range extremes
   {
     ET_PROF(c, s, "k_rmq_blocks");
-    hipLaunchKernelGGL(k_rmq_blocks, dim3(gn), dim3(kB), 0, s, amin, amax, n, pmin, smin, pmax, smax, stmin, stmax);
+    hipLaunchKernelGGL(k_rmq_blocks, dim3(gn), dim3(kB), 0, s, amin, amax, n, mmin, mmax, stmin, stmax);
   }
   for (int k = 1; k < levels; ++k) {
     ET_PROF(c, s, "k_sparse_level");
@@ -602,10 +750,10 @@ int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, i
                        stmax + (size_t)k * nb);
   }
   // 6. test
-  Rmq q{amin, amax, pmin, smin, pmax, smax, stmin, stmax, nb};
+  Rmq q{amin, amax, mmin, mmax, stmin, stmax, nb};
   {
     ET_PROF(c, s, "k_bridge_test");
-    hipLaunchKernelGGL(k_bridge_test, dim3(gn), dim3(kB), 0, s, pre, vsize, vpslot, vuslot, n, q, mask, c->d_bcount);
+    hipLaunchKernelGGL(k_bridge_test, dim3(gn), dim3(kB), 0, s, byp, dw, Lcap, n, q, mask, c->d_bcount);
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }

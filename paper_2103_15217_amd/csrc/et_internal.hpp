@@ -34,8 +34,17 @@ struct ProfRec {
   hipEvent_t a, b;
 };
 
+// Launch shape of the sublist list ranking (tunable per context).
+struct LrShape {
+  int k1_log2 = 4;       // level 1: one splitter per 2^k1 consecutive ids
+  int per_wave1 = 256;   // level 1: sublists owned by one wavefront
+  int kn_log2 = 3;       // upper levels: one splitter per 2^kn elements
+  int per_waven = 128;   // upper levels: sublists per wavefront
+};
+
 struct Ctx {
   int device = 0;
+  LrShape lr;
   // kernel timing: when enabled, every instrumented launch is bracketed by
   // a pair of events on its stream
   bool profiling = false;

@@ -375,7 +375,7 @@ int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const 
                    hipStream_t s, bool empty_head_ok) {
   const int32_t L = len, H = nheads;
   // level-1 splitter spacing: K = 16 (a sublist averages 16 elements)
-  const int ks1 = (L >= (1 << 12)) ? 4 : 2;
+  const int ks1 = (L >= (1 << 12)) ? c->lr.k1_log2 : 2;
   const int32_t S1 = (int32_t)(((int64_t)L + (1 << ks1) - 1) >> ks1);
   const int32_t cont_max = L / kCap + H + 64;
   const int32_t T1 = S1 + H + cont_max;
@@ -387,7 +387,7 @@ int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const 
   hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, ctr + 1, 0);
   hipLaunchKernelGGL(k_fill_int4, dim3(ceil_div(cont_max, 256)), dim3(256), 0, s, rec1, S1 + H, T1,
                      make_int4(-3, 0, 0, 0));
-  const int32_t per_wave1 = 256;
+  const int32_t per_wave1 = c->lr.per_wave1;
   if (tree_weights) {
     ET_PROF(c, s, "k_walk1<true>");
     hipLaunchKernelGGL(k_walk1<true>, dim3(walk_grid(S1 + H, per_wave1)), dim3(kWalkThreads), 0, s, succ, L,
@@ -412,14 +412,14 @@ int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const 
   for (;;) {
     Lvl& cur = lv.back();
     if (cur.T <= kLdsMax) break;
-    const int ks = 3;  // K = 8
-    const int32_t S = (int32_t)(((int64_t)cur.T + 7) >> ks);
+    const int ks = c->lr.kn_log2;
+    const int32_t S = (int32_t)(((int64_t)cur.T + (1 << ks) - 1) >> ks);
     const int32_t Tn = S + H;
     if ((int64_t)Tn * 2 > cur.T) break;  // many heads: shrinking stalls
     int4* el = sc.get<int4>((size_t)cur.T);
     int4* rec = sc.get<int4>((size_t)Tn);
     if (sc.failed) return ET_ENOMEM;
-    const int32_t per_wave = 128;
+    const int32_t per_wave = c->lr.per_waven;
     {
       ET_PROF(c, s, "k_walkN");
       hipLaunchKernelGGL(k_walkN, dim3(walk_grid(Tn, per_wave)), dim3(kWalkThreads), 0, s, cur.rec, cur.T,

@@ -15,7 +15,9 @@
 //   downsweep  each wavefront ranks its 16 rounds of 64 keys stably: 8
 //              ballots find the lanes that share a digit, the lowest such
 //              lane bumps the wavefront's LDS counter for that digit, and
-//              the four wavefront counters are chained per digit.
+//              the four wavefront counters are chained per digit. The tile
+//              is then sorted by digit in LDS and written out run by run,
+//              so consecutive lanes store to consecutive addresses.
 //
 // The first pass reads the parent array directly (the root's -1 becomes the
 // all-ones key and sorts last), validates it, finds the root, and writes
@@ -82,12 +84,16 @@ __global__ __launch_bounds__(kThreads) void k_downsweep(const void* __restrict__
                                                         uint32_t* __restrict__ keys_out,
                                                         int32_t* __restrict__ vals_out) {
   __shared__ uint32_t cnt[kWaves][256];
-  __shared__ uint32_t base_off[kWaves][256];
+  __shared__ uint32_t lstart[256];   // tile-local start of each digit's run
+  __shared__ uint32_t gstart[256];   // global start of this tile's run of each digit
+  __shared__ uint32_t skey[kTile];
+  __shared__ int32_t sval[kTile];
   const int wave = threadIdx.x >> 6;
   const uint32_t mask = (1u << nbits) - 1u;
   for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&cnt[0][0])[i] = 0;
   __syncthreads();
-  const int64_t wbase = (int64_t)blockIdx.x * kTile + (int64_t)wave * (64 * kRounds) + __lane_id();
+  const int64_t tbase = (int64_t)blockIdx.x * kTile;
+  const int64_t wbase = tbase + (int64_t)wave * (64 * kRounds) + __lane_id();
   const uint64_t below = lanemask_lt();
   uint32_t key[kRounds];
   int32_t val[kRounds];
@@ -116,23 +122,59 @@ __global__ __launch_bounds__(kThreads) void k_downsweep(const void* __restrict__
     if (valid && lower == 0) cnt[wave][dg] = c0 + (uint32_t)__popcll(peers);
   }
   __syncthreads();
-  for (int d = threadIdx.x; d <= (int)mask; d += kThreads) {
-    uint32_t run = offsets[(int64_t)d * ntiles + blockIdx.x];
+  // per digit: chain the wave counters, then an exclusive scan over digits
+  // gives each digit's run inside the tile
+  {
+    const int d = threadIdx.x;  // kThreads == 256 digits
+    uint32_t tot = 0;
+    if (d <= (int)mask) {
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-      base_off[w][d] = run;
-      run += cnt[w][d];
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t c = cnt[w][d];
+        cnt[w][d] = tot;  // exclusive prefix over the waves
+        tot += c;
+      }
+      gstart[d] = offsets[(int64_t)d * ntiles + blockIdx.x];
     }
+    // block exclusive scan of tot over the 256 digits (4 waves)
+    uint32_t inc = tot;
+    const int lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t u = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += u;
+    }
+    __shared__ uint32_t wsum[kWaves];
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    lstart[d] = before + inc - tot;
   }
   __syncthreads();
+  // place every key at its tile-local sorted position
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const int64_t idx = wbase + r * 64;
     if (idx < n) {
       const uint32_t dg = (key[r] >> shift) & mask;
-      const uint32_t pos = base_off[wave][dg] + rnk[r];
-      keys_out[pos] = key[r];
-      vals_out[pos] = val[r];
+      const uint32_t lp = lstart[dg] + cnt[wave][dg] + rnk[r];
+      skey[lp] = key[r];
+      sval[lp] = val[r];
+    }
+  }
+  __syncthreads();
+  // write the tile out digit run by digit run: consecutive lanes, consecutive addresses
+  const int valid_in_tile = (int)min<int64_t>((int64_t)kTile, n - tbase);
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int i = r * kThreads + threadIdx.x;
+    if (i < valid_in_tile) {
+      const uint32_t k = skey[i];
+      const uint32_t dg = (k >> shift) & mask;
+      const uint32_t pos = gstart[dg] + (uint32_t)i - lstart[dg];
+      keys_out[pos] = k;
+      vals_out[pos] = sval[i];
     }
   }
 }

@@ -16,13 +16,13 @@
 //      trailing zeros, in closed form (j >> k) << k with j = pre + size and
 //      k the highest bit in which pre and j differ.
 //   5. k_head: a node is the top of its inlabel path iff it is the root or
-//      its parent's inlabel differs; head[inlabel] = {parent, depth - 1}.
-//      Each path top c puts 2^h(inlabel c) on both of its half-edges in tour
-//      order (every other half-edge gets 0).
-//   6. an xor array scan over the tour (the paper's one-ranking-then-scans
-//      optimisation, Section 2.2): at rank(2v) the prefix xor holds the bits
-//      of exactly the path tops above or at v, whose levels are distinct, so
-//      xor = or = ascendant(v) without the root's bit (added by k_asc).
+//      its parent's inlabel differs; head[inlabel] = {parent, depth - 1},
+//      and the label of the parent's path is recorded per label.
+//   6. ascendant(v) (the OR of 2^h over the labels of v's ancestors) only
+//      depends on v's path: it is the ascendant of the path above plus the
+//      path's own level bit. Labels on a root path have strictly decreasing
+//      levels, so one pass per level, from the highest down, fills a table
+//      by label; k_asc copies it into the node records.
 #include "et_internal.hpp"
 
 namespace et {
@@ -68,7 +68,7 @@ __device__ __forceinline__ uint32_t inlabel_of(int32_t pre, int32_t size) {
 __global__ void k_node(const uint64_t* __restrict__ packed, const int2* __restrict__ off, int32_t nsub,
                        int32_t n, const int32_t* __restrict__ sc, int32_t* __restrict__ rank,
                        int32_t* __restrict__ pre_out, int32_t* __restrict__ size_out, int4* __restrict__ rec,
-                       uint32_t* __restrict__ status) {
+                       uint32_t* __restrict__ inl_out, uint32_t* __restrict__ status) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   const int32_t root = sc[SC_ROOT];
@@ -94,13 +94,17 @@ __global__ void k_node(const uint64_t* __restrict__ packed, const int2* __restri
   reinterpret_cast<int2*>(rank)[c] = make_int2(r0, r1);
   pre_out[c] = pre;
   size_out[c] = size;
-  rec[c] = make_int4((int32_t)inlabel_of(pre, size), 0, depth, pre);
+  const uint32_t inl = inlabel_of(pre, size);
+  rec[c] = make_int4((int32_t)inl, 0, depth, pre);
+  inl_out[c] = inl;
 }
 
+// Path tops: a node is the top of its inlabel path iff it is the root or its
+// parent's inlabel differs. head[I] = {parent of the top, its depth}, and
+// plab[I] = the inlabel of that parent (0 for the root's path).
 __global__ void k_head(const int32_t* __restrict__ parent, const int4* __restrict__ rec,
-                       const int32_t* __restrict__ rank, int32_t n, const int32_t* __restrict__ sc,
-                       int2* __restrict__ head, uint32_t* __restrict__ xw, int32_t L,
-                       uint32_t* __restrict__ status) {
+                       const uint32_t* __restrict__ inl_of, int32_t n, const int32_t* __restrict__ sc,
+                       int2* __restrict__ head, uint32_t* __restrict__ plab, uint32_t* __restrict__ status) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int32_t root = sc[SC_ROOT];
@@ -108,47 +112,60 @@ __global__ void k_head(const int32_t* __restrict__ parent, const int4* __restric
   const uint32_t inl = (uint32_t)rv.x;
   const int32_t p = parent[v];
   bool top;
+  uint32_t pinl = 0;
   if (v == root) {
     top = true;
   } else if ((uint32_t)p < (uint32_t)n) {
-    top = (uint32_t)rec[p].x != inl;
+    pinl = inl_of[p];
+    top = pinl != inl;
   } else {
     top = true;
     flag(status, ST_BAD_INDEX);
   }
   if (top) {
-    if (inl >= 1u && inl <= (uint32_t)n) head[inl] = make_int2(v == root ? -1 : p, rv.z - 1);
-    else flag(status, ST_BAD_INDEX);
-  }
-  if (v != root) {
-    const uint32_t w = (top && inl) ? (1u << ctz32(inl)) : 0u;
-    const int2 r = reinterpret_cast<const int2*>(rank)[v];
-    if ((uint32_t)r.x < (uint32_t)L && (uint32_t)r.y < (uint32_t)L) {
-      xw[r.x] = w;
-      xw[r.y] = w;
+    if (inl >= 1u && inl <= (uint32_t)n) {
+      head[inl] = make_int2(v == root ? -1 : p, rv.z - 1);
+      plab[inl] = (v == root) ? 0u : pinl;
     } else {
       flag(status, ST_BAD_INDEX);
     }
   }
 }
 
-__global__ void k_asc(int4* __restrict__ rec, const int32_t* __restrict__ rank, const uint32_t* __restrict__ X,
-                      int32_t n, int32_t L, const int32_t* __restrict__ sc, uint32_t* __restrict__ status) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const int32_t root = sc[SC_ROOT];
-  uint32_t rootbit = 1u;
-  if ((uint32_t)root < (uint32_t)n) {
-    const uint32_t ri = (uint32_t)rec[root].x;
-    rootbit = ri ? (1u << ctz32(ri)) : 1u;
-  }
-  uint32_t asc = rootbit;
-  if (v != root) {
-    const int32_t r0 = rank[2 * v];
-    if ((uint32_t)r0 < (uint32_t)L) asc ^= X[r0];
+// Ascendant of a path label I at level t = h(I): the ascendant of the path
+// it hangs from (a label of a strictly higher level, already done) plus bit
+// t. plab[] holds the parent path's label on entry and the ascendant on
+// exit; unused labels keep kUnused.
+constexpr uint32_t kUnused = 0xffffffffu;
+
+__global__ void k_asc_level(uint32_t* __restrict__ plab, int32_t n, int t, uint32_t* __restrict__ status) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t I = ((2 * k + 1) << t);
+  if (I > n) return;
+  const uint32_t pl = plab[I];
+  if (pl == kUnused) return;
+  uint32_t up = 0;
+  if (pl != 0) {
+    if (pl <= (uint32_t)n && ctz32(pl) > t) up = plab[pl];
     else flag(status, ST_BAD_INDEX);
   }
-  reinterpret_cast<int32_t*>(rec)[4 * v + 1] = (int32_t)asc;
+  plab[I] = up | (1u << t);
+}
+
+__global__ void k_asc(int4* __restrict__ rec, const uint32_t* __restrict__ asc_of_label, int32_t n,
+                      uint32_t* __restrict__ status) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint32_t inl = (uint32_t)rec[v].x;
+  uint32_t a = 0;
+  if (inl >= 1u && inl <= (uint32_t)n) a = asc_of_label[inl];
+  else flag(status, ST_BAD_INDEX);
+  reinterpret_cast<int32_t*>(rec)[4 * v + 1] = (int32_t)a;
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
 }
 
 // n == 1: the root is the only node
@@ -343,8 +360,7 @@ int tree_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
                        t->d_rec, t->d_head, c->d_status);
     return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
   }
-  const int32_t L2 = 2 * n;          // half-edge id space
-  const int32_t L = 2 * (n - 1);     // tour length
+  const int32_t L2 = 2 * n;          // half-edge id space (the tour uses 2(n-1) of them)
   Scratch scr(c);
   uint32_t* kv = scr.get<uint32_t>((size_t)L2);  // sorted parents | children, later the xor weights
   if (scr.failed) return ET_ENOMEM;
@@ -352,6 +368,8 @@ int tree_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
   int32_t* vals = reinterpret_cast<int32_t*>(kv + n);
   const int gn = ceil_div(n, kB);
   LRResult lr;
+  uint32_t* inl = scr.get<uint32_t>((size_t)n);  // inlabel of every node, compact for gathers
+  if (scr.failed) return ET_ENOMEM;
   int rc;
   {
     ET_PROF(c, s, "phase:tour");
@@ -366,21 +384,30 @@ int tree_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
     {
       ET_PROF(c, s, "k_node");
       hipLaunchKernelGGL(k_node, dim3(gn), dim3(kB), 0, s, lr.packed, lr.off, lr.nsub, n, sc, t->d_rank, t->d_pre,
-                         t->d_size, t->d_rec, c->d_status);
+                         t->d_size, t->d_rec, inl, c->d_status);
     }
   }
   ET_PROF(c, s, "phase:inlabel");
-  uint32_t* xw = kv;
+  uint32_t* plab = kv;  // n+1 label slots (the grouping keys are dead by now)
+  hipLaunchKernelGGL(k_fill_u32, dim3(std::min(ceil_div((int64_t)n + 1, kB), 8192)), dim3(kB), 0, s, plab,
+                     (int64_t)n + 1, kUnused);
   {
     ET_PROF(c, s, "k_head");
-    hipLaunchKernelGGL(k_head, dim3(gn), dim3(kB), 0, s, parent, t->d_rec, t->d_rank, n, sc, t->d_head, xw, L,
+    hipLaunchKernelGGL(k_head, dim3(gn), dim3(kB), 0, s, parent, t->d_rec, inl, n, sc, t->d_head, plab,
                        c->d_status);
   }
-  rc = scan_u32(c, xw, xw, L, ScanOp::Xor, false, s);
-  if (rc) return rc;
+  {
+    ET_PROF(c, s, "k_asc_level");
+    int top = 0;
+    while ((2ll << top) <= n) ++top;  // highest level a label <= n can have
+    for (int lv = top; lv >= 0; --lv) {
+      const int64_t cand = ((int64_t)n >> lv) / 2 + 1;  // labels (2k+1) 2^lv <= n
+      hipLaunchKernelGGL(k_asc_level, dim3(ceil_div(cand, kB)), dim3(kB), 0, s, plab, n, lv, c->d_status);
+    }
+  }
   {
     ET_PROF(c, s, "k_asc");
-    hipLaunchKernelGGL(k_asc, dim3(gn), dim3(kB), 0, s, t->d_rec, t->d_rank, xw, n, L, sc, c->d_status);
+    hipLaunchKernelGGL(k_asc, dim3(gn), dim3(kB), 0, s, t->d_rec, plab, n, c->d_status);
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }

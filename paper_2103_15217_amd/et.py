@@ -30,6 +30,7 @@ _SIG = {
     "et_ctx_status": ([_P, _P], ctypes.c_int),
     "et_ctx_status_bits": ([_P, _P, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
     "et_ctx_profile": ([_P, ctypes.c_int], ctypes.c_int),
+    "et_ctx_set_param": ([_P, ctypes.c_char_p, _i64], ctypes.c_int),
     "et_ctx_profile_read": ([_P, _P, ctypes.c_char_p, _i32], ctypes.c_int),
     "et_list_rank": ([_P, _P, _i32, _P, _i32, _P, _P], ctypes.c_int),
     "et_tree_build": ([_P, _P, _i32, _P, ctypes.POINTER(_P)], ctypes.c_int),
@@ -114,6 +115,10 @@ class Context:
         if bits:
             names = [v for k, v in STATUS_BITS.items() if bits & k]
             raise EtError(ET_EINPUT, "device status: " + ", ".join(names))
+
+    def set_param(self, name, value):
+        """Set a tunable launch parameter (see et_ctx_set_param in et.h)."""
+        _check(_lib.et_ctx_set_param(self._h, name.encode(), int(value)), f"et_ctx_set_param({name})")
 
     def profile(self, enable=True):
         """Bracket every later kernel launch on this context with HIP events."""
