@@ -53,20 +53,17 @@ __device__ __forceinline__ void st(int32_t* p, int32_t v) {
 }
 
 // Union-find over cc[]: roots satisfy cc[r] == r. A link always hangs the
-// root with the larger key under the one with the smaller key, where the
-// key is the vertex id except that the designated big component's root
-// (if any) counts as smallest; keys therefore strictly decrease towards the
+// root with the larger key under the node with the smaller key, where the
+// key is the vertex id except that the designated big component's root (if
+// any) counts as smallest; keys therefore strictly decrease towards the
 // root, so the forest stays acyclic under concurrent links, and every
 // successful compare-and-swap joins two different trees: its edge is a
 // spanning-forest edge.
 //
-// Finds use ordinary cached loads, which may return an out-of-date parent
-// (each XCD has its own L2); an out-of-date view is still a chain of
-// ancestors. Only the device-scope compare-and-swap decides a link: if the
-// node it targets is no longer a root it fails and returns the node's
-// current parent, and the hook continues from there, so every failure moves
-// strictly up. Two nodes of one tree can never be linked: the one with the
-// larger key is never that tree's root, and the swap is always on it.
+// Loads are ordinary cached loads, which may return an out-of-date parent
+// (each XCD has its own L2); an out-of-date parent is still an ancestor.
+// Only the device-scope compare-and-swap decides a link, and when it fails
+// it returns the node's current parent, from which the link continues.
 __device__ __forceinline__ int32_t ldc(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -88,17 +85,28 @@ __device__ int32_t cc_find(int32_t* cc, int32_t x) {
 
 __device__ __forceinline__ int64_t cc_key(int32_t v, int32_t big) { return v == big ? -1 : (int64_t)v; }
 
-// true iff this call linked the trees of u and w (its edge joins the forest)
+// Climbing link of the trees of u and w: keep one ancestor of each, and at
+// every step try to hang the one with the larger key (if it is a root)
+// under the other, else move it up to its grandparent and the other one up
+// to its parent. A node of one tree is never hung under a node of the same
+// tree: the larger key of two such nodes is never that tree's root. Every
+// step moves the larger-key side strictly up, so the loop ends.
+// Returns true iff this call linked two trees (edge {u, w} joins the forest).
 __device__ bool cc_hook(int32_t* cc, int32_t u, int32_t w, int32_t big, bool* over) {
-  int32_t ru = cc_find(cc, u), rw = cc_find(cc, w);
+  int32_t p1 = ldc(cc + u), p2 = ldc(cc + w);
   for (int it = 0; it < (1 << 22); ++it) {
-    if (ru == rw) return false;
-    const bool u_up = cc_key(ru, big) > cc_key(rw, big);
-    const int32_t hi = u_up ? ru : rw, lo = u_up ? rw : ru;
-    const int32_t old = atomicCAS(cc + hi, hi, lo);
-    if (old == hi) return true;
-    if (u_up) ru = cc_find(cc, old);
-    else rw = cc_find(cc, old);
+    if (p1 == p2) return false;
+    const bool up1 = cc_key(p1, big) > cc_key(p2, big);
+    const int32_t hi = up1 ? p1 : p2, lo = up1 ? p2 : p1;
+    int32_t ph = ldc(cc + hi);
+    if (ph == lo) return false;
+    if (ph == hi) {
+      const int32_t old = atomicCAS(cc + hi, hi, lo);
+      if (old == hi) return true;
+      ph = old;  // linked meanwhile: continue from its current parent
+    }
+    p1 = ldc(cc + ph);
+    p2 = ldc(cc + lo);
   }
   *over = true;
   return false;
@@ -145,24 +153,26 @@ __device__ __forceinline__ int row_of(const int32_t* rp_lds, int cnt, int32_t k)
   return lo;
 }
 
-// Sampling phase: every vertex hooks its first kSample distinct neighbours.
+// Sampling phase: in round j every vertex hooks its j-th distinct neighbour
+// (rounds 0 .. kSample-1, each followed by a full path compression).
 constexpr int kSample = 2;
 
 __global__ void k_hook_sample(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, int32_t n,
-                              int32_t nnz, int32_t* cc, uint32_t* __restrict__ tbits, uint32_t* __restrict__ status) {
+                              int32_t nnz, int32_t* cc, uint32_t* __restrict__ tbits, uint32_t* __restrict__ status,
+                              int jsel) {
   const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= n) return;
   const int32_t a = clampi(row_ptr[u], 0, nnz), b = clampi(row_ptr[u + 1], a, nnz);
   bool bad = false, over = false;
   int taken = 0;
-  for (int32_t k = a; k < b && taken < kSample; ++k) {
+  for (int32_t k = a; k < b && taken <= jsel; ++k) {
     const int32_t w = col[k];
     if ((uint32_t)w >= (uint32_t)n) {
       bad = true;
       continue;
     }
     if (w == u || (k > a && col[k - 1] == w)) continue;  // self-loop or a parallel copy
-    ++taken;
+    if (taken++ != jsel) continue;
     if (cc_hook(cc, (int32_t)u, w, -1, &over)) mark_forest(row_ptr, col, nnz, tbits, k, (int32_t)u, w, &bad);
   }
   if (bad) flag(status, ST_BAD_CSR);
@@ -660,13 +670,15 @@ int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, i
   hipLaunchKernelGGL(k_iota, dim3(gn), dim3(kB), 0, s, cc, n);
   hipLaunchKernelGGL(k_fill_i32, dim3(std::min(ceil_div(words, kB), 4096)), dim3(kB), 0, s,
                      reinterpret_cast<int32_t*>(tbits), (int64_t)words, 0);
-  {
-    ET_PROF(c, s, "k_hook_sample");
-    hipLaunchKernelGGL(k_hook_sample, dim3(gn), dim3(kB), 0, s, row_ptr, col, n, nnz, cc, tbits, c->d_status);
-  }
-  {
-    ET_PROF(c, s, "k_cc_compress");
-    hipLaunchKernelGGL(k_cc_compress, dim3(gn), dim3(kB), 0, s, cc, n);
+  for (int j = 0; j < kSample; ++j) {
+    {
+      ET_PROF(c, s, "k_hook_sample");
+      hipLaunchKernelGGL(k_hook_sample, dim3(gn), dim3(kB), 0, s, row_ptr, col, n, nnz, cc, tbits, c->d_status, j);
+    }
+    {
+      ET_PROF(c, s, "k_cc_compress");
+      hipLaunchKernelGGL(k_cc_compress, dim3(gn), dim3(kB), 0, s, cc, n);
+    }
   }
   {
     ET_PROF(c, s, "k_big_component");
