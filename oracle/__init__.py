@@ -25,13 +25,8 @@ def build():
     os.replace(tmp, _LIB)
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build()
-    lib = ctypes.CDLL(_LIB)
+def _bind(path):
+    lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     i32, i64 = ctypes.c_int32, ctypes.c_int64
     sig = {
@@ -46,8 +41,26 @@ def _load():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
-    _lib = lib
     return lib
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    _lib = _bind(_LIB)
+    return _lib
+
+
+def use_library(path):
+    """Point this module at another build of the oracle source (used by the
+    tests that plant mistakes in a copy of it); returns the previous one."""
+    global _lib
+    prev = _lib
+    _lib = _bind(path) if isinstance(path, str) else path
+    return prev
 
 
 class OracleInputError(ValueError):

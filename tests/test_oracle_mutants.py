@@ -1,0 +1,107 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case plants one mistake in a copy of the oracle source (on the CPU),
+builds it with gcc, points the oracle wrapper at the mutant and runs the pin
+battery of test_oracle_pins.py; at least one pin must fail. The committed
+oracle itself is untouched.
+"""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "et_oracle.c")
+
+MUTANTS = {
+    # children visited in descending id order
+    "child_order": ("for (int32_t v = 0; v < n; ++v)\n        if (parent[v] >= 0) cidx[fill[parent[v]]++] = v;",
+                    "for (int32_t v = n - 1; v >= 0; --v)\n        if (parent[v] >= 0) cidx[fill[parent[v]]++] = v;"),
+    # preorder numbered from 1
+    "pre_base": ("int32_t visited = 0;    /* next preorder number */",
+                 "int32_t visited = 1;    /* next preorder number */"),
+    # subtree size without the node itself
+    "size_self": ("int32_t s = 1;\n            for (int32_t k = cptr[u]",
+                  "int32_t s = 0;\n            for (int32_t k = cptr[u]"),
+    # depth not incremented
+    "depth": ("d[c] = d[u] + 1;", "d[c] = d[u];"),
+    # ranks reported off by one
+    "rank_origin": ("if (rank) rank[2 * c] = (int32_t)pos;", "if (rank) rank[2 * c] = (int32_t)pos + 1;"),
+    # offline LCA unites in the wrong direction (the parent's set under the child's)
+    "lca_union": ("up[a] = b;\n            anc[b] = p;", "up[b] = a;\n            anc[b] = p;"),
+    # climbing LCA reports the meeting point's parent
+    "lca_climb": ("while (x != y) { x = parent[x]; y = parent[y]; }\n        out[i] = x;",
+                  "while (x != y) { x = parent[x]; y = parent[y]; }\n        out[i] = parent[x] >= 0 ? parent[x] : x;"),
+    # offline LCA answers a query when the other end is not finished yet
+    "lca_done": ("if (done[other]) out[i] = anc[dsu_find(up, other)];",
+                 "if (!done[other]) out[i] = anc[dsu_find(up, other)];"),
+    # inlabel = the interval's largest member instead of the most trailing zeros
+    "inlabel": ("for (int t = 31; t >= 0 && !best; --t) {", "for (int t = 0; t >= 0 && !best; --t) {"),
+    # ascendant without the node's own level
+    "asc_own": ("asc[v] = (parent[v] < 0) ? own : (asc[parent[v]] | own);",
+                "asc[v] = (parent[v] < 0) ? own : asc[parent[v]];"),
+    # head table stores the top's depth instead of its parent's
+    "head_depth": ("head_depth[inlabel[v]] = depth[v] - 1;", "head_depth[inlabel[v]] = depth[v];"),
+    # every copy of the parent edge skipped (parallel edges then look like bridges)
+    "bridge_multi": ("if (w == par[u] && back_slot[u] == -1) { back_slot[u] = k; continue; }",
+                     "if (w == par[u]) { back_slot[u] = k; continue; }"),
+    # non-strict bridge comparison
+    "bridge_cmp": ("if (low[u] > disc[p]) {", "if (low[u] >= disc[p]) {"),
+    # list ranks start at 1
+    "list_rank_origin": ("int32_t r = 0;\n        while (e != -1) {", "int32_t r = 1;\n        while (e != -1) {"),
+}
+
+
+def battery(mod):
+    """Run the pins against the current oracle library; return the first failure."""
+    checks = [
+        lambda: pins.test_fig1_tour_from_oracle(mod),
+        *[lambda s=s: pins.test_paper_dcel_tour_equals_oracle_when_parents_precede_children(mod, s)
+          for s in range(8)],
+        *[lambda s=s: pins.test_tree_stats_match_definitions(mod, s) for s in range(40)],
+        lambda: pins.test_tour_invariants(mod, 2000, None, 2),
+        lambda: pins.test_tour_matches_networkx_dfs(mod, 0),
+        *[lambda s=s: pins.test_list_rank_vs_pointer_jumping(mod, s) for s in range(4)],
+        *[lambda s=s: pins.test_lca_bruteforce_all_pairs(mod, s) for s in range(12)],
+        lambda: pins.test_lca_closed_forms(mod),
+        *[lambda s=s: pins.test_sv_tables_and_query(mod, s) for s in range(20)],
+        *[lambda s=s: pins.test_bridges_bruteforce_multigraphs(mod, s) for s in range(40)],
+        lambda: pins.test_bridges_special_graphs(mod),
+    ]
+    for chk in checks:
+        try:
+            chk()
+        except (AssertionError, oracle.OracleInputError, RuntimeError, IndexError, ValueError) as e:
+            return e
+    return None
+
+
+@pytest.fixture(scope="module")
+def builddir(tmp_path_factory):
+    return tmp_path_factory.mktemp("mutants")
+
+
+def test_unmodified_oracle_passes_battery(oracle_mod):
+    assert battery(oracle_mod) is None
+
+
+@pytest.mark.timeout(120)
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(oracle_mod, builddir, name):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site of {name} not found exactly once"
+    path_c = os.path.join(builddir, f"{name}.c")
+    path_so = os.path.join(builddir, f"{name}.so")
+    with open(path_c, "w") as f:
+        f.write(src.replace(old, new))
+    subprocess.check_call(["gcc", "-O1", "-std=c99", "-shared", "-fPIC", path_c, "-o", path_so])
+    prev = oracle.use_library(path_so)
+    try:
+        failure = battery(oracle)
+    finally:
+        oracle.use_library(prev)
+    assert failure is not None, f"planted mistake '{name}' passed every pin"
