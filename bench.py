@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-tree batched vs plain comparison")
     ap.add_argument("--batch-trees", type=int, default=4096)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served vs plain trace replay")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--no-kernel-times", action="store_true",
                     help="do not bracket kernels with events during the timed steps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -245,6 +248,9 @@ def main():
     if not args.no_batch:
         log("batched forest: generating")
         result["components"]["batched"] = batched_vs_plain(args, et, ctx, d, dev)
+    if not args.no_serve:
+        log("serving: generating the job pool")
+        result["components"]["serving"] = serving(args, dev)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on the sample")
         result["cpu_baseline"], result["parity"] = cpu_baseline(trees[0], qx, qy, rp, col, ginfo, et, d, ctx,
@@ -295,6 +301,18 @@ def batched_vs_plain(args, et, ctx, d, dev):
         e1.record(stream)
         torch.cuda.synchronize()
         res[name] = {"gpu_ms": e0.elapsed_time(e1) / reps, "wall_ms": (time.perf_counter() - w0) * 1e3 / reps}
+    g = et.BatchGraph(d_parent, d_off, d_qt, d_qx, d_qy, ctx=ctx)
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    res["graph"] = {"gpu_ms": e0.elapsed_time(e1) / 5}
+    graph_ok = bool(torch.equal(g.out, d_out))
+    g.close()
     ctx.check()
     nodes, q = int(off[-1]), len(b["qx"])
     return {"trees": T, "nodes": nodes, "queries": q,
@@ -303,7 +321,27 @@ def batched_vs_plain(args, et, ctx, d, dev):
             "batched_nodes_per_s": nodes / (res["batched"]["gpu_ms"] * 1e-3),
             "plain_nodes_per_s": nodes / (res["plain"]["gpu_ms"] * 1e-3),
             "batched_queries_per_s": q / (res["batched"]["gpu_ms"] * 1e-3),
-            "speedup": res["plain"]["gpu_ms"] / res["batched"]["gpu_ms"]}
+            "speedup": res["plain"]["gpu_ms"] / res["batched"]["gpu_ms"],
+            "graph_ms": res["graph"]["gpu_ms"], "graph_matches_eager": graph_ok}
+
+
+def serving(args, dev):
+    """Open-loop Poisson trace (70 % LCA jobs on trees of 2^10..2^22 nodes,
+    half of them on a tree seen before; 30 % bridge jobs on graphs of
+    2^12..2^20 vertices, average degree 8..32) replayed in real time through
+    the plain FCFS per-job path and through the continuous-batching server."""
+    from paper_2103_15217_amd import serve
+    t0 = time.time()
+    pool = serve.make_pool(seed=args.seed)
+    dpool = serve.upload_pool(pool, dev)
+    jobs = serve.make_trace(pool, args.serve_rate, args.serve_seconds, seed=args.seed)
+    serve.upload_trace(jobs, dev)
+    log(f"serving: pool and {len(jobs)}-job trace ready in {time.time() - t0:.1f}s")
+    res = serve.compare(dpool, jobs)
+    res["rate_jobs_per_s"] = args.serve_rate
+    res["trace_seconds"] = args.serve_seconds
+    res["p99_ratio_served_over_plain"] = res["served"]["p99_ms"] / res["plain"]["p99_ms"]
+    return res
 
 
 def measured_traffic(kernel):

@@ -290,3 +290,39 @@ def et_bridges(row_ptr, col, mask=None, ctx=None, count=True):
     _check(_lib.et_bridges(ctx.handle, _ptr(row_ptr), _ptr(col), n, nnz, _ptr(mask),
                            ctypes.byref(c) if count else None, _stream()), "et_bridges")
     return mask, (int(c.value) if count else None)
+
+
+class BatchGraph:
+    """A batched build plus batched LCA queries captured once in a HIP graph
+    and replayed as one launch.
+
+    A warm-up call fills the context's scratch pool first, so the captured
+    calls allocate nothing; the captured tree stays alive with the graph
+    (its tables are what the replays write). Every library fill is a kernel,
+    so the graph holds no memset nodes. Inputs are read from the same
+    device buffers at every replay; results land in ``out``.
+    """
+
+    def __init__(self, parent, offsets, qtree, qx, qy, ctx=None):
+        self.ctx = ctx or default_context()
+        self.inputs = (parent, offsets, qtree, qx, qy)
+        warm = et_tree_build_batch(parent, offsets, ctx=self.ctx)
+        warm.lca_batch(qtree, qx, qy)
+        torch.cuda.synchronize()
+        warm.free()
+        self.out = torch.empty_like(qx)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.tree = et_tree_build_batch(parent, offsets, ctx=self.ctx)
+            self.tree.lca_batch(qtree, qx, qy, out=self.out)
+
+    def replay(self):
+        self.graph.replay()
+        return self.out
+
+    def close(self):
+        torch.cuda.synchronize()
+        self.graph = None
+        if self.tree is not None:
+            self.tree.free()
+            self.tree = None
