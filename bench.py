@@ -36,8 +36,11 @@ ALG_BYTES = {
     "k_walk1<false>": (8, "half-edge", lambda w: 2 * (w["graph_n"] - 1)),
     # LCA: 12 B streamed (x, y, out) + 4 gathers of 16-B records per query
     "k_lca": (76, "query", lambda w: w["q"]),
-    # CC hooking: read each CSR slot once (4 B) plus the row pointer per vertex
-    "k_hook": (4, "CSR slot", lambda w: w["graph_nnz"]),
+    # first hooking round: row pointers (8 B) and up to two columns (8 B) per vertex
+    "k_hook_sample": (16, "vertex", lambda w: w["graph_n"]),
+    # node statistics: the 8-B records of 2c and 2c+1 and their two 8-B sublist offsets
+    # read; rank pair (8 B), pre, size, inlabel (4 B each) and the 16-B node record written
+    "k_node": (68, "node", lambda w: w["n"]),
     # non-forest min/max: column (4 B) + gathered preorder (4 B) per slot
     "k_minmax": (8, "CSR slot", lambda w: w["graph_nnz"]),
     # radix passes: key + value read and written
