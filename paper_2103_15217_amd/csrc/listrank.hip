@@ -98,11 +98,34 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk1(
       continue;
     }
     if (cur >= 0) {
-      const int32_t nx = succ[cur];
-      if (TREE) d += ((cur & 1) == 0);
-      packed[cur] = (uint64_t)(uint32_t)sub | ((uint64_t)(uint32_t)j << 32) | ((uint64_t)(uint32_t)d << 48);
-      ++j;
-      ++steps;
+      int32_t nx;
+      bool pair = false;
+      if (TREE && (cur & 1) == 0) {
+        // A leaf's down half-edge 2c is followed by its own up half-edge
+        // 2c+1; both successors share one aligned 8-byte load and both
+        // records one 16-byte store, unless 2c+1 starts a sublist or the
+        // pair would reach the length cap.
+        const int2 sp = *reinterpret_cast<const int2*>(succ + cur);
+        nx = sp.x;
+        if (nx == cur + 1 && j + 2 < kCap && !is_splitter(cur + 1, ks, salt)) {
+          ++d;
+          const uint64_t lo = (uint64_t)(uint32_t)sub | ((uint64_t)(uint32_t)d << 48);
+          *reinterpret_cast<ulonglong2*>(packed + cur) =
+              make_ulonglong2(lo | ((uint64_t)(uint32_t)j << 32), lo | ((uint64_t)(uint32_t)(j + 1) << 32));
+          j += 2;
+          steps += 2;
+          nx = sp.y;
+          pair = true;
+        }
+      } else {
+        nx = succ[cur];
+      }
+      if (!pair) {
+        if (TREE) d += ((cur & 1) == 0);
+        packed[cur] = (uint64_t)(uint32_t)sub | ((uint64_t)(uint32_t)j << 32) | ((uint64_t)(uint32_t)d << 48);
+        ++j;
+        ++steps;
+      }
       bool stop = true;
       int32_t link = -1;
       if (nx == -1) {
