@@ -397,14 +397,15 @@ __global__ void k_rank_of(const uint64_t* __restrict__ packed, const int2* __res
 }
 
 // per forest half-edge: direction, parent edge and subtree size of the
-// child, and the scan weight in tour order
+// child, and the scan weight in tour order. Each vertex gets one record
+// vrec = {rank of its entering half-edge (or of its component's first
+// half-edge), subtree size, CSR slot of its parent edge at the parent,
+// slot of the same edge in its own row}; the two slots are -1 at a root.
 __global__ void k_direction(const int32_t* __restrict__ rank, const int32_t* __restrict__ ttwin,
                             const int32_t* __restrict__ tsrc, const int32_t* __restrict__ tnbr,
                             const int32_t* __restrict__ tslot, const uint32_t* __restrict__ tptr,
                             const int32_t* cc, int32_t n, int32_t Lcap, const int32_t* __restrict__ sc,
-                            uint32_t* __restrict__ dw, int32_t* __restrict__ vR, int32_t* __restrict__ vsize,
-                            int32_t* __restrict__ vpslot, int32_t* __restrict__ vuslot,
-                            uint32_t* __restrict__ status) {
+                            uint32_t* __restrict__ dw, int4* __restrict__ vrec, uint32_t* __restrict__ status) {
   const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t L = sc[0];
   if (h >= L) {
@@ -426,38 +427,29 @@ __global__ void k_direction(const int32_t* __restrict__ rank, const int32_t* __r
     return;
   }
   dw[r] = (uint32_t)down + (uint32_t)head;
-  if (down) {
-    vR[w] = r;
-    vsize[w] = (rt - r + 1) >> 1;
-    vpslot[w] = tslot[h];
-    vuslot[w] = tslot[t];
-  }
+  if (down) vrec[w] = make_int4(r, (rt - r + 1) >> 1, tslot[h], tslot[t]);
   if (head) {
     const int32_t tail = ttwin[clampi((int32_t)tptr[u + 1] - 1, 0, L - 1)];
-    vR[u] = r;
-    vsize[u] = ((rank[tail] - r + 1) >> 1) + 1;
-    vpslot[u] = -1;
-    vuslot[u] = -1;
+    vrec[u] = make_int4(r, ((rank[tail] - r + 1) >> 1) + 1, -1, -1);
   }
 }
 
 // preorder of every vertex (-1 if isolated), and the vertex's subtree size
 // and forest-edge slots stored by preorder for the bridge test
-__global__ void k_preorder(const int32_t* __restrict__ vR, const int32_t* __restrict__ vsize,
-                           const int32_t* __restrict__ vpslot, const int32_t* __restrict__ vuslot,
-                           const uint32_t* __restrict__ I, int32_t n, int32_t Lcap, int32_t* __restrict__ pre,
-                           int4* __restrict__ byp) {
+__global__ void k_preorder(const int4* __restrict__ vrec, const uint32_t* __restrict__ I, int32_t n, int32_t Lcap,
+                           int32_t* __restrict__ pre, int4* __restrict__ byp) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const int32_t r = vR[v];
+  const int4 vr = vrec[v];
+  const int32_t r = vr.x;
   if (r < 0 || r >= Lcap) {
     pre[v] = -1;
     return;
   }
-  const int32_t ps = vpslot[v];
+  const int32_t ps = vr.z;
   const int32_t p = (int32_t)I[r] - (ps < 0 ? 2 : 1);
   pre[v] = p;
-  if ((uint32_t)p < (uint32_t)n) byp[p] = make_int4(vsize[v], ps, vuslot[v], 0);
+  if ((uint32_t)p < (uint32_t)n) byp[p] = make_int4(vr.y, ps, vr.w, 0);
 }
 
 // per vertex: min / max preorder over itself and its non-forest neighbours,
@@ -640,10 +632,7 @@ int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, i
   uint32_t* rflag = sc.get<uint32_t>(n);
   uint32_t* rpos = sc.get<uint32_t>(n);
   int32_t* roots = sc.get<int32_t>(n);
-  int32_t* vR = sc.get<int32_t>(n);
-  int32_t* vsize = sc.get<int32_t>(n);
-  int32_t* vpslot = sc.get<int32_t>(n);
-  int32_t* vuslot = sc.get<int32_t>(n);
+  int4* vrec = sc.get<int4>(n);
   int32_t* pre = sc.get<int32_t>(n);
   int4* byp = sc.get<int4>(n);
   int32_t* amin = sc.get<int32_t>(n);
@@ -731,18 +720,18 @@ int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, i
     hipLaunchKernelGGL(k_rank_of, dim3(gl), dim3(kB), 0, s, lr.packed, lr.off, lr.nsub, Lcap, scal, rank,
                        c->d_status);
   }
-  hipLaunchKernelGGL(k_fill_i32, dim3(std::min(gn, 4096)), dim3(kB), 0, s, vR, (int64_t)n, -1);
-  hipLaunchKernelGGL(k_fill_i32, dim3(std::min(gn, 4096)), dim3(kB), 0, s, vpslot, (int64_t)n, -1);
+  hipLaunchKernelGGL(k_fill_i32, dim3(std::min(4 * (int64_t)gn, (int64_t)8192)), dim3(kB), 0, s,
+                     reinterpret_cast<int32_t*>(vrec), 4 * (int64_t)n, -1);
   {
     ET_PROF(c, s, "k_direction");
     hipLaunchKernelGGL(k_direction, dim3(gl), dim3(kB), 0, s, rank, ttwin, tsrc, tnbr, tslot, tptr, cc, n, Lcap, scal,
-                       dw, vR, vsize, vpslot, vuslot, c->d_status);
+                       dw, vrec, c->d_status);
   }
   rc = scan_u32(c, dw, dw, Lcap, ScanOp::Add, false, s);
   if (rc) return rc;
   {
     ET_PROF(c, s, "k_preorder");
-    hipLaunchKernelGGL(k_preorder, dim3(gn), dim3(kB), 0, s, vR, vsize, vpslot, vuslot, dw, n, Lcap, pre, byp);
+    hipLaunchKernelGGL(k_preorder, dim3(gn), dim3(kB), 0, s, vrec, dw, n, Lcap, pre, byp);
   }
   // 4. non-forest extremes by preorder
   {
