@@ -217,6 +217,11 @@ def main():
                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                         "alg_bytes_per_unit": bpu, "unit_name": unit, "units_per_launch": units_per_launch,
                         "avg_launch_ms": avg_ms, "launches_per_step": launches}
+            if traffic:
+                # what the memory system actually moves: every random access costs a whole line
+                rate = traffic / (avg_ms * 1e-3) / 1e9
+                roofline["traffic_GBps"] = rate
+                roofline["traffic_frac"] = rate / HBM_PEAK_GBS
         else:
             roofline = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": None, "traffic": traffic, "avg_launch_ms": avg_ms}

@@ -2,7 +2,9 @@
 
 Every HIP translation unit under ``csrc/`` is compiled to an object in a
 build folder next to this file and linked into ``libet.so`` in the package
-directory, where the Python binding loads it.
+directory, where the Python binding loads it. The random-access ceiling
+probe (``probe/ceiling.hip``, a standalone measurement program that does
+not use the library) is built next to its source.
 """
 import os
 import subprocess
@@ -13,6 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libet.so")
+PROBE_SRC = os.path.join(HERE, "probe", "ceiling.hip")
+PROBE = os.path.join(HERE, "probe", "ceiling")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 ARCH = os.environ.get("ET_OFFLOAD_ARCH", "gfx950")
 
@@ -58,6 +62,11 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError("link failed\n" + r.stderr)
     os.replace(tmp, LIB)
+    tmp = PROBE + ".tmp"
+    r = subprocess.run([HIPCC, *FLAGS, PROBE_SRC, "-o", tmp], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("probe build failed\n" + r.stderr)
+    os.replace(tmp, PROBE)
     return LIB
 
 
