@@ -196,7 +196,8 @@ int et_lca(const et_tree* tree, const int32_t* d_qx, const int32_t* d_qy, int64_
  *   d_row_ptr[n+1], d_col[nnz]  symmetric CSR: every edge {u, w} appears as
  *                  slot (u, w) in row u and slot (w, u) in row w; each row
  *                  sorted ascending; parallel edges repeat a column; a
- *                  self-loop {u, u} gives two (u, u) slots. nnz < 2^31.
+ *                  self-loop {u, u} gives two (u, u) slots. n < 2^30,
+ *                  nnz < 2^31.
  *   d_mask[ceil(nnz/32)]  output: bit k (word k/32, bit k%32) is set iff
  *                  slot k belongs to a bridge (both slots of a bridge set)
  *   h_count        optional host output: number of bridges. When non-NULL

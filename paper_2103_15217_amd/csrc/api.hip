@@ -324,7 +324,7 @@ int et_lca(const et_tree* tree, const int32_t* d_qx, const int32_t* d_qy, int64_
 
 int et_bridges(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col, int32_t n, int32_t nnz,
                uint32_t* d_mask, int64_t* h_count, hipStream_t s) {
-  if (!ctx || n < 0 || nnz < 0 || !d_row_ptr) return ET_EINVAL;
+  if (!ctx || n < 0 || n >= (1 << 30) || nnz < 0 || !d_row_ptr) return ET_EINVAL;  // 2(n-1) forest half-edges fit int32
   if (nnz > 0 && (!d_col || !d_mask)) return ET_EINVAL;
   Ctx* c = &ctx->impl;
   int rc = et::bridges_run(c, d_row_ptr, d_col, n, nnz, d_mask, s);

@@ -241,7 +241,9 @@ __global__ __launch_bounds__(kB) void k_hook_rest(const int32_t* __restrict__ ro
   __syncthreads();
   const int32_t kbeg = rp[0], kend = rp[cnt];
   bool bad = false, over = false;
-  for (int32_t k = kbeg + threadIdx.x; k < kend; k += kB) {
+  // 64-bit counter: kend may lie within one stride of 2^31
+  for (int64_t kk = (int64_t)kbeg + threadIdx.x; kk < kend; kk += kB) {
+    const int32_t k = (int32_t)kk;
     const int ri = row_of(rp, cnt, k);
     if (skip[ri]) continue;
     const int32_t u = r0 + ri;
@@ -468,7 +470,8 @@ __global__ __launch_bounds__(kB) void k_minmax(const int32_t* __restrict__ row_p
   if (p < 0 || p >= n) return;        // isolated vertex
   const int32_t a = clampi(row_ptr[u], 0, nnz), b = clampi(row_ptr[u + 1], a, nnz);
   int32_t mn = p, mx = p;
-  for (int32_t k = a + sub; k < b; k += kRowLanes) {
+  for (int64_t kk = (int64_t)a + sub; kk < b; kk += kRowLanes) {  // b may lie within one stride of 2^31
+    const int32_t k = (int32_t)kk;
     if ((tbits[k >> 5] >> (k & 31)) & 1u) continue;
     const int32_t w = col[k];
     if ((uint32_t)w >= (uint32_t)n) continue;

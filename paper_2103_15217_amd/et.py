@@ -187,9 +187,18 @@ class Tree:
         self.ctx = ctx
         self.batch = batch
 
-    def export(self):
+    def export(self, fields=None):
+        """Device tensors of the tree's tables; ``fields`` limits which are
+        copied out (default: all that the tree kind provides)."""
         n = self.n
         dev = torch.device("cuda", self.ctx.device)
+        if fields is not None:
+            sizes = {"succ": 2 * n, "rank": 2 * n, "depth": n, "pre": n, "size": n, "inlabel": n, "asc": n}
+            out = {k: torch.empty(sizes[k], dtype=torch.int32, device=dev) for k in fields}
+            _check(_lib.et_tree_export(self._h, *[_ptr(out[k]) if k in out else None for k in
+                                                  ("succ", "rank", "depth", "pre", "size", "inlabel", "asc")],
+                                       _stream()), "et_tree_export")
+            return out
         if self.batch:
             out = {k: torch.empty(n, dtype=torch.int32, device=dev) for k in ("depth", "pre", "size")}
             _check(_lib.et_tree_export(self._h, None, None, _ptr(out["depth"]), _ptr(out["pre"]),
