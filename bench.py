@@ -62,8 +62,13 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-tree batched vs plain comparison")
     ap.add_argument("--batch-trees", type=int, default=4096)
     ap.add_argument("--no-serve", action="store_true", help="skip the served vs plain trace replay")
+    ap.add_argument("--no-naive", action="store_true",
+                    help="skip the naive (climbing) LCA comparison and its depth and q:n sweeps")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--serve-sweep", default="1000,4000,8000",
+                    help="extra arrival rates (jobs/s) replayed for 2 s each to show where each path saturates; "
+                         "empty to skip")
     ap.add_argument("--no-kernel-times", action="store_true",
                     help="do not bracket kernels with events during the timed steps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -256,6 +261,9 @@ def main():
     if not args.no_batch:
         log("batched forest: generating")
         result["components"]["batched"] = batched_vs_plain(args, et, ctx, d, dev)
+    if not args.no_naive:
+        log("naive LCA: levels and climbing queries")
+        result["components"]["naive_lca"] = naive_vs_inlabel(args, et, ctx, d, d_parent, d_qx, d_qy, grasps)
     if not args.no_serve:
         log("serving: generating the job pool")
         result["components"]["serving"] = serving(args, dev)
@@ -264,6 +272,83 @@ def main():
         result["cpu_baseline"], result["parity"] = cpu_baseline(trees[0], qx, qy, rp, col, ginfo, et, d, ctx,
                                                                 d_parent[0], d_qx, d_qy, d_rp, d_col)
     print(json.dumps(result), flush=True)
+
+
+def _gpu_ms(fn, reps=3):
+    """Best-of-reps GPU time of fn() on the current stream (after one warm-up call)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def naive_vs_inlabel(args, et, ctx, d, d_parent, d_qx, d_qy, grasps):
+    """The paper's comparison of the naive algorithm (levels by pointer
+    jumping, queries by climbing) with Inlabel (Section 3.2, Figs. 4-5):
+    preprocessing of the three 2^log2n bench trees, queries where climbing
+    stays affordable, a depth sweep (grasp) and a q:n sweep at 2^20 nodes."""
+    import torch
+    import gen
+    res = {"trees": {}}
+    n = d_parent[0].numel()
+    names = ["n", "1000", "1"]
+    for i, g in enumerate(grasps):
+        lv = torch.empty_like(d_parent[i])
+        r = {"levels_ms": _gpu_ms(lambda: et.et_levels(d_parent[i], out=lv, ctx=ctx))}
+        q = {None: n, 1000: 1 << 16}.get(g)          # a path makes every climb ~n/3 steps long
+        if q:
+            x, y = d_qx[:q], d_qy[:q]
+            out = torch.empty_like(x)
+            r["queries"] = q
+            r["naive_query_ms"] = _gpu_ms(lambda: et.et_lca_naive(d_parent[i], lv, x, y, out=out, ctx=ctx))
+            tree = et.et_tree_build(d_parent[i], ctx=ctx)
+            ref = tree.lca(x, y)
+            r["inlabel_query_ms"] = _gpu_ms(lambda: tree.lca(x, y, out=ref))
+            r["naive_matches_inlabel"] = bool(torch.equal(out, ref))
+            tree.free()
+        r["inlabel_build_ms"] = _gpu_ms(lambda: et.et_tree_build(d_parent[i], ctx=ctx).free())
+        res["trees"][names[i]] = r
+        ctx.check()
+    m = 1 << 20
+    qx, qy = gen.random_queries(m, 1 << 24, seed=args.seed + 5)
+    dqx, dqy = d(qx), d(qy)
+
+    def both(parent, q):
+        lv = torch.empty_like(parent)
+        out = torch.empty(q, dtype=torch.int32, device=parent.device)
+        x, y = dqx[:q], dqy[:q]
+
+        def naive():
+            et.et_levels(parent, out=lv, ctx=ctx)
+            et.et_lca_naive(parent, lv, x, y, out=out, ctx=ctx)
+
+        def inlabel():
+            t = et.et_tree_build(parent, ctx=ctx)
+            t.lca(x, y, out=out)
+            t.free()
+        return _gpu_ms(naive, 2), _gpu_ms(inlabel, 2)
+
+    res["depth_sweep"] = []
+    for g in (None, 1 << 14, 1 << 10, 1 << 8, 1 << 6):
+        parent = d(gen.random_tree(m, g, seed=args.seed + 7))
+        nv, il = both(parent, m)
+        res["depth_sweep"].append({"n": m, "grasp": g or m, "q": m, "naive_ms": nv, "inlabel_ms": il})
+        log(f"naive sweep grasp {g or m}: naive {nv:.3f} ms, inlabel {il:.3f} ms")
+    parent = d(gen.random_tree(m, None, seed=args.seed + 8))
+    res["q_sweep"] = []
+    for lq in (10, 14, 18, 20, 22, 24):
+        nv, il = both(parent, 1 << lq)
+        res["q_sweep"].append({"n": m, "grasp": m, "q": 1 << lq, "naive_ms": nv, "inlabel_ms": il})
+    ctx.check()
+    return res
 
 
 def batched_vs_plain(args, et, ctx, d, dev):
@@ -349,6 +434,17 @@ def serving(args, dev):
     res["rate_jobs_per_s"] = args.serve_rate
     res["trace_seconds"] = args.serve_seconds
     res["p99_ratio_served_over_plain"] = res["served"]["p99_ms"] / res["plain"]["p99_ms"]
+    sweep = []
+    for rate in [float(r) for r in args.serve_sweep.split(",") if r.strip()]:
+        jobs = serve.make_trace(pool, rate, 2.0, seed=args.seed + 1)
+        serve.upload_trace(jobs, dev)
+        r = serve.compare(dpool, jobs)
+        log(f"serving sweep {rate:.0f} jobs/s: plain p99 {r['plain']['p99_ms']:.2f} ms, "
+            f"served p99 {r['served']['p99_ms']:.2f} ms")
+        sweep.append({"rate_jobs_per_s": rate, "jobs": len(jobs),
+                      **{f"{k}_{m}": r[k][m] for k in ("plain", "served")
+                         for m in ("p50_ms", "p99_ms", "jobs_per_s", "wall_s")}})
+    res["sweep"] = sweep
     return res
 
 

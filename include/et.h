@@ -187,6 +187,32 @@ int et_lca(const et_tree* tree, const int32_t* d_qx, const int32_t* d_qy, int64_
            int32_t* d_out, hipStream_t s);
 
 /*
+ * Node levels (distance from the root) by pointer jumping: the
+ * preprocessing of the naive LCA algorithm the paper compares against
+ * (Section 3.1, "The Naive Algorithm"). Every node's ancestor pointer starts
+ * at its parent and is doubled until it reaches a node of known level; five
+ * jumps are made between global synchronisations.
+ *   d_parent[n]  parent array as for et_tree_build (n >= 1, n < 2^30)
+ *   d_level[n]   output (caller-owned device array)
+ * A parent array that is not a tree sets ET_EINPUT in ctx's status (nodes
+ * that never reach the root keep level -1).
+ */
+int et_levels(et_ctx* ctx, const int32_t* d_parent, int32_t n, int32_t* d_level, hipStream_t s);
+
+/*
+ * LCA queries by climbing (Section 3.1, "The Naive Algorithm"): one lane per
+ * query moves the deeper of x, y up to the other's level, then both up
+ * until they meet; time grows with the x-y distance.
+ *   d_parent[n], d_level[n]  the tree and its levels from et_levels
+ *   d_qx[q], d_qy[q]         query pairs; d_out[q] receives the LCA, or -1
+ *                            for a query with an id out of range or levels
+ *                            that do not match the parent array (both also
+ *                            set ET_EINPUT).
+ */
+int et_lca_naive(et_ctx* ctx, const int32_t* d_parent, const int32_t* d_level, int32_t n,
+                 const int32_t* d_qx, const int32_t* d_qy, int64_t q, int32_t* d_out, hipStream_t s);
+
+/*
  * Bridges of an undirected graph (Section 4: edge e is a bridge iff
  * deleting it disconnects its endpoints), by Tarjan-Vishkin: spanning
  * forest by hooking connected components, Euler tour of the forest,

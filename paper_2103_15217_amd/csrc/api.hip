@@ -337,6 +337,18 @@ int et_bridges(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col, int3
   return ET_OK;
 }
 
+int et_levels(et_ctx* ctx, const int32_t* d_parent, int32_t n, int32_t* d_level, hipStream_t s) {
+  if (!ctx || n < 1 || n >= (1 << 30) || !d_parent || !d_level) return ET_EINVAL;
+  return et::levels_run(&ctx->impl, d_parent, n, d_level, s);
+}
+
+int et_lca_naive(et_ctx* ctx, const int32_t* d_parent, const int32_t* d_level, int32_t n, const int32_t* d_qx,
+                 const int32_t* d_qy, int64_t q, int32_t* d_out, hipStream_t s) {
+  if (!ctx || n < 1 || n >= (1 << 30) || !d_parent || !d_level || q < 0) return ET_EINVAL;
+  if (q > 0 && (!d_qx || !d_qy || !d_out)) return ET_EINVAL;
+  return et::lca_naive_run(&ctx->impl, d_parent, d_level, n, d_qx, d_qy, q, d_out, s);
+}
+
 int et_bridges_count(et_ctx* ctx, int64_t* d_count, hipStream_t s) {
   if (!ctx || !d_count) return ET_EINVAL;
   return hipMemcpyAsync(d_count, ctx->impl.d_bcount, sizeof(int64_t), hipMemcpyDeviceToDevice, s) == hipSuccess

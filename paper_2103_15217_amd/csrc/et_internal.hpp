@@ -159,6 +159,10 @@ struct LRResult {
 int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const int32_t* heads,
                    int32_t nheads, bool tree_weights, const int32_t* expected_reach,
                    LRResult* out, hipStream_t s, bool empty_head_ok = false);
+// naive.hip: node levels by pointer jumping and climbing LCA queries
+int levels_run(Ctx* c, const int32_t* parent, int32_t n, int32_t* level, hipStream_t s);
+int lca_naive_run(Ctx* c, const int32_t* parent, const int32_t* level, int32_t n, const int32_t* qx,
+                  const int32_t* qy, int64_t q, int32_t* out, hipStream_t s);
 int list_rank_generic(Ctx* c, const int32_t* succ, int32_t len, const int32_t* heads,
                       int32_t nheads, int32_t* rank, hipStream_t s);
 

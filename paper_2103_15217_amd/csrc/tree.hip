@@ -362,7 +362,7 @@ int tree_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
   }
   const int32_t L2 = 2 * n;          // half-edge id space (the tour uses 2(n-1) of them)
   Scratch scr(c);
-  uint32_t* kv = scr.get<uint32_t>((size_t)L2);  // sorted parents | children, later the xor weights
+  uint32_t* kv = scr.get<uint32_t>((size_t)L2);  // sorted parents | children, later the path-label table
   if (scr.failed) return ET_ENOMEM;
   uint32_t* keys = kv;
   int32_t* vals = reinterpret_cast<int32_t*>(kv + n);

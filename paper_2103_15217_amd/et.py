@@ -43,6 +43,8 @@ _SIG = {
     "et_lca": ([_P, _P, _P, _i64, _P, _P], ctypes.c_int),
     "et_bridges": ([_P, _P, _P, _i32, _i32, _P, ctypes.POINTER(_i64), _P], ctypes.c_int),
     "et_bridges_count": ([_P, _P, _P], ctypes.c_int),
+    "et_levels": ([_P, _P, _i32, _P, _P], ctypes.c_int),
+    "et_lca_naive": ([_P, _P, _P, _i32, _P, _P, _i64, _P, _P], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIG.items():
     _fn = getattr(_lib, _name)
@@ -299,6 +301,32 @@ def et_bridges(row_ptr, col, mask=None, ctx=None, count=True):
     _check(_lib.et_bridges(ctx.handle, _ptr(row_ptr), _ptr(col), n, nnz, _ptr(mask),
                            ctypes.byref(c) if count else None, _stream()), "et_bridges")
     return mask, (int(c.value) if count else None)
+
+
+def et_levels(parent, out=None, ctx=None):
+    """Node levels by pointer jumping (the naive algorithm's preprocessing)."""
+    ctx = ctx or default_context()
+    parent = _dev(parent, torch.int32, "parent")
+    if out is None:
+        out = torch.empty_like(parent)
+    _check(_lib.et_levels(ctx.handle, _ptr(parent), parent.numel(), _ptr(out), _stream()), "et_levels")
+    return out
+
+
+def et_lca_naive(parent, level, qx, qy, out=None, ctx=None):
+    """LCA queries by climbing parent pointers with the levels of et_levels."""
+    ctx = ctx or default_context()
+    parent = _dev(parent, torch.int32, "parent")
+    level = _dev(level, torch.int32, "level")
+    qx = _dev(qx, torch.int32, "qx")
+    qy = _dev(qy, torch.int32, "qy")
+    if qx.numel() != qy.numel() or level.numel() != parent.numel():
+        raise ValueError("array lengths differ")
+    if out is None:
+        out = torch.empty_like(qx)
+    _check(_lib.et_lca_naive(ctx.handle, _ptr(parent), _ptr(level), parent.numel(), _ptr(qx), _ptr(qy),
+                             qx.numel(), _ptr(out), _stream()), "et_lca_naive")
+    return out
 
 
 class BatchGraph:
