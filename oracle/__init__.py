@@ -36,6 +36,7 @@ def _bind(path):
         "oracle_lca_offline": [P, i32, P, P, i64, P],
         "oracle_sv_tables": [P, P, P, P, i32, P, P, P, P],
         "oracle_bridges": [P, P, i32, i64, P, P],
+        "oracle_euler_tour_edges": [i32, i64, P, P, i32, P, P, P, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -116,6 +117,28 @@ def tree_succ(parent):
         succ[tour[-1]] = -1
     head = int(tour[0]) if tour.shape[0] else -1
     return succ, head
+
+
+def euler_tour_edges(n, eu, ev, root):
+    """Euler tour of the tree given by the unordered edges (eu[i], ev[i]),
+    rooted at ``root``, by the DCEL construction of Section 2.1.
+
+    Half-edge 2i is (eu[i] -> ev[i]) and 2i+1 its twin. Returns ``succ`` and
+    ``rank`` [2m] (succ -1 at the tail), ``tour`` (half-edge ids in order),
+    and per node ``parent`` (-1 at the root), ``depth``, ``pre``, ``size``.
+    """
+    eu, ev = _i32(eu), _i32(ev)
+    m = eu.shape[0]
+    succ = np.empty(2 * m, dtype=np.int32)
+    rank = np.empty(2 * m, dtype=np.int32)
+    parent, depth, pre, size = (np.empty(n, dtype=np.int32) for _ in range(4))
+    rc = _load().oracle_euler_tour_edges(int(n), m, _ptr(eu), _ptr(ev), int(root), _ptr(succ), _ptr(rank),
+                                         _ptr(parent), _ptr(depth), _ptr(pre), _ptr(size))
+    _check(rc, "euler_tour_edges")
+    tour = np.empty(2 * m, dtype=np.int32)
+    tour[rank] = np.arange(2 * m, dtype=np.int32)
+    return {"succ": succ, "rank": rank, "tour": tour, "parent": parent, "depth": depth, "pre": pre,
+            "size": size}
 
 
 def list_rank(succ, heads):

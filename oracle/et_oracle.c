@@ -25,6 +25,14 @@
  *     found by trying the largest power of two first; ascendant(v) is the
  *     OR of 2^h(inlabel(u)) over all ancestors-or-self u; head[I] records
  *     the parent of the top node of the path labelled I and its depth.
+ *   - Euler tour from an unordered edge list (Section 2.1, Fig. 2): the
+ *     DCEL construction itself. Both directions of every edge become
+ *     half-edges (2i and 2i+1 for edge i, twins of each other); B is the
+ *     list of half-edges in lexicographic (source, target) order; next(e)
+ *     is the half-edge after e in its source's run of B, wrapping to the
+ *     run's first; succ(e) = next(twin(e)). The cycle is cut before the
+ *     first half-edge of the root's run. Children are then visited in
+ *     cyclic id order starting after the parent.
  *   - Bridges (Section 4.1): Tarjan's depth-first low-link algorithm. A
  *     tree edge {p, u} is a bridge iff low(u) > disc(p). Parallel edges
  *     are handled by skipping the parent only once; self-loops are ignored.
@@ -297,6 +305,91 @@ int oracle_sv_tables(const int32_t* parent, const int32_t* depth, const int32_t*
         }
     }
     return ORC_OK;
+}
+
+/* Euler tour from the unordered edge list of a tree (Section 2.1): the
+ * DCEL of Fig. 2 built as described there. eu[i], ev[i] is edge i; half-edge
+ * 2i is (eu[i] -> ev[i]) and 2i+1 its twin. Outputs: succ[2m] (-1 at the
+ * tail), rank[2m], and per node parent (-1 at the root), depth, pre, size.
+ * The edges must form one tree on n nodes (m = n - 1). */
+int oracle_euler_tour_edges(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev, int32_t root,
+                            int32_t* succ, int32_t* rank, int32_t* parent, int32_t* depth, int32_t* pre,
+                            int32_t* size) {
+    if (n < 1 || m != (int64_t)n - 1 || root < 0 || root >= n) return ORC_EINPUT;
+    const int64_t L = 2 * m;
+    for (int64_t i = 0; i < m; ++i)
+        if (eu[i] < 0 || eu[i] >= n || ev[i] < 0 || ev[i] >= n || eu[i] == ev[i]) return ORC_EINPUT;
+    for (int32_t v = 0; v < n; ++v) { parent[v] = -1; depth[v] = 0; pre[v] = 0; size[v] = 1; }
+    size[root] = n;
+    if (L == 0) return ORC_OK;
+    int32_t* src = malloc(L * sizeof(int32_t));
+    int32_t* dst = malloc(L * sizeof(int32_t));
+    int32_t* B = malloc(L * sizeof(int32_t));
+    int32_t* tmp = malloc(L * sizeof(int32_t));
+    int32_t* pos = malloc(L * sizeof(int32_t));
+    int64_t* cnt = calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t* first = malloc(((size_t)n + 1) * sizeof(int64_t));
+    if (!src || !dst || !B || !tmp || !pos || !cnt || !first) {
+        free(src); free(dst); free(B); free(tmp); free(pos); free(cnt); free(first);
+        return ORC_EINVAL;
+    }
+    for (int64_t i = 0; i < m; ++i) {
+        src[2 * i] = eu[i]; dst[2 * i] = ev[i];
+        src[2 * i + 1] = ev[i]; dst[2 * i + 1] = eu[i];
+    }
+    /* B: lexicographic order of (source, target), as two stable counting
+     * sorts (by target, then by source) */
+    for (int64_t h = 0; h < L; ++h) cnt[dst[h] + 1]++;
+    for (int32_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
+    for (int64_t h = 0; h < L; ++h) tmp[cnt[dst[h]]++] = (int32_t)h;
+    memset(cnt, 0, ((size_t)n + 1) * sizeof(int64_t));
+    for (int64_t h = 0; h < L; ++h) cnt[src[h] + 1]++;
+    for (int32_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
+    for (int32_t v = 0; v <= n; ++v) first[v] = cnt[v];   /* first[x]: start of x's run in B */
+    for (int64_t k = 0; k < L; ++k) {
+        const int32_t h = tmp[k];
+        B[cnt[src[h]]++] = h;
+    }
+    for (int64_t k = 0; k < L; ++k) pos[B[k]] = (int32_t)k;
+    /* succ(e) = next(twin(e)); next wraps inside the source's run */
+    for (int64_t e = 0; e < L; ++e) {
+        const int32_t t = (int32_t)(e ^ 1);
+        const int32_t x = src[t];
+        const int64_t k = pos[t];
+        succ[e] = (k + 1 < first[x + 1]) ? B[k + 1] : B[first[x]];
+    }
+    /* cut the cycle before the root's first half-edge */
+    int rc = ORC_OK;
+    if (first[root] == first[root + 1]) rc = ORC_EINPUT;          /* root has no edge */
+    const int32_t head = (rc == ORC_OK) ? B[first[root]] : -1;
+    for (int64_t e = 0; e < L && rc == ORC_OK; ++e)
+        if (succ[e] == head) { succ[e] = -1; break; }
+    /* walk: ranks, directions (a half-edge goes down iff it precedes its twin),
+     * parent, depth, preorder, size */
+    for (int64_t e = 0; e < L; ++e) rank[e] = -1;
+    int64_t r = 0;
+    for (int32_t e = head; rc == ORC_OK && e != -1; e = succ[e]) {
+        if (r >= L || rank[e] != -1) { rc = ORC_EINPUT; break; }
+        rank[e] = (int32_t)r++;
+    }
+    if (rc == ORC_OK && r != L) rc = ORC_EINPUT;                /* edges not one connected tree */
+    if (rc == ORC_OK) {
+        int32_t d = 0, visited = 1;
+        for (int32_t e = head; e != -1; e = succ[e]) {
+            const int32_t tw = e ^ 1;
+            if (rank[e] < rank[tw]) {                          /* down into dst[e] */
+                const int32_t c = dst[e];
+                parent[c] = src[e];
+                depth[c] = ++d;
+                pre[c] = visited++;
+                size[c] = (rank[tw] - rank[e] + 1) / 2;
+            } else {
+                --d;
+            }
+        }
+    }
+    free(src); free(dst); free(B); free(tmp); free(pos); free(cnt); free(first);
+    return rc;
 }
 
 /* Bridges of an undirected multigraph in symmetric CSR form (rows need not

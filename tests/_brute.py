@@ -149,3 +149,44 @@ def bridge_slots(row_ptr, col):
             flags[a] = flags[b] = True
             count += 1
     return flags, count
+
+
+def cyclic_dfs_tour(n, edges, root):
+    """Depth-first traversal of the tree given by undirected ``edges`` in
+    the child order that the DCEL's next() produces (Section 2.1): at a node
+    entered from p the neighbours are taken in ascending id order starting
+    after p and wrapping around; at the root they start from the smallest.
+    Written as a plain recursive DFS over sorted adjacency lists, with no
+    half-edge arrays. Returns the tour as (x, y) pairs and parent, depth,
+    preorder and subtree size lists."""
+    import sys
+    adj = [[] for _ in range(n)]
+    for x, y in edges:
+        adj[x].append(y)
+        adj[y].append(x)
+    for a in adj:
+        a.sort()
+    tour, parent = [], [-1] * n
+    depth, pre, size = [0] * n, [0] * n, [1] * n
+    counter = [0]
+    sys.setrecursionlimit(max(1000, 4 * n + 100))
+
+    def visit(x, p, d):
+        pre[x] = counter[0]
+        counter[0] += 1
+        depth[x] = d
+        nb = adj[x]
+        if p < 0:
+            order = nb
+        else:
+            k = nb.index(p)
+            order = nb[k + 1:] + nb[:k]
+        for c in order:
+            parent[c] = x
+            tour.append((x, c))
+            visit(c, x, d + 1)
+            size[x] += size[c]
+            tour.append((c, x))
+
+    visit(root, -1, 0)
+    return tour, parent, depth, pre, size

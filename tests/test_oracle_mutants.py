@@ -50,6 +50,14 @@ MUTANTS = {
                      "if (w == par[u]) { back_slot[u] = k; continue; }"),
     # non-strict bridge comparison
     "bridge_cmp": ("if (low[u] > disc[p]) {", "if (low[u] >= disc[p]) {"),
+    # next() wraps to the end of the source's run instead of its start
+    "dcel_wrap": ("succ[e] = (k + 1 < first[x + 1]) ? B[k + 1] : B[first[x]];",
+                  "succ[e] = (k + 1 < first[x + 1]) ? B[k + 1] : B[first[x + 1] - 1];"),
+    # successor taken as next(e) instead of next(twin(e))
+    "dcel_no_twin": ("const int32_t t = (int32_t)(e ^ 1);", "const int32_t t = (int32_t)e;"),
+    # a half-edge counted as going down when it follows its twin
+    "dcel_direction": ("if (rank[e] < rank[tw]) {                          /* down into dst[e] */",
+                       "if (rank[e] > rank[tw]) {                          /* down into dst[e] */"),
     # list ranks start at 1
     "list_rank_origin": ("int32_t r = 0;\n        while (e != -1) {", "int32_t r = 1;\n        while (e != -1) {"),
 }
@@ -70,6 +78,10 @@ def battery(mod):
         *[lambda s=s: pins.test_sv_tables_and_query(mod, s) for s in range(20)],
         *[lambda s=s: pins.test_bridges_bruteforce_multigraphs(mod, s) for s in range(40)],
         lambda: pins.test_bridges_special_graphs(mod),
+        lambda: pins.test_fig1_tour_from_edge_list(mod),
+        *[lambda s=s: pins.test_edge_list_tour_is_the_cyclic_dfs(mod, s) for s in range(12)],
+        *[lambda s=s: pins.test_edge_list_tour_matches_ascending_oracle_when_order_agrees(mod, s)
+          for s in range(3)],
     ]
     for chk in checks:
         try:

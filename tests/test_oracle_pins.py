@@ -427,3 +427,89 @@ def test_bridges_planted_chains(oracle_mod):
     for a, b in info["chain_edges"]:
         assert (int(a), int(b)) in bridge_pairs and (int(b), int(a)) in bridge_pairs
     assert cnt >= len(info["chain_edges"])
+
+
+# --------------------------------------------------------------- tour from an edge list (Section 2.1)
+
+def _half_edge_pairs(eu, ev):
+    src = np.empty(2 * len(eu), dtype=np.int64)
+    dst = np.empty(2 * len(eu), dtype=np.int64)
+    src[0::2], dst[0::2] = eu, ev
+    src[1::2], dst[1::2] = ev, eu
+    return src, dst
+
+
+def test_fig1_tour_from_edge_list(oracle_mod):
+    fig = _fig()
+    E = np.array(fig["tree_edges_parent_child"])
+    t = oracle_mod.euler_tour_edges(6, E[:, 0], E[:, 1], fig["root"])
+    src, dst = _half_edge_pairs(E[:, 0], E[:, 1])
+    pairs = [[int(src[h]), int(dst[h])] for h in t["tour"]]
+    assert pairs == fig["fig1_tour_in_order"]
+    # the worked example: succ of tour edge 6 is tour edge 7, through the twin of edge 6 (tour edge 1)
+    ex = fig["worked_succ_example"]
+    e6 = int(t["tour"][ex["edge_number"] - 1])
+    assert int(t["tour"][ex["twin_edge_number"] - 1]) == e6 ^ 1
+    assert int(t["succ"][e6]) == int(t["tour"][ex["succ_edge_number"] - 1])
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_edge_list_tour_is_the_cyclic_dfs(oracle_mod, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 40))
+    parent = gen.random_tree(n, [None, 1, 2, 4][seed % 4], seed=seed)
+    edges = [(int(parent[c]), c) for c in range(n) if parent[c] >= 0]
+    flip = rng.random(len(edges)) < 0.5                  # input orientation and order are arbitrary
+    edges = [(y, x) if f else (x, y) for (x, y), f in zip(edges, flip)]
+    edges = [edges[i] for i in rng.permutation(len(edges))]
+    root = int(rng.integers(n))
+    eu = np.array([e[0] for e in edges], dtype=np.int32)
+    ev = np.array([e[1] for e in edges], dtype=np.int32)
+    t = oracle_mod.euler_tour_edges(n, eu, ev, root)
+    tour, par, dep, pre, size = brute.cyclic_dfs_tour(n, edges, root)
+    src, dst = _half_edge_pairs(eu, ev)
+    assert [(int(src[h]), int(dst[h])) for h in t["tour"]] == tour
+    assert list(t["parent"]) == par and list(t["depth"]) == dep
+    assert list(t["pre"]) == pre and list(t["size"]) == size
+    assert all(t["rank"][t["tour"]] == np.arange(len(t["tour"])))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_edge_list_tour_matches_ascending_oracle_when_order_agrees(oracle_mod, seed):
+    # rooted at 0 with every parent id below its children's, the cyclic order
+    # after the parent is ascending order: both constructions give one tour
+    n = 5 + 7 * seed
+    parent = gen.random_tree(n, [None, 1, 3][seed % 3], seed=seed, relabel=False)
+    eu = parent[1:].astype(np.int32)
+    ev = np.arange(1, n, dtype=np.int32)
+    t = oracle_mod.euler_tour_edges(n, eu, ev, 0)
+    ref = oracle_mod.euler_tour(parent)
+    src, dst = _half_edge_pairs(eu, ev)
+    assert [(int(src[h]), int(dst[h])) for h in t["tour"]] == \
+        [_half_edge_pair(parent, int(e)) for e in ref["tour"]]
+    for k in ("depth", "pre", "size"):
+        assert np.array_equal(t[k], ref[k]), k
+    assert np.array_equal(t["parent"], parent)
+
+
+@pytest.mark.parametrize("bad", ["cycle", "self_loop", "out_of_range", "too_few", "isolated_root"])
+def test_edge_list_malformed(oracle_mod, bad):
+    eu, ev, n, root = [0, 1, 2], [1, 2, 3], 4, 0
+    if bad == "cycle":
+        eu, ev = [0, 1, 2], [1, 2, 0]                      # 3 edges on 4 nodes: node 3 cut off
+    elif bad == "self_loop":
+        eu, ev = [0, 1, 2], [1, 2, 2]
+    elif bad == "out_of_range":
+        ev = [1, 2, 4]
+    elif bad == "too_few":
+        eu, ev = [0, 1], [1, 2]
+    else:
+        eu, ev, root = [1, 1, 2], [2, 3, 3], 0            # root 0 has no edge (and 1-2-3 is a cycle)
+    with pytest.raises(oracle_mod.OracleInputError):
+        oracle_mod.euler_tour_edges(n, np.array(eu), np.array(ev), root)
+
+
+def test_edge_list_single_node(oracle_mod):
+    t = oracle_mod.euler_tour_edges(1, np.zeros(0, np.int32), np.zeros(0, np.int32), 0)
+    assert t["tour"].shape[0] == 0
+    assert list(t["parent"]) == [-1] and list(t["size"]) == [1] and list(t["pre"]) == [0]
