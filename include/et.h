@@ -127,6 +127,28 @@ int et_tree_build(et_ctx* ctx, const int32_t* d_parent, int32_t n, hipStream_t s
                   et_tree** out);
 
 /*
+ * Euler tour and tree tables from the unordered edge list of a tree, by the
+ * DCEL construction of Section 2.1 (Fig. 2): both directions of each edge
+ * as twin half-edges, the half-edges sorted lexicographically, next() inside
+ * a node's sorted run (cyclic), succ = next(twin), the cycle cut before the
+ * root's first half-edge.
+ *   d_u[n-1], d_v[n-1]  edge i joins d_u[i] and d_v[i] (any order, any
+ *                       orientation); half-edge 2i is (u_i -> v_i), 2i+1 its
+ *                       twin. n >= 1, n < 2^30, 0 <= root < n.
+ *   d_parent_out[n]     optional (NULL allowed): parent of every node in the
+ *                       tree rooted at root (-1 at the root).
+ * The tour visits the children of a node entered from p in cyclic id order
+ * starting after p (at the root: ascending), so it differs from
+ * et_tree_build's ascending order; depth, subtree size and LCA answers do
+ * not depend on the order. et_tree_export's succ / rank are indexed by these
+ * half-edge ids (2n - 2 used; the last two are -2 / -1). Edges that are not
+ * one tree on n nodes (an id out of range, a self-loop, a repeated edge, a
+ * cycle) set ET_EINPUT in ctx's status.
+ */
+int et_tree_build_edges(et_ctx* ctx, const int32_t* d_u, const int32_t* d_v, int32_t n, int32_t root,
+                        int32_t* d_parent_out, hipStream_t s, et_tree** out);
+
+/*
  * Batch of independent rooted trees, built in one pass (Section 3.3, batched
  * queries; the C4 workload of thousands of trees of uneven size).
  *   d_parent[n_total]        the trees' parent arrays concatenated; ids are

@@ -262,6 +262,23 @@ int et_tree_build(et_ctx* ctx, const int32_t* d_parent, int32_t n, hipStream_t s
   return ET_OK;
 }
 
+int et_tree_build_edges(et_ctx* ctx, const int32_t* d_u, const int32_t* d_v, int32_t n, int32_t root,
+                        int32_t* d_parent_out, hipStream_t s, et_tree** out) {
+  if (!out) return ET_EINVAL;
+  *out = nullptr;
+  if (!ctx || n < 1 || n >= (1 << 30) || root < 0 || root >= n) return ET_EINVAL;
+  if (n > 1 && (!d_u || !d_v)) return ET_EINVAL;
+  et_tree* t = tree_alloc(ctx, n, 0);
+  if (!t) return ET_ENOMEM;
+  int rc = et::tree_build_edges(&ctx->impl, t, d_u, d_v, root, d_parent_out, s);
+  if (rc) {
+    et_tree_free(t, s);
+    return rc;
+  }
+  *out = t;
+  return ET_OK;
+}
+
 int et_tree_build_batch(et_ctx* ctx, const int32_t* d_parent, const int64_t* d_offsets, int32_t n_trees,
                         int64_t n_total, hipStream_t s, et_tree** out) {
   if (!out) return ET_EINVAL;

@@ -12,6 +12,8 @@
 
 #include "../../include/et.h"
 
+struct et_tree;
+
 namespace et {
 
 // ---------------------------------------------------------------- status bits
@@ -134,6 +136,15 @@ __device__ __forceinline__ int ctz32(uint32_t x) { return __ffs((int)x) - 1; }
 
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// Schieber-Vishkin inlabel (Section 3.1): the member of [pre+1, pre+size]
+// with the most trailing zeros, in closed form (j >> k) << k with j =
+// pre + size and k the highest bit in which pre and j differ.
+__device__ __forceinline__ uint32_t inlabel_of(int32_t pre, int32_t size) {
+  const uint32_t j = (uint32_t)pre + (uint32_t)size;          // pre+1 .. pre+size, 1-based
+  const int k = msb32((uint32_t)pre ^ j);                      // (p-1) xor j with p = pre+1
+  return (j >> k) << k;
+}
+
 // ---------------------------------------------------------------- launchers
 // scan.hip: inclusive scan of u32 over [0, n) with + or xor
 enum class ScanOp { Add, Xor };
@@ -159,6 +170,16 @@ struct LRResult {
 int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const int32_t* heads,
                    int32_t nheads, bool tree_weights, const int32_t* expected_reach,
                    LRResult* out, hipStream_t s, bool empty_head_ok = false);
+// radix.hip: stable sort of (key, value) pairs by the low `bits` key bits
+int sort_pairs_u32(Ctx* c, const uint32_t* keys, const int32_t* vals, int32_t n, int bits, uint32_t* keys_out,
+                   int32_t* vals_out, hipStream_t s);
+// tree.hip: head table, path labels and ascendants of a tree whose node
+// records {inlabel, -, depth, pre} and compact inlabels are written;
+// t->d_root[0] must hold the root id; plab needs n+1 slots of scratch
+int inlabel_phase(Ctx* c, et_tree* t, const int32_t* parent, const uint32_t* inl, uint32_t* plab, hipStream_t s);
+// edges.hip: tree tables from an unordered edge list (the DCEL construction)
+int tree_build_edges(Ctx* c, et_tree* t, const int32_t* eu, const int32_t* ev, int32_t root, int32_t* parent_out,
+                     hipStream_t s);
 // naive.hip: node levels by pointer jumping and climbing LCA queries
 int levels_run(Ctx* c, const int32_t* parent, int32_t n, int32_t* level, hipStream_t s);
 int lca_naive_run(Ctx* c, const int32_t* parent, const int32_t* level, int32_t n, const int32_t* qx,

@@ -235,4 +235,44 @@ int group_by_parent_impl(Ctx* c, const int32_t* parent, int32_t n, uint32_t* key
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }
 
+// Stable sort of (key, value) pairs by the low `bits` bits of the key, with
+// the same kernels: keys_out / vals_out receive the sorted pairs; the inputs
+// are left as they are.
+int sort_pairs_u32(Ctx* c, const uint32_t* keys, const int32_t* vals, int32_t n, int bits, uint32_t* keys_out,
+                   int32_t* vals_out, hipStream_t s) {
+  if (n <= 0) return ET_OK;
+  bits = std::max(1, std::min(bits, 32));
+  const int passes = (bits + 7) / 8;
+  const int32_t ntiles = ceil_div(n, kTile);
+  Scratch sc(c);
+  uint32_t* hist = sc.get<uint32_t>((size_t)256 * ntiles);
+  uint32_t* tk = sc.get<uint32_t>((size_t)n);
+  int32_t* tv = sc.get<int32_t>((size_t)n);
+  if (sc.failed) return ET_ENOMEM;
+  const void* kin = keys;
+  const int32_t* vin = vals;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    const int nbits = std::min(8, bits - shift);
+    const bool to_out = ((passes - 1 - p) % 2) == 0;
+    uint32_t* kout = to_out ? keys_out : tk;
+    int32_t* vout = to_out ? vals_out : tv;
+    {
+      ET_PROF(c, s, "k_upsweep<false>");
+      hipLaunchKernelGGL(k_upsweep<false>, dim3(ntiles), dim3(kThreads), 0, s, kin, n, shift, nbits, ntiles, hist,
+                         nullptr, nullptr, c->d_status);
+    }
+    int rc = scan_u32(c, hist, hist, (int64_t)(1 << nbits) * ntiles, ScanOp::Add, true, s);
+    if (rc) return rc;
+    {
+      ET_PROF(c, s, "k_downsweep<false>");
+      hipLaunchKernelGGL(k_downsweep<false>, dim3(ntiles), dim3(kThreads), 0, s, kin, vin, n, shift, nbits, ntiles,
+                         hist, kout, vout);
+    }
+    kin = kout;
+    vin = vout;
+  }
+  return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+}
+
 }  // namespace et

@@ -59,12 +59,6 @@ __global__ void k_succ(const uint32_t* __restrict__ keys, const int32_t* __restr
   }
 }
 
-__device__ __forceinline__ uint32_t inlabel_of(int32_t pre, int32_t size) {
-  const uint32_t j = (uint32_t)pre + (uint32_t)size;          // pre+1 .. pre+size, 1-based
-  const int k = msb32((uint32_t)pre ^ j);                      // (p-1) xor j with p = pre+1
-  return (j >> k) << k;
-}
-
 __global__ void k_node(const uint64_t* __restrict__ packed, const int2* __restrict__ off, int32_t nsub,
                        int32_t n, const int32_t* __restrict__ sc, int32_t* __restrict__ rank,
                        int32_t* __restrict__ pre_out, int32_t* __restrict__ size_out, int4* __restrict__ rec,
@@ -387,8 +381,14 @@ int tree_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
                          t->d_size, t->d_rec, inl, c->d_status);
     }
   }
+  return inlabel_phase(c, t, parent, inl, kv, s);  // n+1 label slots: the grouping keys are dead by now
+}
+
+int inlabel_phase(Ctx* c, et_tree* t, const int32_t* parent, const uint32_t* inl, uint32_t* plab, hipStream_t s) {
+  const int32_t n = t->n;
+  int32_t* sc = t->d_root;
+  const int gn = ceil_div(n, kB);
   ET_PROF(c, s, "phase:inlabel");
-  uint32_t* plab = kv;  // n+1 label slots (the grouping keys are dead by now)
   hipLaunchKernelGGL(k_fill_u32, dim3(std::min(ceil_div((int64_t)n + 1, kB), 8192)), dim3(kB), 0, s, plab,
                      (int64_t)n + 1, kUnused);
   {

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libet.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with paper_2103_15217_amd/build.py "
+    raise ImportError(f"{LIB_PATH} is missing: build it with python paper_2103_15217_amd/build.py "
                       "(or __graft_entry__.build()); there is no fallback")
 
 _lib = ctypes.CDLL(LIB_PATH)
@@ -44,6 +44,7 @@ _SIG = {
     "et_bridges": ([_P, _P, _P, _i32, _i32, _P, ctypes.POINTER(_i64), _P], ctypes.c_int),
     "et_bridges_count": ([_P, _P, _P], ctypes.c_int),
     "et_levels": ([_P, _P, _i32, _P, _P], ctypes.c_int),
+    "et_tree_build_edges": ([_P, _P, _P, _i32, _i32, _P, _P, ctypes.POINTER(_P)], ctypes.c_int),
     "et_lca_naive": ([_P, _P, _P, _i32, _P, _P, _i64, _P, _P], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIG.items():
@@ -262,6 +263,26 @@ def et_tree_build(parent, ctx=None):
     _check(_lib.et_tree_build(ctx.handle, _ptr(parent), parent.numel(), _stream(), ctypes.byref(h)),
            "et_tree_build")
     return Tree(h, parent.numel(), ctx)
+
+
+def et_tree_build_edges(u, v, n, root, ctx=None, parent_out=None):
+    """Build from the unordered edge list (u[i], v[i]) of a tree on n nodes,
+    rooted at ``root`` (the DCEL construction). With ``parent_out`` (an int32
+    device tensor of n entries) the rooted parent array is written there."""
+    ctx = ctx or default_context()
+    u = _dev(u, torch.int32, "u")
+    v = _dev(v, torch.int32, "v")
+    if u.numel() != n - 1 or v.numel() != n - 1:
+        raise ValueError("a tree on n nodes has n - 1 edges")
+    if parent_out is not None:
+        parent_out = _dev(parent_out, torch.int32, "parent_out")
+        if parent_out.numel() != n:
+            raise ValueError("parent_out needs n entries")
+    h = _P()
+    _check(_lib.et_tree_build_edges(ctx.handle, _ptr(u) if n > 1 else None, _ptr(v) if n > 1 else None, int(n),
+                                    int(root), _ptr(parent_out), _stream(), ctypes.byref(h)),
+           "et_tree_build_edges")
+    return Tree(h, int(n), ctx)
 
 
 def et_lca(tree, qx, qy, out=None):
