@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-tree batched vs plain comparison")
     ap.add_argument("--batch-trees", type=int, default=4096)
     ap.add_argument("--no-serve", action="store_true", help="skip the served vs plain trace replay")
+    ap.add_argument("--no-edges", action="store_true",
+                    help="skip the edge-list (DCEL construction) build comparison")
     ap.add_argument("--no-naive", action="store_true",
                     help="skip the naive (climbing) LCA comparison and its depth and q:n sweeps")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -261,6 +263,9 @@ def main():
     if not args.no_batch:
         log("batched forest: generating")
         result["components"]["batched"] = batched_vs_plain(args, et, ctx, d, dev)
+    if not args.no_edges:
+        log("edge-list build")
+        result["components"]["edge_list_build"] = edges_vs_parent(args, et, ctx, d, trees, d_parent, grasps)
     if not args.no_naive:
         log("naive LCA: levels and climbing queries")
         result["components"]["naive_lca"] = naive_vs_inlabel(args, et, ctx, d, d_parent, d_qx, d_qy, grasps)
@@ -288,6 +293,38 @@ def _gpu_ms(fn, reps=3):
         torch.cuda.synchronize()
         best = min(best, e0.elapsed_time(e1))
     return best
+
+
+def edges_vs_parent(args, et, ctx, d, trees, d_parent, grasps):
+    """The same three 2^log2n trees given as unordered, randomly oriented
+    edge lists: et_tree_build_edges (the DCEL construction of Section 2.1,
+    with its lexicographic sort) against et_tree_build from the parent
+    array; also checks that depth and size agree."""
+    import torch
+    res = {}
+    names = ["n", "1000", "1"]
+    for i, g in enumerate(grasps):
+        parent = trees[i]
+        rng = np.random.default_rng(args.seed + 40 + i)
+        c = np.flatnonzero(parent >= 0).astype(np.int32)
+        p = parent[c]
+        flip = rng.random(c.shape[0]) < 0.5
+        order = rng.permutation(c.shape[0])
+        u, v = d(np.where(flip, c, p)[order]), d(np.where(flip, p, c)[order])
+        n = parent.shape[0]
+        root = int(np.flatnonzero(parent == -1)[0])
+        edges_ms = _gpu_ms(lambda: et.et_tree_build_edges(u, v, n, root, ctx=ctx).free())
+        parent_ms = _gpu_ms(lambda: et.et_tree_build(d_parent[i], ctx=ctx).free())
+        te = et.et_tree_build_edges(u, v, n, root, ctx=ctx)
+        tp = et.et_tree_build(d_parent[i], ctx=ctx)
+        a, b = te.export(("depth", "size")), tp.export(("depth", "size"))
+        same = bool(torch.equal(a["depth"], b["depth"]) and torch.equal(a["size"], b["size"]))
+        te.free()
+        tp.free()
+        ctx.check()
+        res[names[i]] = {"edges_build_ms": edges_ms, "parent_build_ms": parent_ms,
+                         "edges_nodes_per_s": n / (edges_ms * 1e-3), "depth_size_agree": same}
+    return res
 
 
 def naive_vs_inlabel(args, et, ctx, d, d_parent, d_qx, d_qy, grasps):
