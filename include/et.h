@@ -256,6 +256,20 @@ int et_lca_naive(et_ctx* ctx, const int32_t* d_parent, const int32_t* d_level, i
 int et_bridges(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col, int32_t n,
                int32_t nnz, uint32_t* d_mask, int64_t* h_count, hipStream_t s);
 
+/*
+ * Bridges by the comparison methods of Section 4.1: Chaitanya-Kothapalli
+ * marking. Every non-tree edge marks the tree edges on its path up to the
+ * endpoints' lowest common ancestor; unmarked tree edges are bridges.
+ *   spanning = 0   CK: a breadth-first-search forest (one root per
+ *                  component, chosen by connectivity labels). The call
+ *                  waits for stream s about once per 16 BFS levels.
+ *   spanning = 1   hybrid: the connectivity forest of et_bridges, rooted and
+ *                  levelled by its Euler tour.
+ * Arguments, output and limits as for et_bridges (the result is the same).
+ */
+int et_bridges_ck(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col, int32_t n, int32_t nnz,
+                  int32_t spanning, uint32_t* d_mask, int64_t* h_count, hipStream_t s);
+
 /* Device-side bridge count of the most recent et_bridges call on ctx
  * (written to a caller-owned device int64). */
 int et_bridges_count(et_ctx* ctx, int64_t* d_count, hipStream_t s);

@@ -18,8 +18,6 @@ int tree_lca(Ctx* c, const et_tree* t, const int32_t* qx, const int32_t* qy, int
 int tree_build_batch(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s);
 int tree_lca_batch(Ctx* c, const et_tree* t, const int32_t* qt, const int32_t* qx, const int32_t* qy, int64_t q,
                    int32_t* out, hipStream_t s);
-int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t nnz, uint32_t* mask,
-                hipStream_t s);
 
 namespace {
 constexpr size_t kAlign = 256;
@@ -344,7 +342,7 @@ int et_bridges(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col, int3
   if (!ctx || n < 0 || n >= (1 << 30) || nnz < 0 || !d_row_ptr) return ET_EINVAL;  // 2(n-1) forest half-edges fit int32
   if (nnz > 0 && (!d_col || !d_mask)) return ET_EINVAL;
   Ctx* c = &ctx->impl;
-  int rc = et::bridges_run(c, d_row_ptr, d_col, n, nnz, d_mask, s);
+  int rc = et::bridges_run(c, d_row_ptr, d_col, n, nnz, d_mask, s, et::kAlgoTV);
   if (rc) return rc;
   if (h_count) {
     if (hipMemcpyAsync(h_count, c->d_bcount, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -364,6 +362,21 @@ int et_lca_naive(et_ctx* ctx, const int32_t* d_parent, const int32_t* d_level, i
   if (!ctx || n < 1 || n >= (1 << 30) || !d_parent || !d_level || q < 0) return ET_EINVAL;
   if (q > 0 && (!d_qx || !d_qy || !d_out)) return ET_EINVAL;
   return et::lca_naive_run(&ctx->impl, d_parent, d_level, n, d_qx, d_qy, q, d_out, s);
+}
+
+int et_bridges_ck(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col, int32_t n, int32_t nnz,
+                  int32_t spanning, uint32_t* d_mask, int64_t* h_count, hipStream_t s) {
+  if (!ctx || n < 0 || n >= (1 << 30) || nnz < 0 || !d_row_ptr || (spanning != 0 && spanning != 1)) return ET_EINVAL;
+  if (nnz > 0 && (!d_col || !d_mask)) return ET_EINVAL;
+  Ctx* c = &ctx->impl;
+  int rc = et::bridges_run(c, d_row_ptr, d_col, n, nnz, d_mask, s, spanning == 0 ? et::kAlgoCK : et::kAlgoHybrid);
+  if (rc) return rc;
+  if (h_count) {
+    if (hipMemcpyAsync(h_count, c->d_bcount, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return ET_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return ET_EHIP;
+  }
+  return ET_OK;
 }
 
 int et_bridges_count(et_ctx* ctx, int64_t* d_count, hipStream_t s) {

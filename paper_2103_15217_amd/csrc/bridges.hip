@@ -407,11 +407,15 @@ __global__ void k_direction(const int32_t* __restrict__ rank, const int32_t* __r
                             const int32_t* __restrict__ tsrc, const int32_t* __restrict__ tnbr,
                             const int32_t* __restrict__ tslot, const uint32_t* __restrict__ tptr,
                             const int32_t* cc, int32_t n, int32_t Lcap, const int32_t* __restrict__ sc,
-                            uint32_t* __restrict__ dw, int4* __restrict__ vrec, uint32_t* __restrict__ status) {
+                            uint32_t* __restrict__ dw, int4* __restrict__ vrec, uint32_t* __restrict__ dd,
+                            uint32_t* __restrict__ status) {
   const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t L = sc[0];
   if (h >= L) {
-    if (h < Lcap) dw[h] = 0u;
+    if (h < Lcap) {
+      dw[h] = 0u;
+      if (dd) dd[h] = 0u;
+    }
     return;
   }
   const int32_t r = rank[h];
@@ -429,6 +433,7 @@ __global__ void k_direction(const int32_t* __restrict__ rank, const int32_t* __r
     return;
   }
   dw[r] = (uint32_t)down + (uint32_t)head;
+  if (dd) dd[r] = down ? 1u : 0xffffffffu;  // +1 / -1: a prefix sum gives the depth (component tours are balanced)
   if (down) vrec[w] = make_int4(r, (rt - r + 1) >> 1, tslot[h], tslot[t]);
   if (head) {
     const int32_t tail = ttwin[clampi((int32_t)tptr[u + 1] - 1, 0, L - 1)];
@@ -608,10 +613,77 @@ __global__ __launch_bounds__(kB) void k_bridge_test(const int4* __restrict__ byp
 
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
 
+// hybrid: parent, level and the two slots of the parent edge of every vertex
+// from the direction records and the depth prefix sums
+__global__ void k_hybrid_nodes(const int4* __restrict__ vrec, const uint32_t* __restrict__ depth_at,
+                               const int32_t* __restrict__ col, int32_t n, int32_t nnz, int32_t Lcap,
+                               int32_t* __restrict__ par, int32_t* __restrict__ lvl, int32_t* __restrict__ pslot,
+                               int32_t* __restrict__ uslot, uint32_t* __restrict__ status) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int4 r = vrec[v];
+  int32_t p = -1, l = -1, ps = -1, us = -1;
+  if (r.x >= 0 && r.x < Lcap) {
+    if (r.z < 0) {
+      p = -2;  // a component root
+      l = 0;
+    } else if ((uint32_t)r.w < (uint32_t)nnz && (uint32_t)r.z < (uint32_t)nnz) {
+      p = col[r.w];
+      l = (int32_t)depth_at[r.x];
+      ps = r.z;
+      us = r.w;
+    } else {
+      flag(status, ST_BAD_INDEX);
+    }
+  }
+  par[v] = p;
+  lvl[v] = l;
+  pslot[v] = ps;
+  uslot[v] = us;
+}
+
 }  // namespace
 
+// Connectivity labels and a spanning forest (both slots of every forest
+// edge set in tbits): sampled hooking rounds, then the rows outside the
+// largest sampled component. cc[v] == v marks one root per component.
+int spanning_forest(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t nnz, int32_t* cc,
+                    uint32_t* tbits, int32_t* big, hipStream_t s) {
+  const int32_t words = (int32_t)(((int64_t)nnz + 31) >> 5);
+  const int gn = ceil_div(n, kB);
+  const int grows = ceil_div(n, kRowsPerBlock);
+  {
+    ET_PROF(c, s, "k_check_csr");
+    hipLaunchKernelGGL(k_check_csr, dim3(gn), dim3(kB), 0, s, row_ptr, n, nnz, c->d_status);
+  }
+  hipLaunchKernelGGL(k_iota, dim3(gn), dim3(kB), 0, s, cc, n);
+  hipLaunchKernelGGL(k_fill_i32, dim3(std::min(ceil_div(words, kB), 4096)), dim3(kB), 0, s,
+                     reinterpret_cast<int32_t*>(tbits), (int64_t)words, 0);
+  for (int j = 0; j < kSample; ++j) {
+    {
+      ET_PROF(c, s, "k_hook_sample");
+      hipLaunchKernelGGL(k_hook_sample, dim3(gn), dim3(kB), 0, s, row_ptr, col, n, nnz, cc, tbits, c->d_status, j);
+    }
+    {
+      ET_PROF(c, s, "k_cc_compress");
+      hipLaunchKernelGGL(k_cc_compress, dim3(gn), dim3(kB), 0, s, cc, n);
+    }
+  }
+  {
+    ET_PROF(c, s, "k_big_component");
+    hipLaunchKernelGGL(k_big_component, dim3(1), dim3(kBigSample), 0, s, cc, n, big);
+  }
+  {
+    ET_PROF(c, s, "k_hook_rest");
+    hipLaunchKernelGGL(k_hook_rest, dim3(grows), dim3(kB), 0, s, row_ptr, col, n, nnz, cc, big, tbits,
+                       c->d_status);
+  }
+  return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+}
+
 int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t nnz, uint32_t* mask,
-                hipStream_t s) {
+                hipStream_t s, int algo) {
+  if (algo == kAlgoCK) return bridges_ck_bfs(c, row_ptr, col, n, nnz, mask, s);
   hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, s, c->d_bcount);
   const int32_t words = (int32_t)(((int64_t)nnz + 31) >> 5);
   if (words > 0)
@@ -651,43 +723,18 @@ int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, i
   if (sc.failed) return ET_ENOMEM;
 
   const int gn = ceil_div(n, kB);
-  const int grows = ceil_div(n, kRowsPerBlock);
   const int gl = ceil_div(Lcap, kB);
   // 1. spanning forest
   ET_PROF(c, s, "phase:bridges");
-  {
-    ET_PROF(c, s, "k_check_csr");
-    hipLaunchKernelGGL(k_check_csr, dim3(gn), dim3(kB), 0, s, row_ptr, n, nnz, c->d_status);
-  }
-  hipLaunchKernelGGL(k_iota, dim3(gn), dim3(kB), 0, s, cc, n);
-  hipLaunchKernelGGL(k_fill_i32, dim3(std::min(ceil_div(words, kB), 4096)), dim3(kB), 0, s,
-                     reinterpret_cast<int32_t*>(tbits), (int64_t)words, 0);
-  for (int j = 0; j < kSample; ++j) {
-    {
-      ET_PROF(c, s, "k_hook_sample");
-      hipLaunchKernelGGL(k_hook_sample, dim3(gn), dim3(kB), 0, s, row_ptr, col, n, nnz, cc, tbits, c->d_status, j);
-    }
-    {
-      ET_PROF(c, s, "k_cc_compress");
-      hipLaunchKernelGGL(k_cc_compress, dim3(gn), dim3(kB), 0, s, cc, n);
-    }
-  }
-  {
-    ET_PROF(c, s, "k_big_component");
-    hipLaunchKernelGGL(k_big_component, dim3(1), dim3(kBigSample), 0, s, cc, n, scal + 4);
-  }
-  {
-    ET_PROF(c, s, "k_hook_rest");
-    hipLaunchKernelGGL(k_hook_rest, dim3(grows), dim3(kB), 0, s, row_ptr, col, n, nnz, cc, scal + 4, tbits,
-                       c->d_status);
-  }
+  int rc = spanning_forest(c, row_ptr, col, n, nnz, cc, tbits, scal + 4, s);
+  if (rc) return rc;
   // 2. forest CSR, twins, successors, component chaining
   {
     ET_PROF(c, s, "k_tree_deg");
     hipLaunchKernelGGL(k_tree_deg, dim3(gn), dim3(kB), 0, s, row_ptr, tbits, n, nnz, tdeg);
   }
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, s, reinterpret_cast<int32_t*>(tdeg + n), (int64_t)1, 0);
-  int rc = scan_u32(c, tdeg, tptr, (int64_t)n + 1, ScanOp::Add, true, s);
+  rc = scan_u32(c, tdeg, tptr, (int64_t)n + 1, ScanOp::Add, true, s);
   if (rc) return rc;
   {
     ET_PROF(c, s, "k_tree_fill");
@@ -728,7 +775,24 @@ int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, i
   {
     ET_PROF(c, s, "k_direction");
     hipLaunchKernelGGL(k_direction, dim3(gl), dim3(kB), 0, s, rank, ttwin, tsrc, tnbr, tslot, tptr, cc, n, Lcap, scal,
-                       dw, vrec, c->d_status);
+                       dw, vrec, algo == kAlgoHybrid ? reinterpret_cast<uint32_t*>(succ) : nullptr, c->d_status);
+  }
+  if (algo == kAlgoHybrid) {
+    // the hybrid of Section 4.1: this rooted forest, levels from the tour,
+    // then Chaitanya-Kothapalli marking instead of low / high
+    uint32_t* depth_at = reinterpret_cast<uint32_t*>(succ);  // the successors are dead after the ranking
+    rc = scan_u32(c, depth_at, depth_at, Lcap, ScanOp::Add, false, s);
+    if (rc) return rc;
+    int32_t* par = pre;                                   // per-vertex arrays of the test phase are unused
+    int32_t* lvl = amin;
+    int32_t* pslot = amax;
+    int32_t* uslot = reinterpret_cast<int32_t*>(mmin);
+    {
+      ET_PROF(c, s, "k_hybrid_nodes");
+      hipLaunchKernelGGL(k_hybrid_nodes, dim3(gn), dim3(kB), 0, s, vrec, depth_at, col, n, nnz, Lcap, par, lvl,
+                         pslot, uslot, c->d_status);
+    }
+    return ck_mark(c, row_ptr, col, n, nnz, tbits, par, lvl, pslot, uslot, mask, s);
   }
   rc = scan_u32(c, dw, dw, Lcap, ScanOp::Add, false, s);
   if (rc) return rc;

@@ -180,6 +180,21 @@ int inlabel_phase(Ctx* c, et_tree* t, const int32_t* parent, const uint32_t* inl
 // edges.hip: tree tables from an unordered edge list (the DCEL construction)
 int tree_build_edges(Ctx* c, et_tree* t, const int32_t* eu, const int32_t* ev, int32_t root, int32_t* parent_out,
                      hipStream_t s);
+// bridges.hip / ck.hip: bridge finding. kAlgoTV = Tarjan-Vishkin (low /
+// high), kAlgoCK = Chaitanya-Kothapalli marking on a BFS forest, kAlgoHybrid
+// = marking on the connectivity forest rooted by the Euler tour.
+enum { kAlgoTV = 0, kAlgoCK = 1, kAlgoHybrid = 2 };
+int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t nnz, uint32_t* mask,
+                hipStream_t s, int algo);
+int spanning_forest(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t nnz, int32_t* cc,
+                    uint32_t* tbits, int32_t* big, hipStream_t s);
+int ck_bfs_forest(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t nnz, const int32_t* cc,
+                  int32_t* par, int32_t* lvl, int32_t* pslot, int32_t* uslot, uint32_t* tbits, hipStream_t s);
+int ck_mark(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t nnz, const uint32_t* tbits,
+            const int32_t* par, const int32_t* lvl, const int32_t* pslot, const int32_t* uslot, uint32_t* mask,
+            hipStream_t s);
+int bridges_ck_bfs(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t nnz, uint32_t* mask,
+                   hipStream_t s);
 // naive.hip: node levels by pointer jumping and climbing LCA queries
 int levels_run(Ctx* c, const int32_t* parent, int32_t n, int32_t* level, hipStream_t s);
 int lca_naive_run(Ctx* c, const int32_t* parent, const int32_t* level, int32_t n, const int32_t* qx,

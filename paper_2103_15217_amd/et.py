@@ -43,6 +43,7 @@ _SIG = {
     "et_lca": ([_P, _P, _P, _i64, _P, _P], ctypes.c_int),
     "et_bridges": ([_P, _P, _P, _i32, _i32, _P, ctypes.POINTER(_i64), _P], ctypes.c_int),
     "et_bridges_count": ([_P, _P, _P], ctypes.c_int),
+    "et_bridges_ck": ([_P, _P, _P, _i32, _i32, _i32, _P, ctypes.POINTER(_i64), _P], ctypes.c_int),
     "et_levels": ([_P, _P, _i32, _P, _P], ctypes.c_int),
     "et_tree_build_edges": ([_P, _P, _P, _i32, _i32, _P, _P, ctypes.POINTER(_P)], ctypes.c_int),
     "et_lca_naive": ([_P, _P, _P, _i32, _P, _P, _i64, _P, _P], ctypes.c_int),
@@ -321,6 +322,24 @@ def et_bridges(row_ptr, col, mask=None, ctx=None, count=True):
     c = _i64(0)
     _check(_lib.et_bridges(ctx.handle, _ptr(row_ptr), _ptr(col), n, nnz, _ptr(mask),
                            ctypes.byref(c) if count else None, _stream()), "et_bridges")
+    return mask, (int(c.value) if count else None)
+
+
+def et_bridges_ck(row_ptr, col, spanning="bfs", mask=None, ctx=None, count=True):
+    """Bridges by Chaitanya-Kothapalli marking on a BFS forest
+    (``spanning="bfs"``) or on the connectivity forest rooted by the Euler
+    tour (``spanning="forest"``, the hybrid); same output as et_bridges."""
+    ctx = ctx or default_context()
+    row_ptr = _dev(row_ptr, torch.int32, "row_ptr")
+    col = _dev(col, torch.int32, "col")
+    n = row_ptr.numel() - 1
+    nnz = col.numel()
+    if mask is None:
+        mask = torch.empty(max((nnz + 31) // 32, 1), dtype=torch.int32, device=col.device)
+    c = _i64(0)
+    sp = {"bfs": 0, "forest": 1}[spanning]
+    _check(_lib.et_bridges_ck(ctx.handle, _ptr(row_ptr), _ptr(col), n, nnz, sp, _ptr(mask),
+                              ctypes.byref(c) if count else None, _stream()), "et_bridges_ck")
     return mask, (int(c.value) if count else None)
 
 
