@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-tree batched vs plain comparison")
     ap.add_argument("--batch-trees", type=int, default=4096)
     ap.add_argument("--no-serve", action="store_true", help="skip the served vs plain trace replay")
+    ap.add_argument("--no-ck", action="store_true",
+                    help="skip the Chaitanya-Kothapalli and hybrid bridge comparison")
     ap.add_argument("--no-edges", action="store_true",
                     help="skip the edge-list (DCEL construction) build comparison")
     ap.add_argument("--no-naive", action="store_true",
@@ -263,6 +265,9 @@ def main():
     if not args.no_batch:
         log("batched forest: generating")
         result["components"]["batched"] = batched_vs_plain(args, et, ctx, d, dev)
+    if not args.no_ck:
+        log("bridges: CK and hybrid")
+        result["components"]["bridges_methods"] = bridges_methods(et, ctx, d_rp, d_col, d_mask, ginfo["m"])
     if not args.no_edges:
         log("edge-list build")
         result["components"]["edge_list_build"] = edges_vs_parent(args, et, ctx, d, trees, d_parent, grasps)
@@ -293,6 +298,42 @@ def _gpu_ms(fn, reps=3):
         torch.cuda.synchronize()
         best = min(best, e0.elapsed_time(e1))
     return best
+
+
+BRIDGE_PHASES = {
+    "spanning forest": ("k_check_csr", "k_hook_sample", "k_cc_compress", "k_big_component", "k_hook_rest"),
+    "BFS": ("k_bfs_level", "k_bfs_slots"),
+    "Euler tour": ("k_tree_deg", "k_tree_fill", "k_root_flags", "k_root_list", "k_succ_csr", "k_link_roots",
+                   "k_walk1<false>", "k_walkN", "k_final_lds", "k_final_walk", "k_push_down", "k_check_reached",
+                   "k_rank_fix", "k_count_used", "k_rank_of", "k_direction", "k_preorder", "k_hybrid_nodes"),
+    "marking": ("k_ck_mark", "k_ck_out"),
+    "low/high + test": ("k_minmax", "k_rmq_blocks", "k_sparse_level", "k_bridge_test"),
+}
+
+
+def bridges_methods(et, ctx, d_rp, d_col, tv_mask, m):
+    """Tarjan-Vishkin against the paper's comparison methods on the bench
+    graph (Section 4.2, Figs. 10-11): Chaitanya-Kothapalli marking on a BFS
+    forest and the hybrid (marking on the Euler-tour-rooted connectivity
+    forest). Whole-call time (best of 2) and a per-phase kernel breakdown."""
+    import torch
+    res = {}
+    calls = {"TV": lambda: et.et_bridges(d_rp, d_col, ctx=ctx, count=False)[0],
+             "CK": lambda: et.et_bridges_ck(d_rp, d_col, spanning="bfs", ctx=ctx, count=False)[0],
+             "hybrid": lambda: et.et_bridges_ck(d_rp, d_col, spanning="forest", ctx=ctx, count=False)[0]}
+    for name, fn in calls.items():
+        ms = _gpu_ms(fn, 2)
+        ctx.profile_read()
+        ctx.profile(True)
+        out = fn()
+        torch.cuda.synchronize()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        phases = {ph: sum(prof[k][1] for k in ks if k in prof) for ph, ks in BRIDGE_PHASES.items()}
+        res[name] = {"ms": ms, "edges_per_s": m / (ms * 1e-3), "same_mask_as_tv": bool(torch.equal(out, tv_mask)),
+                     "phase_ms": {k: v for k, v in phases.items() if v > 0}}
+        ctx.check()
+    return res
 
 
 def edges_vs_parent(args, et, ctx, d, trees, d_parent, grasps):
