@@ -119,3 +119,46 @@ def forest_batch(num_trees, seed=0, log2_min=6, log2_max=18,
         "qx": np.concatenate(qx), "qy": np.concatenate(qy),
         "qtree": np.concatenate(qt),
     }
+
+
+def ba_tree(n, seed=0, relabel=True):
+    """Scale-free tree by preferential attachment (Barabasi-Albert with one
+    edge per new node; the paper's Section 3.2 scale-free LCA workload):
+    nodes 0 and 1 start joined; node i >= 2 attaches to an existing node
+    chosen with probability proportional to its degree, i.e. to one end of
+    a uniformly chosen earlier edge. Returns a parent array rooted at node 0
+    (ids then go through a seeded permutation with ``relabel``).
+
+    Edge k (k = 1..i-1) joins node k and its parent, so a uniform choice
+    among the 2(i-1) edge ends is: r even -> node r/2 + 1, r odd -> the
+    parent of node (r-1)/2 + 1. The second case refers to an earlier
+    parent, resolved below by pointer jumping over the whole array."""
+    n = int(n)
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), 0xBA]))
+    seq = np.full(n, -1, dtype=np.int64)
+    if n >= 2:
+        seq[1] = 0
+    if n >= 3:
+        i = np.arange(2, n, dtype=np.int64)
+        r = rng.integers(0, 2 * (i - 1))
+        k = r // 2 + 1
+        direct = (r % 2) == 0
+        target = np.where(direct, k, -1)       # parent known now
+        ref = np.where(direct, -1, k)          # parent = parent of node ref
+        seq[2:] = target
+        refs = np.full(n, -1, dtype=np.int64)
+        refs[2:] = ref
+        todo = np.flatnonzero(refs >= 0)
+        while todo.size:
+            a = refs[todo]
+            pa = seq[a]
+            done = pa >= 0
+            seq[todo[done]] = pa[done]
+            # not known yet: node a also copies a parent, so look where a looks
+            refs[todo[~done]] = refs[a[~done]]
+            todo = todo[~done]
+    if not relabel:
+        return seq.astype(np.int32)
+    return _relabel(seq, rng)

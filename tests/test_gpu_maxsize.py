@@ -13,8 +13,9 @@ determine the result at any size (the oracle would take minutes here):
   recurrence, preorder a permutation with nested intervals, size recurrence,
   ascending sibling order on sampled parents, and sampled LCA queries by
   climbing;
-* a graph of a 2^28-vertex cycle and a 2^28-vertex path (nnz = 2^31 - 2),
-  relabelled: exactly the path edges are bridges.
+* a graph of a 2^29-vertex cycle and a (2^29 - 1)-vertex path (n = 2^30 - 1
+  vertices, nnz = 2^31 - 4 slots), relabelled: exactly the path edges are
+  bridges.
 """
 import numpy as np
 import pytest
@@ -209,10 +210,10 @@ def cycle_and_path_csr(c, p, seed):
 
 
 def test_bridges_at_the_slot_limit(lib, ctx):
-    c = p = 1 << 28
+    c, p = 1 << 29, (1 << 29) - 1                     # n = 2^30 - 1 vertices
     row_ptr, col, is_path, deg = cycle_and_path_csr(c, p, seed=31)
     nnz = col.shape[0]
-    assert nnz == (1 << 31) - 2
+    assert nnz == (1 << 31) - 4                       # 2c + 2(p - 1) slots
     log(f"cycle + path graph: V={c + p} nnz={nnz}")
     d_rp, d_col = dev(row_ptr), dev(col)
     del row_ptr, col

@@ -513,3 +513,24 @@ def test_edge_list_single_node(oracle_mod):
     t = oracle_mod.euler_tour_edges(1, np.zeros(0, np.int32), np.zeros(0, np.int32), 0)
     assert t["tour"].shape[0] == 0
     assert list(t["parent"]) == [-1] and list(t["size"]) == [1] and list(t["pre"]) == [0]
+
+
+# --------------------------------------------------------------- scale-free generator (Section 3.2)
+
+def test_ba_tree_degree_distribution():
+    # preferential attachment with one edge per node: P(deg = k) = 4 / (k (k+1) (k+2))
+    n = 1 << 20
+    p = gen.ba_tree(n, seed=3, relabel=False)
+    assert p[0] == -1 and np.all(p[1:] >= 0) and np.all(p[1:] < np.arange(1, n))
+    deg = np.bincount(p[1:], minlength=n) + (np.arange(n) > 0)
+    for k in (1, 2, 3, 4, 8):
+        expect = 4.0 / (k * (k + 1) * (k + 2))
+        assert abs(np.mean(deg == k) - expect) < 5 * np.sqrt(expect / n) + 1e-4, k
+
+
+def test_ba_tree_small_cases_and_relabel(oracle_mod):
+    assert list(gen.ba_tree(1, seed=0)) == [-1]
+    assert sorted(gen.ba_tree(2, seed=0).tolist()) == [-1, 0] or sorted(gen.ba_tree(2, seed=0).tolist()) == [-1, 1]
+    p = gen.ba_tree(5000, seed=4)
+    t = oracle_mod.euler_tour(p)                         # a valid tree: the oracle accepts it
+    assert t["size"][t["root"]] == 5000
