@@ -149,6 +149,22 @@ int et_tree_build_edges(et_ctx* ctx, const int32_t* d_u, const int32_t* d_v, int
                         int32_t* d_parent_out, hipStream_t s, et_tree** out);
 
 /*
+ * LCA by range minima over the Euler tour (the RMQ approach that Section 3
+ * compares Inlabel with): et_tree_rmq_build adds to a tree built by
+ * et_tree_build the tour's node sequence as {depth, node} keys, in-block
+ * suffix-minimum masks over 32-position blocks and a sparse table over the
+ * block minima (about 14 bytes per half-edge); et_lca_rmq answers queries
+ * with them (same results as et_lca).
+ *   d_parent[n]  the parent array the tree was built from (read during the
+ *                call only).
+ * ET_EINVAL for a batch, a tree built from an edge list, or et_lca_rmq on a
+ * tree without the tables. The tables are freed with the tree.
+ */
+int et_tree_rmq_build(et_tree* tree, const int32_t* d_parent, hipStream_t s);
+int et_lca_rmq(const et_tree* tree, const int32_t* d_qx, const int32_t* d_qy, int64_t q, int32_t* d_out,
+               hipStream_t s);
+
+/*
  * Batch of independent rooted trees, built in one pass (Section 3.3, batched
  * queries; the C4 workload of thousands of trees of uneven size).
  *   d_parent[n_total]        the trees' parent arrays concatenated; ids are

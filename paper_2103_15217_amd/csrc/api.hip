@@ -268,6 +268,7 @@ int et_tree_build_edges(et_ctx* ctx, const int32_t* d_u, const int32_t* d_v, int
   if (n > 1 && (!d_u || !d_v)) return ET_EINVAL;
   et_tree* t = tree_alloc(ctx, n, 0);
   if (!t) return ET_ENOMEM;
+  t->from_edges = 1;
   int rc = et::tree_build_edges(&ctx->impl, t, d_u, d_v, root, d_parent_out, s);
   if (rc) {
     et_tree_free(t, s);
@@ -275,6 +276,26 @@ int et_tree_build_edges(et_ctx* ctx, const int32_t* d_u, const int32_t* d_v, int
   }
   *out = t;
   return ET_OK;
+}
+
+int et_tree_rmq_build(et_tree* tree, const int32_t* d_parent, hipStream_t s) {
+  if (!tree || tree->batch || tree->from_edges || (tree->n > 1 && !d_parent)) return ET_EINVAL;
+  Ctx* c = &tree->ctx->impl;
+  for (void** p : {reinterpret_cast<void**>(&tree->d_rmq_e), reinterpret_cast<void**>(&tree->d_rmq_mask),
+                   reinterpret_cast<void**>(&tree->d_rmq_st)})
+    if (*p) {
+      et::pool_put(c, *p);
+      *p = nullptr;
+    }
+  return et::tree_rmq_build(c, tree, d_parent, s);
+}
+
+int et_lca_rmq(const et_tree* tree, const int32_t* d_qx, const int32_t* d_qy, int64_t q, int32_t* d_out,
+               hipStream_t s) {
+  if (!tree || tree->batch || q < 0 || q > (int64_t)0x7fffffff * 64) return ET_EINVAL;
+  if (tree->n > 1 && !tree->d_rmq_e) return ET_EINVAL;  // et_tree_rmq_build first
+  if (q > 0 && (!d_qx || !d_qy || !d_out)) return ET_EINVAL;
+  return et::tree_lca_rmq(&tree->ctx->impl, tree, d_qx, d_qy, q, d_out, s);
 }
 
 int et_tree_build_batch(et_ctx* ctx, const int32_t* d_parent, const int64_t* d_offsets, int32_t n_trees,
@@ -323,8 +344,8 @@ void et_tree_free(et_tree* tree, hipStream_t s) {
   (void)s;
   if (!tree) return;
   Ctx* c = &tree->ctx->impl;
-  void* blocks[] = {tree->d_succ, tree->d_rank, tree->d_pre, tree->d_size, tree->d_rec,
-                    tree->d_head, tree->d_root, tree->d_off, tree->d_root_of};
+  void* blocks[] = {tree->d_succ, tree->d_rank, tree->d_pre,   tree->d_size,    tree->d_rec,     tree->d_head,
+                    tree->d_root, tree->d_off,  tree->d_root_of, tree->d_rmq_e, tree->d_rmq_mask, tree->d_rmq_st};
   for (void* p : blocks)
     if (p) et::pool_put(c, p);
   delete tree;

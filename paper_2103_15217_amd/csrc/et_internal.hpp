@@ -195,6 +195,10 @@ int ck_mark(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32
             hipStream_t s);
 int bridges_ck_bfs(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t nnz, uint32_t* mask,
                    hipStream_t s);
+// rmq.hip: LCA by range minima over the Euler tour
+int tree_rmq_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s);
+int tree_lca_rmq(Ctx* c, const et_tree* t, const int32_t* qx, const int32_t* qy, int64_t q, int32_t* out,
+                 hipStream_t s);
 // naive.hip: node levels by pointer jumping and climbing LCA queries
 int levels_run(Ctx* c, const int32_t* parent, int32_t n, int32_t* level, hipStream_t s);
 int lca_naive_run(Ctx* c, const int32_t* parent, const int32_t* level, int32_t n, const int32_t* qx,
@@ -222,4 +226,10 @@ struct et_tree {
   int4* d_rec;         // [n] {inlabel, asc, depth, pre}
   int2* d_head;        // [n+2] by inlabel: {parent of path top, its depth}
   int32_t* d_root;     // device scalar
+  int32_t from_edges;  // built by et_tree_build_edges (half-edge ids follow the edge list)
+  // optional RMQ query engine (et_tree_rmq_build)
+  uint64_t* d_rmq_e;     // [2(n-1)] {depth, node} after every tour half-edge
+  uint32_t* d_rmq_mask;  // [2(n-1)] in-block suffix-minimum masks
+  uint64_t* d_rmq_st;    // sparse table over 32-position block minima, level-major
+  int32_t rmq_nb;        // number of blocks
 };

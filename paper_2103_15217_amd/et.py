@@ -46,6 +46,8 @@ _SIG = {
     "et_bridges_ck": ([_P, _P, _P, _i32, _i32, _i32, _P, ctypes.POINTER(_i64), _P], ctypes.c_int),
     "et_levels": ([_P, _P, _i32, _P, _P], ctypes.c_int),
     "et_tree_build_edges": ([_P, _P, _P, _i32, _i32, _P, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "et_tree_rmq_build": ([_P, _P, _P], ctypes.c_int),
+    "et_lca_rmq": ([_P, _P, _P, _i64, _P, _P], ctypes.c_int),
     "et_lca_naive": ([_P, _P, _P, _i32, _P, _P, _i64, _P, _P], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIG.items():
@@ -243,6 +245,23 @@ class Tree:
         if out is None:
             out = torch.empty_like(qx)
         _check(_lib.et_lca(self._h, _ptr(qx), _ptr(qy), qx.numel(), _ptr(out), _stream()), "et_lca")
+        return out
+
+    def rmq_build(self, parent):
+        """Add the RMQ query engine's tables (``parent``: the array the tree was built from)."""
+        parent = _dev(parent, torch.int32, "parent")
+        _check(_lib.et_tree_rmq_build(self._h, _ptr(parent), _stream()), "et_tree_rmq_build")
+        return self
+
+    def lca_rmq(self, qx, qy, out=None):
+        """LCA queries answered by range minima over the Euler tour."""
+        qx = _dev(qx, torch.int32, "qx")
+        qy = _dev(qy, torch.int32, "qy")
+        if qx.numel() != qy.numel():
+            raise ValueError("qx and qy differ in length")
+        if out is None:
+            out = torch.empty_like(qx)
+        _check(_lib.et_lca_rmq(self._h, _ptr(qx), _ptr(qy), qx.numel(), _ptr(out), _stream()), "et_lca_rmq")
         return out
 
     def free(self):
