@@ -34,6 +34,7 @@ namespace {
 constexpr int kB = 256;
 constexpr int kRowsPerBlock = 256;
 constexpr int kRmqLog = 5;  // 32-element RMQ blocks
+constexpr int kMaxGrid = 1 << 20;  // workgroups of a grid-stride launch (a dispatch holds < 2^32 work-items)
 
 __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -468,30 +469,33 @@ __global__ __launch_bounds__(kB) void k_minmax(const int32_t* __restrict__ row_p
                                               const uint32_t* __restrict__ tbits, const int32_t* __restrict__ pre,
                                               int32_t n, int32_t nnz, int32_t* __restrict__ amin,
                                               int32_t* __restrict__ amax) {
-  const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes;
   const int sub = threadIdx.x & (kRowLanes - 1);
-  if (u >= n) return;                 // whole row group leaves together
-  const int32_t p = pre[u];
-  if (p < 0 || p >= n) return;        // isolated vertex
-  const int32_t a = clampi(row_ptr[u], 0, nnz), b = clampi(row_ptr[u + 1], a, nnz);
-  int32_t mn = p, mx = p;
-  for (int64_t kk = (int64_t)a + sub; kk < b; kk += kRowLanes) {  // b may lie within one stride of 2^31
-    const int32_t k = (int32_t)kk;
-    if ((tbits[k >> 5] >> (k & 31)) & 1u) continue;
-    const int32_t w = col[k];
-    if ((uint32_t)w >= (uint32_t)n) continue;
-    const int32_t pw = pre[w];
-    mn = min(mn, pw);
-    mx = max(mx, pw);
-  }
+  const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kRowLanes);
+  // rows stride over the grid: 16 lanes per row would exceed the 2^32
+  // work-items of one dispatch beyond 2^28 rows
+  for (int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes; u < n; u += groups) {
+    const int32_t p = pre[u];
+    if (p < 0 || p >= n) continue;    // isolated vertex (the whole row group skips together)
+    const int32_t a = clampi(row_ptr[u], 0, nnz), b = clampi(row_ptr[u + 1], a, nnz);
+    int32_t mn = p, mx = p;
+    for (int64_t kk = (int64_t)a + sub; kk < b; kk += kRowLanes) {  // b may lie within one stride of 2^31
+      const int32_t k = (int32_t)kk;
+      if ((tbits[k >> 5] >> (k & 31)) & 1u) continue;
+      const int32_t w = col[k];
+      if ((uint32_t)w >= (uint32_t)n) continue;
+      const int32_t pw = pre[w];
+      mn = min(mn, pw);
+      mx = max(mx, pw);
+    }
 #pragma unroll
-  for (int o = kRowLanes / 2; o > 0; o >>= 1) {
-    mn = min(mn, __shfl_xor(mn, o, kRowLanes));
-    mx = max(mx, __shfl_xor(mx, o, kRowLanes));
-  }
-  if (sub == 0) {
-    amin[p] = mn;
-    amax[p] = mx;
+    for (int o = kRowLanes / 2; o > 0; o >>= 1) {
+      mn = min(mn, __shfl_xor(mn, o, kRowLanes));
+      mx = max(mx, __shfl_xor(mx, o, kRowLanes));
+    }
+    if (sub == 0) {
+      amin[p] = mn;
+      amax[p] = mx;
+    }
   }
 }
 
@@ -803,8 +807,8 @@ int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, i
   // 4. non-forest extremes by preorder
   {
     ET_PROF(c, s, "k_minmax");
-    hipLaunchKernelGGL(k_minmax, dim3(ceil_div((int64_t)n * kRowLanes, kB)), dim3(kB), 0, s, row_ptr, col, tbits, pre,
-                       n, nnz, amin, amax);
+    hipLaunchKernelGGL(k_minmax, dim3(std::min(ceil_div((int64_t)n * kRowLanes, kB), kMaxGrid)), dim3(kB), 0, s,
+                       row_ptr, col, tbits, pre, n, nnz, amin, amax);
   }
   // 5. range extremes
   {

@@ -111,11 +111,11 @@ __global__ __launch_bounds__(kB) void k_ck_mark(const int32_t* __restrict__ row_
                                                int32_t n, int32_t nnz, const uint32_t* __restrict__ tbits,
                                                const int32_t* __restrict__ par, const int32_t* __restrict__ lvl,
                                                uint8_t* __restrict__ mark, uint32_t* __restrict__ status) {
-  const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLanes;
   const int sub = threadIdx.x & (kLanes - 1);
-  if (u >= n) return;
-  const int32_t a = min(max(row_ptr[u], 0), nnz), b = min(max(row_ptr[u + 1], a), nnz);
+  const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kLanes);
   bool bad = false;
+  for (int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLanes; u < n; u += groups) {
+  const int32_t a = min(max(row_ptr[u], 0), nnz), b = min(max(row_ptr[u + 1], a), nnz);
   for (int64_t kk = (int64_t)a + sub; kk < b; kk += kLanes) {
     const int32_t k = (int32_t)kk;
     const int32_t w = col[k];
@@ -149,6 +149,7 @@ __global__ __launch_bounds__(kB) void k_ck_mark(const int32_t* __restrict__ row_
     }
     if (x < 0 || y < 0) bad = true;
   }
+  }
   if (bad) flag(status, ST_BAD_INDEX);
 }
 
@@ -180,8 +181,8 @@ int ck_mark(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32
                      reinterpret_cast<int32_t*>(mark), ((int64_t)n + 3) / 4, 0);
   {
     ET_PROF(c, s, "k_ck_mark");
-    hipLaunchKernelGGL(k_ck_mark, dim3(ceil_div((int64_t)n * kLanes, kB)), dim3(kB), 0, s, row_ptr, col, n, nnz,
-                       tbits, par, lvl, mark, c->d_status);
+    hipLaunchKernelGGL(k_ck_mark, dim3(std::min(ceil_div((int64_t)n * kLanes, kB), 1 << 20)), dim3(kB), 0, s, row_ptr,
+                       col, n, nnz, tbits, par, lvl, mark, c->d_status);
   }
   {
     ET_PROF(c, s, "k_ck_out");

@@ -136,6 +136,9 @@ __device__ __forceinline__ int ctz32(uint32_t x) { return __ffs((int)x) - 1; }
 
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// queries per dispatch: a dispatch holds fewer than 2^32 work-items
+constexpr int64_t kQueryChunk = (int64_t)1 << 31;
+
 // Schieber-Vishkin inlabel (Section 3.1): the member of [pre+1, pre+size]
 // with the most trailing zeros, in closed form (j >> k) << k with j =
 // pre + size and k the highest bit in which pre and j differ.

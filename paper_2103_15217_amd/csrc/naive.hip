@@ -161,11 +161,11 @@ int levels_run(Ctx* c, const int32_t* parent, int32_t n, int32_t* level, hipStre
 int lca_naive_run(Ctx* c, const int32_t* parent, const int32_t* level, int32_t n, const int32_t* qx,
                   const int32_t* qy, int64_t q, int32_t* out, hipStream_t s) {
   if (q == 0) return ET_OK;
-  const int64_t blocks = (q + kB - 1) / kB;
-  {
-    ET_PROF(c, s, "k_lca_naive");
-    hipLaunchKernelGGL(k_lca_naive, dim3((unsigned)blocks), dim3(kB), 0, s, parent, level, n, qx, qy, q, out,
-                       c->d_status);
+  ET_PROF(c, s, "k_lca_naive");
+  for (int64_t q0 = 0; q0 < q; q0 += kQueryChunk) {  // one dispatch holds < 2^32 work-items
+    const int64_t m = std::min(q - q0, kQueryChunk);
+    hipLaunchKernelGGL(k_lca_naive, dim3((unsigned)((m + kB - 1) / kB)), dim3(kB), 0, s, parent, level, n, qx + q0,
+                       qy + q0, m, out + q0, c->d_status);
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }

@@ -163,11 +163,11 @@ int tree_lca_rmq(Ctx* c, const et_tree* t, const int32_t* qx, const int32_t* qy,
   if (q == 0) return ET_OK;
   const int32_t L = 2 * (t->n - 1);
   RmqTables tab{t->d_rmq_e, t->d_rmq_mask, t->d_rmq_st, t->rmq_nb};
-  const int64_t blocks = (q + kB - 1) / kB;
-  {
-    ET_PROF(c, s, "k_lca_rmq");
-    hipLaunchKernelGGL(k_lca_rmq, dim3((unsigned)blocks), dim3(kB), 0, s, tab, t->d_rank, t->n, t->d_root, L, qx,
-                       qy, q, out, c->d_status);
+  ET_PROF(c, s, "k_lca_rmq");
+  for (int64_t q0 = 0; q0 < q; q0 += kQueryChunk) {  // one dispatch holds < 2^32 work-items
+    const int64_t m = std::min(q - q0, kQueryChunk);
+    hipLaunchKernelGGL(k_lca_rmq, dim3((unsigned)((m + kB - 1) / kB)), dim3(kB), 0, s, tab, t->d_rank, t->n,
+                       t->d_root, L, qx + q0, qy + q0, m, out + q0, c->d_status);
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }

@@ -436,11 +436,11 @@ int tree_export(const et_tree* t, int32_t* succ, int32_t* rank, int32_t* depth, 
 int tree_lca_batch(Ctx* c, const et_tree* t, const int32_t* qt, const int32_t* qx, const int32_t* qy, int64_t q,
                    int32_t* out, hipStream_t s) {
   if (q == 0) return ET_OK;
-  const int64_t blocks = (q + kB - 1) / kB;
-  {
-    ET_PROF(c, s, "k_lca_batch");
-    hipLaunchKernelGGL(k_lca_batch, dim3((unsigned)blocks), dim3(kB), 0, s, t->d_rec, t->d_head, t->n, t->d_off,
-                       t->batch, qt, qx, qy, q, out, c->d_status);
+  ET_PROF(c, s, "k_lca_batch");
+  for (int64_t q0 = 0; q0 < q; q0 += kQueryChunk) {  // one dispatch holds < 2^32 work-items
+    const int64_t m = std::min(q - q0, kQueryChunk);
+    hipLaunchKernelGGL(k_lca_batch, dim3((unsigned)((m + kB - 1) / kB)), dim3(kB), 0, s, t->d_rec, t->d_head, t->n,
+                       t->d_off, t->batch, qt + q0, qx + q0, qy + q0, m, out + q0, c->d_status);
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }
@@ -464,11 +464,11 @@ int tree_build_batch(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
 int tree_lca(Ctx* c, const et_tree* t, const int32_t* qx, const int32_t* qy, int64_t q, int32_t* out,
              hipStream_t s) {
   if (q == 0) return ET_OK;
-  const int64_t blocks = (q + kB - 1) / kB;
-  {
-    ET_PROF(c, s, "k_lca");
-    hipLaunchKernelGGL(k_lca, dim3((unsigned)blocks), dim3(kB), 0, s, t->d_rec, t->d_head, t->n, qx, qy, q, out,
-                       c->d_status);
+  ET_PROF(c, s, "k_lca");
+  for (int64_t q0 = 0; q0 < q; q0 += kQueryChunk) {  // one dispatch holds < 2^32 work-items
+    const int64_t m = std::min(q - q0, kQueryChunk);
+    hipLaunchKernelGGL(k_lca, dim3((unsigned)((m + kB - 1) / kB)), dim3(kB), 0, s, t->d_rec, t->d_head, t->n, qx + q0,
+                       qy + q0, m, out + q0, c->d_status);
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }
