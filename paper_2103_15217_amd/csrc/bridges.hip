@@ -263,9 +263,9 @@ __global__ __launch_bounds__(kB) void k_hook_rest(const int32_t* __restrict__ ro
 __device__ __forceinline__ uint32_t bits_in(const uint32_t* tbits, int32_t a, int32_t b, int32_t wd) {
   // forest bits of slots [a, b) that fall into word wd
   uint32_t x = tbits[wd];
-  const int32_t base = wd << 5;
-  if (a > base) x &= ~0u << (a - base);
-  if (b < base + 32) x &= (b - base <= 0) ? 0u : (~0u >> (32 - (b - base)));
+  const int64_t base = (int64_t)wd << 5;  // 64-bit: base + 32 reaches 2^31 in the last word
+  if (a > base) x &= ~0u << (int)(a - base);
+  if (b < base + 32) x &= (b - base <= 0) ? 0u : (~0u >> (int)(32 - (b - base)));
   return x;
 }
 

@@ -133,7 +133,7 @@ int tree_rmq_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
   const int32_t n = t->n;
   const int32_t L = 2 * (n - 1);
   if (L == 0) return ET_OK;
-  const int32_t nb = (L + 31) >> kLog;
+  const int32_t nb = (int32_t)(((int64_t)L + 31) >> kLog);
   int levels = 1;
   while ((1 << levels) <= nb) ++levels;
   t->d_rmq_e = static_cast<uint64_t*>(pool_get(c, (size_t)L * sizeof(uint64_t)));
