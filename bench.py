@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-tree batched vs plain comparison")
     ap.add_argument("--batch-trees", type=int, default=4096)
     ap.add_argument("--no-serve", action="store_true", help="skip the served vs plain trace replay")
+    ap.add_argument("--no-engines", action="store_true",
+                    help="skip the Inlabel vs RMQ query engine comparison (and the scale-free tree)")
     ap.add_argument("--no-ck", action="store_true",
                     help="skip the Chaitanya-Kothapalli and hybrid bridge comparison")
     ap.add_argument("--no-edges", action="store_true",
@@ -265,6 +267,9 @@ def main():
     if not args.no_batch:
         log("batched forest: generating")
         result["components"]["batched"] = batched_vs_plain(args, et, ctx, d, dev)
+    if not args.no_engines:
+        log("query engines: Inlabel vs RMQ, scale-free tree")
+        result["components"]["query_engines"] = query_engines(args, et, ctx, d, d_parent, d_qx, d_qy, grasps)
     if not args.no_ck:
         log("bridges: CK and hybrid")
         result["components"]["bridges_methods"] = bridges_methods(et, ctx, d_rp, d_col, d_mask, ginfo["m"])
@@ -298,6 +303,40 @@ def _gpu_ms(fn, reps=3):
         torch.cuda.synchronize()
         best = min(best, e0.elapsed_time(e1))
     return best
+
+
+def query_engines(args, et, ctx, d, d_parent, d_qx, d_qy, grasps):
+    """Inlabel against the RMQ engine over the Euler tour (Section 3) on the
+    three bench trees and on a 2^log2n scale-free (Barabasi-Albert) tree
+    (Section 3.2, Figs. 7-8), with 2^log2n uniform queries each; the naive
+    method is added on the scale-free tree, which is shallow."""
+    import torch
+    import gen
+    res = {}
+    trees = list(zip(["n", "1000", "1"], d_parent))
+    n = d_parent[0].numel()
+    t0 = time.time()
+    trees.append(("scale_free", d(gen.ba_tree(n, seed=args.seed + 9))))
+    log(f"scale-free tree generated in {time.time() - t0:.1f}s")
+    out = torch.empty_like(d_qx)
+    for name, par in trees:
+        r = {"inlabel_build_ms": _gpu_ms(lambda: et.et_tree_build(par, ctx=ctx).free(), 2)}
+        tree = et.et_tree_build(par, ctx=ctx)
+        r["rmq_build_ms"] = _gpu_ms(lambda: tree.rmq_build(par), 2)
+        r["inlabel_query_ms"] = _gpu_ms(lambda: tree.lca(d_qx, d_qy, out=out))
+        ref = out.clone()
+        r["rmq_query_ms"] = _gpu_ms(lambda: tree.lca_rmq(d_qx, d_qy, out=out))
+        r["rmq_matches_inlabel"] = bool(torch.equal(out, ref))
+        if name == "scale_free":
+            lv = torch.empty_like(par)
+            r["naive_levels_ms"] = _gpu_ms(lambda: et.et_levels(par, out=lv, ctx=ctx), 2)
+            r["naive_query_ms"] = _gpu_ms(lambda: et.et_lca_naive(par, lv, d_qx, d_qy, out=out, ctx=ctx))
+            r["naive_matches_inlabel"] = bool(torch.equal(out, ref))
+        tree.free()
+        ctx.check()
+        r["queries"] = d_qx.numel()
+        res[name] = r
+    return res
 
 
 BRIDGE_PHASES = {
