@@ -13,10 +13,12 @@
 // BFS: level-synchronous and top-down from one root per component (the
 // roots of the connectivity labels), 16 lanes per frontier vertex; a
 // neighbour is claimed by compare-and-swap on its parent entry, which also
-// records the claiming CSR slot as its tree edge. Launches are issued in
-// groups of 16 levels between reads of the frontier size, so the call waits
-// on its stream about once per 16 levels (levels after the frontier empties
-// cost one empty launch each).
+// records the claiming CSR slot as its tree edge. A large frontier gets one
+// grid launch per level (issued 16 at a time between reads of the frontier
+// size); while the frontier is small (long chains, the tail of a search) a
+// single workgroup runs level after level in one launch, synchronising at a
+// workgroup barrier instead of a kernel boundary, so sparse high-diameter
+// stretches do not cost a launch per level.
 #include "et_internal.hpp"
 
 namespace et {
@@ -25,6 +27,8 @@ namespace {
 constexpr int kB = 256;
 constexpr int kLanes = 16;          // lanes per frontier vertex / per row
 constexpr int kLevelsPerCheck = 16;
+constexpr int kSmallFrontier = 128;  // frontier size handled by the one-workgroup kernel
+constexpr int kSmallThreads = 1024;
 
 __global__ void k_fill32(int32_t* __restrict__ p, int64_t n, int32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -43,35 +47,88 @@ __global__ void k_bfs_seed(const int32_t* __restrict__ cc, int32_t n, int32_t* _
   }
 }
 
-// cnt[0] = current frontier size, cnt[1] = next frontier size
-__global__ __launch_bounds__(kB) void k_bfs_level(const int32_t* __restrict__ row_ptr,
-                                                 const int32_t* __restrict__ col, int32_t n, int32_t nnz,
-                                                 const int32_t* __restrict__ frontier, int32_t* __restrict__ next,
-                                                 int32_t* __restrict__ cnt, int32_t* par, int32_t* __restrict__ lvl,
-                                                 int32_t* __restrict__ pslot, int32_t level) {
-  const int32_t fsize = min(cnt[0], n);
-  const int sub = threadIdx.x & (kLanes - 1);
-  const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kLanes);
-  for (int64_t f = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLanes; f < fsize; f += groups) {
-    const int32_t u = frontier[f];
-    const int32_t a = min(max(row_ptr[u], 0), nnz), b = min(max(row_ptr[u + 1], a), nnz);
-    for (int64_t kk = (int64_t)a + sub; kk < b; kk += kLanes) {
-      const int32_t k = (int32_t)kk;
-      const int32_t w = col[k];
-      if ((uint32_t)w >= (uint32_t)n || w == u) continue;
-      if (__hip_atomic_load(par + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != -1) continue;
-      if (atomicCAS(par + w, -1, u) == -1) {
-        lvl[w] = level + 1;
-        pslot[w] = k;
-        next[atomicAdd(cnt + 1, 1)] = w;
-      }
+// cnt[0] = current frontier size, cnt[1] = next frontier size, cnt[2] = the
+// current level; the frontier of level l is in q0 for even l, q1 for odd l.
+__device__ __forceinline__ int32_t ldcnt(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// one frontier vertex per kLanes lanes: claim its unvisited neighbours
+__device__ __forceinline__ void bfs_expand(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                           int32_t n, int32_t nnz, int32_t u, int sub, int32_t level, int32_t* next,
+                                           int32_t* cnt, int32_t* par, int32_t* lvl, int32_t* pslot) {
+  const int32_t a = min(max(row_ptr[u], 0), nnz), b = min(max(row_ptr[u + 1], a), nnz);
+  for (int64_t kk = (int64_t)a + sub; kk < b; kk += kLanes) {
+    const int32_t k = (int32_t)kk;
+    const int32_t w = col[k];
+    if ((uint32_t)w >= (uint32_t)n || w == u) continue;
+    if (ldcnt(par + w) != -1) continue;
+    if (atomicCAS(par + w, -1, u) == -1) {
+      lvl[w] = level + 1;
+      pslot[w] = k;
+      next[atomicAdd(cnt + 1, 1)] = w;
     }
   }
+}
+
+__global__ __launch_bounds__(kB) void k_bfs_level(const int32_t* __restrict__ row_ptr,
+                                                 const int32_t* __restrict__ col, int32_t n, int32_t nnz, int32_t* q0,
+                                                 int32_t* q1, int32_t* cnt, int32_t* par, int32_t* __restrict__ lvl,
+                                                 int32_t* __restrict__ pslot) {
+  const int32_t fsize = min(cnt[0], n);
+  const int32_t level = cnt[2];
+  const int32_t* frontier = (level & 1) ? q1 : q0;
+  int32_t* next = (level & 1) ? q0 : q1;
+  const int sub = threadIdx.x & (kLanes - 1);
+  const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kLanes);
+  for (int64_t f = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kLanes; f < fsize; f += groups)
+    bfs_expand(row_ptr, col, n, nnz, frontier[f], sub, level, next, cnt, par, lvl, pslot);
 }
 
 __global__ void k_bfs_advance(int32_t* __restrict__ cnt) {
   cnt[0] = cnt[1];
   cnt[1] = 0;
+  cnt[2] += 1;
+}
+
+// one workgroup, many levels: runs while the frontier is non-empty and at
+// most kSmallFrontier vertices; every level ends at a workgroup barrier.
+// Thread 0 reads the frontier size and level and broadcasts them through
+// LDS, so every thread takes the same exit at the same barrier. Stores are
+// fenced at device scope before each barrier and read back with device-scope
+// loads. Each pass advances the level and claims every vertex at most once,
+// so the loop ends after at most n passes.
+__global__ __launch_bounds__(kSmallThreads) void k_bfs_small(const int32_t* __restrict__ row_ptr,
+                                                            const int32_t* __restrict__ col, int32_t n, int32_t nnz,
+                                                            int32_t* q0, int32_t* q1, int32_t* cnt, int32_t* par,
+                                                            int32_t* __restrict__ lvl, int32_t* __restrict__ pslot) {
+  __shared__ int32_t s_fsize, s_level;
+  const int sub = threadIdx.x & (kLanes - 1);
+  const int group = threadIdx.x / kLanes;
+  constexpr int kGroups = kSmallThreads / kLanes;
+  for (int32_t pass = 0; pass <= n; ++pass) {
+    if (threadIdx.x == 0) {
+      s_fsize = ldcnt(cnt);
+      s_level = ldcnt(cnt + 2);
+    }
+    __syncthreads();
+    const int32_t fsize = s_fsize, level = s_level;
+    if (fsize == 0 || fsize > kSmallFrontier) break;  // the same value in every thread
+    const int32_t* frontier = (level & 1) ? q1 : q0;
+    int32_t* next = (level & 1) ? q0 : q1;
+    for (int32_t f = group; f < fsize; f += kGroups)
+      bfs_expand(row_ptr, col, n, nnz, __hip_atomic_load(frontier + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                 sub, level, next, cnt, par, lvl, pslot);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(cnt, ldcnt(cnt + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(cnt + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(cnt + 2, level + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+    }
+    __syncthreads();
+  }
 }
 
 // both slots of every tree edge in the bitmask: the claiming slot in the
@@ -204,28 +261,35 @@ int ck_bfs_forest(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n,
   const int gn = ceil_div(n, kB);
   hipLaunchKernelGGL(k_fill32, dim3(std::min(gn, 4096)), dim3(kB), 0, s, par, (int64_t)n, -1);
   hipLaunchKernelGGL(k_fill32, dim3(std::min(gn, 4096)), dim3(kB), 0, s, lvl, (int64_t)n, -1);
-  hipLaunchKernelGGL(k_fill32, dim3(1), dim3(kB), 0, s, cnt, (int64_t)4, 0);
+  hipLaunchKernelGGL(k_fill32, dim3(1), dim3(kB), 0, s, cnt, (int64_t)4, 0);  // sizes and level 0
   hipLaunchKernelGGL(k_bfs_seed, dim3(gn), dim3(kB), 0, s, cc, n, par, lvl, q0, cnt);
   // a frontier of f vertices needs f * kLanes lanes; the grid strides over larger ones
   const int grid = std::max(1, std::min(ceil_div((int64_t)n * kLanes, kB), 8192));
   int rc = ET_OK;
-  int32_t level = 0;
   {
     ET_PROF(c, s, "k_bfs_level");
-    for (bool done = false; !done && level < n;) {
-      for (int j = 0; j < kLevelsPerCheck; ++j, ++level) {
-        int32_t* cur = (level & 1) ? q1 : q0;
-        int32_t* nxt = (level & 1) ? q0 : q1;
-        hipLaunchKernelGGL(k_bfs_level, dim3(grid), dim3(kB), 0, s, row_ptr, col, n, nnz, cur, nxt, cnt, par, lvl,
-                           pslot, level);
-        hipLaunchKernelGGL(k_bfs_advance, dim3(1), dim3(1), 0, s, cnt);
-      }
+    // every round either ends the search, runs small levels until the frontier
+    // grows or empties, or runs kLevelsPerCheck grid levels: at most n rounds
+    for (int32_t round = 0; round <= n; ++round) {
       if (hipMemcpyAsync(h_cnt, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess) {
         rc = ET_EHIP;
         break;
       }
-      done = (*h_cnt == 0);
+      const int32_t f = *h_cnt;
+      if (f == 0) break;
+      if (f <= kSmallFrontier) {
+        hipLaunchKernelGGL(k_bfs_small, dim3(1), dim3(kSmallThreads), 0, s, row_ptr, col, n, nnz, q0, q1, cnt, par,
+                           lvl, pslot);
+      } else {
+        // size the grid for a frontier up to 8x the one just read (larger ones stride)
+        const int g = std::max(64, std::min(ceil_div((int64_t)f * 8 * kLanes, kB), grid));
+        for (int j = 0; j < kLevelsPerCheck; ++j) {
+          hipLaunchKernelGGL(k_bfs_level, dim3(g), dim3(kB), 0, s, row_ptr, col, n, nnz, q0, q1, cnt, par, lvl,
+                             pslot);
+          hipLaunchKernelGGL(k_bfs_advance, dim3(1), dim3(1), 0, s, cnt);
+        }
+      }
     }
   }
   (void)hipHostFree(h_cnt);
