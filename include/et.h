@@ -88,6 +88,11 @@ int et_ctx_set_param(et_ctx* ctx, const char* name, int64_t value);
  * this context is bracketed by a pair of HIP events on its stream. */
 int et_ctx_profile(et_ctx* ctx, int enable);
 
+/* Restrict that timing to the launches of one kernel (its name as reported
+ * by et_ctx_profile_read, copied); NULL or "" times every kernel again.
+ * Timing few launches keeps the events' own cost out of the work measured. */
+int et_ctx_profile_only(et_ctx* ctx, const char* kernel_name);
+
 /* Wait for stream s, then write a JSON object into h_buf (NUL-terminated,
  * at most buflen bytes): {"kernel": [launches, total_ms, max_ms], ...} over
  * the launches timed since the previous read; clears the records. Returns

@@ -152,6 +152,12 @@ int et_ctx_profile(et_ctx* ctx, int enable) {
   return ET_OK;
 }
 
+int et_ctx_profile_only(et_ctx* ctx, const char* kernel_name) {
+  if (!ctx) return ET_EINVAL;
+  ctx->impl.prof_only = kernel_name ? kernel_name : "";
+  return ET_OK;
+}
+
 int et_ctx_profile_read(et_ctx* ctx, hipStream_t s, char* h_buf, int32_t buflen) {
   if (!ctx || !h_buf || buflen < 3) return ET_EINVAL;
   Ctx* c = &ctx->impl;

@@ -8,6 +8,7 @@
 
 #include <cstddef>
 #include <map>
+#include <string>
 #include <vector>
 
 #include "../../include/et.h"
@@ -50,6 +51,7 @@ struct Ctx {
   // kernel timing: when enabled, every instrumented launch is bracketed by
   // a pair of events on its stream
   bool profiling = false;
+  std::string prof_only;  // time only this kernel when non-empty
   std::vector<ProfRec> prof;
   std::vector<hipEvent_t> spare_events;
   uint32_t* d_status = nullptr;      // accumulated status bits
@@ -75,7 +77,7 @@ struct ProfScope {
   const char* name;
   hipEvent_t a = nullptr;
   ProfScope(Ctx* ctx, hipStream_t st, const char* nm) : c(ctx), s(st), name(nm) {
-    if (c->profiling) {
+    if (c->profiling && (c->prof_only.empty() || c->prof_only == nm)) {
       a = prof_event(c);
       if (a) (void)hipEventRecord(a, s);
     }

@@ -30,6 +30,7 @@ _SIG = {
     "et_ctx_status": ([_P, _P], ctypes.c_int),
     "et_ctx_status_bits": ([_P, _P, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
     "et_ctx_profile": ([_P, ctypes.c_int], ctypes.c_int),
+    "et_ctx_profile_only": ([_P, ctypes.c_char_p], ctypes.c_int),
     "et_ctx_set_param": ([_P, ctypes.c_char_p, _i64], ctypes.c_int),
     "et_ctx_profile_read": ([_P, _P, ctypes.c_char_p, _i32], ctypes.c_int),
     "et_list_rank": ([_P, _P, _i32, _P, _i32, _P, _P], ctypes.c_int),
@@ -126,8 +127,10 @@ class Context:
         """Set a tunable launch parameter (see et_ctx_set_param in et.h)."""
         _check(_lib.et_ctx_set_param(self._h, name.encode(), int(value)), f"et_ctx_set_param({name})")
 
-    def profile(self, enable=True):
-        """Bracket every later kernel launch on this context with HIP events."""
+    def profile(self, enable=True, only=None):
+        """Bracket every later kernel launch on this context with HIP events
+        (only the launches of kernel ``only`` when given)."""
+        _check(_lib.et_ctx_profile_only(self._h, only.encode() if only else None), "et_ctx_profile_only")
         _check(_lib.et_ctx_profile(self._h, 1 if enable else 0), "et_ctx_profile")
 
     def profile_read(self):
