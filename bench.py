@@ -249,6 +249,17 @@ def main():
                 rate = traffic / (avg_ms * 1e-3) / 1e9
                 roofline["traffic_GBps"] = rate
                 roofline["traffic_frac"] = rate / HBM_PEAK_GBS
+                copy = probe_ceiling("copy", 27, "GB_per_s")        # measured stream-copy peak
+                if copy:
+                    roofline["copy_GBps"] = copy
+                    roofline["traffic_frac_of_copy"] = rate / copy
+            # the walk is a dependent random read per unit: compare with the
+            # measured random-access ceiling of this GPU (probe/ceiling.hip)
+            ceil = probe_ceiling("chase+w8" if dom.startswith("k_walk1") else "gather")
+            if ceil:
+                roofline["units_per_s"] = units_per_launch / (avg_ms * 1e-3)
+                roofline["random_ceiling_per_s"] = ceil
+                roofline["random_frac"] = roofline["units_per_s"] / ceil
         else:
             roofline = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": None, "traffic": traffic, "avg_launch_ms": avg_ms}
@@ -579,6 +590,21 @@ def serving(args, dev):
                          for m in ("p50_ms", "p99_ms", "jobs_per_s", "wall_s")}})
     res["sweep"] = sweep
     return res
+
+
+def probe_ceiling(name, log2n=25, field="elements_per_s"):
+    """One figure of a probe of probe/ceiling.hip (copy, gather, dependent
+    chase, chase with an 8-byte store) from its committed summary
+    (profiles/random_access_ceiling.txt)."""
+    path = os.path.join(ROOT, "profiles", "random_access_ceiling.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("{"):
+            rec = json.loads(line)
+            if rec.get("probe") == name and rec.get("log2n") == log2n:
+                return rec[field]
+    return None
 
 
 def measured_traffic(kernel):
