@@ -64,6 +64,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-tree batched vs plain comparison")
     ap.add_argument("--batch-trees", type=int, default=4096)
+    ap.add_argument("--batch-graphs", type=int, default=1024)
     ap.add_argument("--no-serve", action="store_true", help="skip the served vs plain trace replay")
     ap.add_argument("--no-engines", action="store_true",
                     help="skip the Inlabel vs RMQ query engine comparison (and the scale-free tree)")
@@ -294,6 +295,9 @@ def main():
     if not args.no_batch:
         log("batched forest: generating")
         result["components"]["batched"] = batched_vs_plain(args, et, ctx, d, dev)
+    if not args.no_batch:
+        log("batched graphs: generating")
+        result["components"]["bridges_batched"] = bridges_batched_vs_plain(args, et, ctx, d)
     if not args.no_engines:
         log("query engines: Inlabel vs RMQ, scale-free tree")
         result["components"]["query_engines"] = query_engines(args, et, ctx, d, d_parent, d_qx, d_qy, grasps)
@@ -560,6 +564,55 @@ def batched_vs_plain(args, et, ctx, d, dev):
             "batched_queries_per_s": q / (res["batched"]["gpu_ms"] * 1e-3),
             "speedup": res["plain"]["gpu_ms"] / res["batched"]["gpu_ms"],
             "graph_ms": res["graph"]["gpu_ms"], "graph_matches_eager": graph_ok}
+
+
+def bridges_batched_vs_plain(args, et, ctx, d):
+    """1024 graphs of log-uniform size in [2^6, 2^14] vertices (average
+    degree 8, a few planted bridge chains each): one et_bridges_batch call
+    versus one et_bridges call per graph, same stream; the per-graph masks
+    of the two must agree."""
+    import torch
+    import gen
+    t0 = time.time()
+    rng = np.random.default_rng(args.seed + 17)
+    graphs = []
+    for t in range(args.batch_graphs):
+        n = int(2 ** rng.uniform(6, 14))
+        chains = max(1, n // 512)
+        rp, col, _ = gen.planted_bridge_graph(n=n, m=4 * n, chains=chains, max_chain=max(2, n // (8 * chains)),
+                                              seed=args.seed * 7919 + t)
+        graphs.append((d(rp), d(col)))
+    nv = sum(g[0].numel() - 1 for g in graphs)
+    m = sum(g[1].numel() for g in graphs) // 2
+    log(f"batched graphs: {len(graphs)} graphs, {nv} vertices, {m} edges in {time.time() - t0:.1f}s")
+    # concatenated inputs made once, as a caller holding a batch would have them
+    rows = torch.cat([g[0] for g in graphs])
+    cols = torch.cat([g[1] for g in graphs])
+    vs = np.concatenate([[0], np.cumsum([g[0].numel() - 1 for g in graphs])])
+    ss = np.concatenate([[0], np.cumsum([g[1].numel() for g in graphs])])
+    voff = torch.from_numpy(vs.astype(np.int64)).cuda()
+    soff = torch.from_numpy(ss.astype(np.int64)).cuda()
+    slots = np.diff(ss).tolist()
+    mask_b = {}
+    masks_p = [None] * len(graphs)
+
+    def batched():
+        mask_b["m"], mask_b["spans"], _ = et.et_bridges_batch(row_ptr=rows, col=cols, voff=voff, soff=soff,
+                                                              slots=slots, ctx=ctx, counts=False)
+
+    def plain():
+        for i, (rp, col) in enumerate(graphs):
+            masks_p[i], _ = et.et_bridges(rp, col, ctx=ctx, count=False)
+
+    res = {}
+    for name, fn, reps in (("batched", batched, 5), ("plain", plain, 1)):
+        res[name] = _gpu_ms(fn, reps)
+    ctx.check()
+    ok = all(torch.equal(mask_b["m"][a:a + w], masks_p[i][:w]) for i, (a, w) in enumerate(mask_b["spans"]))
+    return {"graphs": len(graphs), "vertices": nv, "edges": m, "batched_ms": res["batched"],
+            "plain_ms": res["plain"], "batched_edges_per_s": m / (res["batched"] * 1e-3),
+            "plain_edges_per_s": m / (res["plain"] * 1e-3), "speedup": res["plain"] / res["batched"],
+            "masks_equal": ok}
 
 
 def serving(args, dev):

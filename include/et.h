@@ -291,7 +291,38 @@ int et_bridges(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col, int3
 int et_bridges_ck(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col, int32_t n, int32_t nnz,
                   int32_t spanning, uint32_t* d_mask, int64_t* h_count, hipStream_t s);
 
-/* Device-side bridge count of the most recent et_bridges call on ctx
+/*
+ * Bridges of a batch of independent graphs in one pass (the bridge problem
+ * of Section 4 for many instances at once, as the tree batch of Section 3.3
+ * does for LCA). The batch runs as the disjoint union of its graphs, so
+ * every graph gets the answer et_bridges gives it alone.
+ *   d_row_ptr[n_total + n_graphs]  the graphs' own row-pointer arrays back to
+ *                  back: graph t's n_t + 1 entries (0 .. nnz_t) start at
+ *                  d_voff[t] + t
+ *   d_col[nnz_total]  the graphs' column arrays back to back, ids local to
+ *                  each graph; each graph a symmetric CSR as for et_bridges
+ *   d_voff[n_graphs + 1], d_soff[n_graphs + 1]  device int64 vertex and slot
+ *                  offsets: graph t owns vertices [voff[t], voff[t+1]) and
+ *                  slots [soff[t], soff[t+1]); both start at 0 and end at
+ *                  n_total and nnz_total; empty graphs are allowed
+ *   d_mask[mask_words]  output, one word-aligned mask per graph: graph t's
+ *                  ceil(nnz_t / 32) words follow those of graphs 0 .. t-1,
+ *                  and its bit k is set iff its slot k belongs to a bridge.
+ *                  mask_words >= the sum of ceil(nnz_t / 32); words past
+ *                  that sum are zeroed
+ *   d_counts[n_graphs]  optional device output: bridges per graph
+ * n_total < 2^30, nnz_total < 2^31. Offsets that do not match the row
+ * pointers, a column outside its own graph, or a mask_words below the
+ * sum set ET_EINPUT in ctx's status (outputs are then undefined).
+ * Scratch: n_total + 1 + nnz_total int32 and ceil(nnz_total / 32) words
+ * beyond what et_bridges takes for the union.
+ */
+int et_bridges_batch(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col, const int64_t* d_voff,
+                     const int64_t* d_soff, int32_t n_graphs, int32_t n_total, int32_t nnz_total,
+                     uint32_t* d_mask, int64_t mask_words, int64_t* d_counts, hipStream_t s);
+
+/* Device-side bridge count of the most recent et_bridges call (for a batch:
+ * the total over its graphs) on ctx
  * (written to a caller-owned device int64). */
 int et_bridges_count(et_ctx* ctx, int64_t* d_count, hipStream_t s);
 

@@ -379,6 +379,16 @@ int et_bridges(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col, int3
   return ET_OK;
 }
 
+int et_bridges_batch(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col, const int64_t* d_voff,
+                     const int64_t* d_soff, int32_t n_graphs, int32_t n_total, int32_t nnz_total, uint32_t* d_mask,
+                     int64_t mask_words, int64_t* d_counts, hipStream_t s) {
+  if (!ctx || n_graphs < 1 || n_total < 0 || n_total >= (1 << 30) || nnz_total < 0 || mask_words < 0) return ET_EINVAL;
+  if (!d_row_ptr || !d_voff || !d_soff || (mask_words > 0 && !d_mask)) return ET_EINVAL;
+  if (nnz_total > 0 && (!d_col || n_total == 0 || mask_words == 0)) return ET_EINVAL;
+  return et::bridges_batch_run(&ctx->impl, d_row_ptr, d_col, d_voff, d_soff, n_graphs, n_total, nnz_total, d_mask,
+                               mask_words, d_counts, s);
+}
+
 int et_levels(et_ctx* ctx, const int32_t* d_parent, int32_t n, int32_t* d_level, hipStream_t s) {
   if (!ctx || n < 1 || n >= (1 << 30) || !d_parent || !d_level) return ET_EINVAL;
   return et::levels_run(&ctx->impl, d_parent, n, d_level, s);

@@ -29,6 +29,7 @@ enum : uint32_t {
   ST_BAD_QUERY = 1u << 6,    // query id out of range
   ST_BAD_CSR = 1u << 7,      // CSR not symmetric / column out of range / rows unsorted
   ST_BAD_INDEX = 1u << 8,    // a gathered table index failed its bounds check
+  ST_OUT_SIZE = 1u << 9,     // a caller's output buffer is smaller than the result
 };
 
 // ---------------------------------------------------------------- context
@@ -200,6 +201,10 @@ int ck_mark(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32
             hipStream_t s);
 int bridges_ck_bfs(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t nnz, uint32_t* mask,
                    hipStream_t s);
+// bridges_batch.hip: a batch of graphs as one disjoint union
+int bridges_batch_run(Ctx* c, const int32_t* rows, const int32_t* col, const int64_t* voff, const int64_t* soff,
+                      int32_t T, int32_t V, int32_t nnz, uint32_t* mask, int64_t mask_words, int64_t* counts,
+                      hipStream_t s);
 // rmq.hip: LCA by range minima over the Euler tour
 int tree_rmq_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s);
 int tree_lca_rmq(Ctx* c, const et_tree* t, const int32_t* qx, const int32_t* qy, int64_t q, int32_t* out,

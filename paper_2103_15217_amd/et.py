@@ -44,6 +44,7 @@ _SIG = {
     "et_lca": ([_P, _P, _P, _i64, _P, _P], ctypes.c_int),
     "et_bridges": ([_P, _P, _P, _i32, _i32, _P, ctypes.POINTER(_i64), _P], ctypes.c_int),
     "et_bridges_count": ([_P, _P, _P], ctypes.c_int),
+    "et_bridges_batch": ([_P, _P, _P, _P, _P, _i32, _i32, _i32, _P, _i64, _P, _P], ctypes.c_int),
     "et_bridges_ck": ([_P, _P, _P, _i32, _i32, _i32, _P, ctypes.POINTER(_i64), _P], ctypes.c_int),
     "et_levels": ([_P, _P, _i32, _P, _P], ctypes.c_int),
     "et_tree_build_edges": ([_P, _P, _P, _i32, _i32, _P, _P, ctypes.POINTER(_P)], ctypes.c_int),
@@ -62,6 +63,7 @@ STATUS_BITS = {
     1 << 0: "bad parent", 1 << 1: "root count", 1 << 2: "unreached element",
     1 << 3: "bad successor", 1 << 4: "bad head", 1 << 5: "walk bound exceeded",
     1 << 6: "bad query", 1 << 7: "bad CSR", 1 << 8: "table index out of range",
+    1 << 9: "output buffer too small",
 }
 
 
@@ -345,6 +347,53 @@ def et_bridges(row_ptr, col, mask=None, ctx=None, count=True):
     _check(_lib.et_bridges(ctx.handle, _ptr(row_ptr), _ptr(col), n, nnz, _ptr(mask),
                            ctypes.byref(c) if count else None, _stream()), "et_bridges")
     return mask, (int(c.value) if count else None)
+
+
+def et_bridges_batch(graphs=None, *, row_ptr=None, col=None, voff=None, soff=None, slots=None, mask=None,
+                     ctx=None, counts=True):
+    """Bridges of a batch of graphs in one pass. Either ``graphs``, a list of
+    (row_ptr, col) device pairs with local ids, or the concatenated arrays
+    ``row_ptr`` (each graph's n_t + 1 entries back to back), ``col`` and
+    int64 device offsets ``voff`` / ``soff`` (n_graphs + 1 each), with the
+    host list ``slots`` of slot counts per graph (read back from ``soff``
+    when absent) to size the output. Returns the per-graph word-aligned
+    masks as one int32 tensor, the list of each graph's (start, words) in
+    it, and with ``counts`` a device int64 tensor of bridges per graph."""
+    ctx = ctx or default_context()
+    if graphs is not None:
+        rps = [_dev(g[0], torch.int32, "row_ptr") for g in graphs]
+        cols = [_dev(g[1], torch.int32, "col") for g in graphs]
+        dev = rps[0].device
+        vs = [r.numel() - 1 for r in rps]
+        ss = [c.numel() for c in cols]
+        row_ptr = torch.cat(rps)
+        col = torch.cat(cols) if sum(ss) else torch.empty(0, dtype=torch.int32, device=dev)
+        # offsets go up from pinned memory without waiting for the stream
+        voff = torch.tensor([0] + vs, dtype=torch.int64).cumsum(0).pin_memory().to(dev, non_blocking=True)
+        soff = torch.tensor([0] + ss, dtype=torch.int64).cumsum(0).pin_memory().to(dev, non_blocking=True)
+    else:
+        row_ptr = _dev(row_ptr, torch.int32, "row_ptr")
+        col = _dev(col, torch.int32, "col")
+        voff = _dev(voff, torch.int64, "voff")
+        soff = _dev(soff, torch.int64, "soff")
+        if soff.numel() != voff.numel():
+            raise ValueError("voff and soff must have the same length")
+        ss = list(slots) if slots is not None else torch.diff(soff).cpu().tolist()
+    T = len(ss)
+    n_total = row_ptr.numel() - T
+    nnz = col.numel()
+    words = [(x + 31) // 32 for x in ss]
+    starts = [0]
+    for w in words[:-1]:
+        starts.append(starts[-1] + w)
+    total = sum(words)
+    if mask is None:
+        mask = torch.empty(max(total, 1), dtype=torch.int32, device=col.device)
+    out = torch.empty(T, dtype=torch.int64, device=col.device) if counts else None
+    _check(_lib.et_bridges_batch(ctx.handle, _ptr(row_ptr), _ptr(col), _ptr(voff), _ptr(soff), T, n_total, nnz,
+                                 _ptr(mask), mask.numel(), _ptr(out) if counts else None, _stream()),
+           "et_bridges_batch")
+    return mask, list(zip(starts, words)), out
 
 
 def et_bridges_ck(row_ptr, col, spanning="bfs", mask=None, ctx=None, count=True):

@@ -158,7 +158,8 @@ class PlainExecutor:
 class ServedExecutor:
     """Continuous batching with a resident-tree cache and memory admission."""
 
-    def __init__(self, dpool, streams=4, budget_bytes=8 << 30, keep_results=False, max_batch=64):
+    def __init__(self, dpool, streams=4, budget_bytes=8 << 30, keep_results=False, max_batch=64,
+                 bridge_batch=True):
         self.dpool = dpool
         self.streams = [torch.cuda.Stream() for _ in range(streams)]
         self.ctxs = []
@@ -169,6 +170,7 @@ class ServedExecutor:
         self.budget = budget_bytes
         self.keep = keep_results
         self.max_batch = max_batch
+        self.bridge_batch = bridge_batch  # waiting bridge jobs go out as one et_bridges_batch call
         self.results = {}
         # resident batches: bid -> {"tree": Tree, "items": [...], "bytes": b, "ready": event, "pins": k}
         self.batches = collections.OrderedDict()
@@ -230,6 +232,35 @@ class ServedExecutor:
         self.resident += need
         return bid
 
+    def _launch_bridges(self, bjobs, inflight):
+        """All waiting bridge jobs that fit the memory budget in one batched
+        call (each graph's result is its word-aligned slice of the batch
+        mask); returns the jobs left for the next pass."""
+        need, take = 0, 0
+        for j in bjobs[: self.max_batch]:
+            b = self.dpool["graph_sizes"][j.item][1] * BRIDGE_BYTES_PER_SLOT
+            if not self._evict_for(need + b):
+                break
+            need += b
+            take += 1
+        if take == 0:
+            if not self._admit(self.dpool["graph_sizes"][bjobs[0].item][1] * BRIDGE_BYTES_PER_SLOT):
+                return bjobs
+            take = 1
+        batch, rest = bjobs[:take], bjobs[take:]
+        st = self.streams[self.rr % len(self.streams)]
+        ctx = self.ctxs[self.rr % len(self.ctxs)]
+        self.rr += 1
+        with torch.cuda.stream(st):
+            mask, spans, _ = et.et_bridges_batch([self.dpool["graphs"][j.item] for j in batch], ctx=ctx,
+                                                 counts=False)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        for j, (start, words) in zip(batch, spans):
+            inflight.append((j, ev, None, mask[start:start + words]))
+        self.active += len(batch)
+        return rest
+
     # ---------------------------------------------------------------- loop
     def run(self, jobs):
         lat = {}
@@ -269,6 +300,7 @@ class ServedExecutor:
             if missing:
                 self._build(missing)
             nxt = collections.deque()
+            bjobs = []
             for j in ready:
                 st = self.streams[self.rr % len(self.streams)]
                 ctx = self.ctxs[self.rr % len(self.ctxs)]
@@ -290,6 +322,8 @@ class ServedExecutor:
                     self.batches.move_to_end(bid)
                     inflight.append((j, ev, bid, out))
                     self.active += 1
+                elif self.bridge_batch:
+                    bjobs.append(j)
                 else:
                     n, nnz = self.dpool["graph_sizes"][j.item]
                     if not self._admit(nnz * BRIDGE_BYTES_PER_SLOT):
@@ -303,6 +337,8 @@ class ServedExecutor:
                         ev.record(st)
                     inflight.append((j, ev, None, out))
                     self.active += 1
+            if bjobs:
+                nxt.extend(self._launch_bridges(bjobs, inflight))
             ready = nxt
         wall = time.perf_counter() - t0
         torch.cuda.synchronize()

@@ -50,3 +50,6 @@ def test_host_argument_checks():
     assert lib.et_lca(None, None, None, 5, None, None) == -1
     lib.et_bridges.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_int32, P, P, P]
     assert lib.et_bridges(None, None, None, 5, 5, None, None, None) == -1
+    I32, I64 = ctypes.c_int32, ctypes.c_int64
+    lib.et_bridges_batch.argtypes = [P, P, P, P, P, I32, I32, I32, P, I64, P, P]
+    assert lib.et_bridges_batch(None, None, None, None, None, 1, 4, 8, None, 1, None, None) == -1
