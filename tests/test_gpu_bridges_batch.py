@@ -1,0 +1,175 @@
+"""GPU parity of et_bridges_batch: many graphs in one call (the bridge
+problem of Section 4 per instance). Each graph's word-aligned mask and count
+must equal the Tarjan DFS oracle's for that graph alone, bit for bit, and
+the plain et_bridges answer on the same graph."""
+import numpy as np
+import pytest
+
+import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    import paper_2103_15217_amd as et
+    assert torch.cuda.is_available()
+    return et
+
+
+def _dev(a, dtype=np.int32):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+def _empty_graph(n):
+    return np.zeros(n + 1, dtype=np.int32), np.zeros(0, dtype=np.int32)
+
+
+def check_batch(lib, oracle_mod, graphs, ctx=None, plain=False):
+    ctx = ctx or lib.default_context()
+    dg = [(_dev(rp), _dev(col)) for rp, col in graphs]
+    mask, spans, counts = lib.et_bridges_batch(dg, ctx=ctx)
+    ctx.check()
+    mask = mask.cpu().numpy().view(np.uint32)
+    counts = counts.cpu().numpy()
+    total = 0
+    for t, ((rp, col), (start, words)) in enumerate(zip(graphs, spans)):
+        ref_mask, ref_cnt = oracle_mod.bridges(rp, col)
+        assert words == len(ref_mask), t
+        assert np.array_equal(mask[start:start + words], ref_mask), f"graph {t}: mask"
+        assert counts[t] == ref_cnt, f"graph {t}: count"
+        total += ref_cnt
+        if plain:
+            m1, c1 = lib.et_bridges(dg[t][0], dg[t][1], ctx=ctx)
+            assert np.array_equal(m1.cpu().numpy().view(np.uint32)[:words], ref_mask) and c1 == ref_cnt
+    return mask, spans, total
+
+
+def test_tiny_multigraphs_one_call(lib, oracle_mod):
+    rng = np.random.default_rng(77)
+    graphs = []
+    for seed in range(300):
+        kind = int(rng.integers(10))
+        if kind == 0:
+            graphs.append(_empty_graph(0))                       # no vertex at all
+        elif kind == 1:
+            graphs.append(_empty_graph(int(rng.integers(1, 5))))  # vertices, no edge
+        else:
+            n = int(rng.integers(1, 14))
+            m = int(rng.integers(0, 20))
+            graphs.append(gen.random_multigraph(n, m, seed=seed, loops=True, multi=True))
+    check_batch(lib, oracle_mod, graphs)
+
+
+@pytest.mark.parametrize("T", [1, 2, 37])
+def test_mixed_sizes_match_plain(lib, oracle_mod, T):
+    rng = np.random.default_rng(T)
+    graphs = []
+    for t in range(T):
+        n = int(2 ** rng.uniform(4, 13))
+        deg = int(rng.integers(2, 12))
+        if rng.random() < 0.5:
+            graphs.append(gen.random_multigraph(n, n * deg // 2, seed=t, loops=True, multi=True))
+        else:
+            chains = max(1, n // 256)
+            rp, col, _ = gen.planted_bridge_graph(n=n, m=n * deg // 2, chains=chains,
+                                                  max_chain=max(2, n // (8 * chains)), seed=t)
+            graphs.append((rp, col))
+    check_batch(lib, oracle_mod, graphs, plain=True)
+
+
+def test_trees_and_cycles(lib, oracle_mod):
+    # every tree edge is a bridge, no cycle edge is: counts are closed forms
+    graphs, expect = [], []
+    for k in range(20):
+        n = 50 + 97 * k
+        if k % 2:
+            graphs.append(gen.tree_graph(gen.random_tree(n, [None, 3, 1][k % 3], seed=k)))
+            expect.append(n - 1)
+        else:
+            graphs.append(gen.cycle_graph(n))
+            expect.append(0)
+    ctx = lib.default_context()
+    _, _, counts = lib.et_bridges_batch([(_dev(a), _dev(b)) for a, b in graphs], ctx=ctx)
+    ctx.check()
+    assert counts.cpu().numpy().tolist() == expect
+    check_batch(lib, oracle_mod, graphs)
+
+
+def test_concatenated_arrays_form(lib, oracle_mod):
+    import torch
+    graphs = [gen.random_multigraph(n, 3 * n, seed=n) for n in (5, 1, 300, 64, 1000)]
+    graphs.insert(2, _empty_graph(0))
+    rows = np.concatenate([g[0] for g in graphs])
+    col = np.concatenate([g[1] for g in graphs])
+    voff = np.concatenate([[0], np.cumsum([len(g[0]) - 1 for g in graphs])])
+    soff = np.concatenate([[0], np.cumsum([len(g[1]) for g in graphs])])
+    ctx = lib.default_context()
+    mask, spans, counts = lib.et_bridges_batch(row_ptr=_dev(rows), col=_dev(col), voff=_dev(voff, np.int64),
+                                               soff=_dev(soff, np.int64), ctx=ctx)
+    ctx.check()
+    m2, spans2, _ = lib.et_bridges_batch(row_ptr=_dev(rows), col=_dev(col), voff=_dev(voff, np.int64),
+                                         soff=_dev(soff, np.int64), slots=np.diff(soff).tolist(), ctx=ctx)
+    ctx.check()
+    assert spans2 == spans and torch.equal(m2, mask)
+    mask = mask.cpu().numpy().view(np.uint32)
+    for t, (rp, c) in enumerate(graphs):
+        ref_mask, ref_cnt = oracle_mod.bridges(rp, c)
+        start, words = spans[t]
+        assert np.array_equal(mask[start:start + words], ref_mask)
+        assert counts[t].item() == ref_cnt
+
+
+def test_many_graphs_large_union(lib, oracle_mod):
+    # 1024 graphs, sizes log-uniform in [2^6, 2^14] (a few million vertices in all)
+    rng = np.random.default_rng(2024)
+    graphs = []
+    for t in range(1024):
+        n = int(2 ** rng.uniform(6, 14))
+        chains = max(1, n // 512)
+        rp, col, _ = gen.planted_bridge_graph(n=n, m=n * 4, chains=chains, max_chain=max(2, n // (8 * chains)),
+                                              seed=t)
+        graphs.append((rp, col))
+    print(f"[bridges batch] {sum(len(g[0]) - 1 for g in graphs)} vertices, "
+          f"{sum(len(g[1]) for g in graphs)} slots", flush=True)
+    check_batch(lib, oracle_mod, graphs)
+
+
+def test_pool_reuse_across_calls(lib, oracle_mod):
+    ctx = lib.Context()
+    for rep, T in enumerate([40, 3, 40, 1]):
+        graphs = [gen.random_multigraph(int(n), int(n) * 2, seed=rep * 100 + i)
+                  for i, n in enumerate(np.random.default_rng(rep).integers(1, 3000, size=T))]
+        check_batch(lib, oracle_mod, graphs, ctx=ctx)
+    ctx.close()
+
+
+def test_rejected_inputs(lib):
+    import torch
+    a = gen.cycle_graph(4)
+    b = gen.cycle_graph(5)
+    # a column outside its own graph (5 is a valid id of the union, not of graph 0)
+    bad_col = a[1].copy()
+    bad_col[0] = 5
+    ctx = lib.Context()
+    lib.et_bridges_batch([(_dev(a[0]), _dev(bad_col)), (_dev(b[0]), _dev(b[1]))], ctx=ctx)
+    with pytest.raises(lib.EtError):
+        ctx.check()
+    # vertex offsets that do not match the row-pointer arrays
+    rows = _dev(np.concatenate([a[0], b[0]]))
+    col = _dev(np.concatenate([a[1], b[1]]))
+    soff = _dev([0, len(a[1]), len(a[1]) + len(b[1])], np.int64)
+    lib.et_bridges_batch(row_ptr=rows, col=col, voff=_dev([0, 4, 10], np.int64), soff=soff, ctx=ctx)
+    with pytest.raises(lib.EtError):
+        ctx.check()
+    # an output buffer shorter than the per-graph masks need
+    lib.et_bridges_batch([(_dev(a[0]), _dev(a[1])), (_dev(b[0]), _dev(b[1]))], ctx=ctx,
+                         mask=torch.zeros(1, dtype=torch.int32, device="cuda"))
+    with pytest.raises(lib.EtError):
+        ctx.check()
+    # the context is usable again afterwards
+    lib.et_bridges_batch([(_dev(a[0]), _dev(a[1]))], ctx=ctx)
+    ctx.check()
+    ctx.close()
