@@ -609,10 +609,15 @@ def bridges_batched_vs_plain(args, et, ctx, d):
         res[name] = _gpu_ms(fn, reps)
     ctx.check()
     ok = all(torch.equal(mask_b["m"][a:a + w], masks_p[i][:w]) for i, (a, w) in enumerate(mask_b["spans"]))
+    g = et.BridgesBatchGraph(rows, cols, voff, soff, slots)
+    res["graph"] = _gpu_ms(g.replay, 5)
+    graph_ok = bool(torch.equal(g.mask, mask_b["m"]))
+    g.ctx.check()
+    g.close()
     return {"graphs": len(graphs), "vertices": nv, "edges": m, "batched_ms": res["batched"],
-            "plain_ms": res["plain"], "batched_edges_per_s": m / (res["batched"] * 1e-3),
+            "plain_ms": res["plain"], "graph_ms": res["graph"], "batched_edges_per_s": m / (res["batched"] * 1e-3),
             "plain_edges_per_s": m / (res["plain"] * 1e-3), "speedup": res["plain"] / res["batched"],
-            "masks_equal": ok}
+            "masks_equal": ok, "graph_matches_eager": graph_ok}
 
 
 def serving(args, dev):

@@ -448,11 +448,14 @@ class BatchGraph:
     calls allocate nothing; the captured tree stays alive with the graph
     (its tables are what the replays write). Every library fill is a kernel,
     so the graph holds no memset nodes. Inputs are read from the same
-    device buffers at every replay; results land in ``out``.
+    device buffers at every replay; results land in ``out``. The scratch
+    blocks the graph writes go back to the context's pool after capture, so
+    the context (a new one unless ``ctx`` is given) must run no other work
+    while the graph lives.
     """
 
     def __init__(self, parent, offsets, qtree, qx, qy, ctx=None):
-        self.ctx = ctx or default_context()
+        self.ctx = ctx or Context()
         self.inputs = (parent, offsets, qtree, qx, qy)
         warm = et_tree_build_batch(parent, offsets, ctx=self.ctx)
         warm.lca_batch(qtree, qx, qy)
@@ -474,3 +477,32 @@ class BatchGraph:
         if self.tree is not None:
             self.tree.free()
             self.tree = None
+
+
+class BridgesBatchGraph:
+    """A batched bridge call (et_bridges_batch on concatenated arrays)
+    captured once in a HIP graph and replayed as one launch; ``mask`` holds
+    the per-graph word-aligned masks (``spans`` gives each graph's words)
+    and ``counts`` the bridges per graph after every replay. Capture rules
+    as for BatchGraph: a warm-up call fills the pool first, and the context
+    (a new one unless ``ctx`` is given) runs no other work while the graph
+    lives."""
+
+    def __init__(self, row_ptr, col, voff, soff, slots, ctx=None):
+        self.ctx = ctx or Context()
+        self.inputs = (row_ptr, col, voff, soff)
+        slots = list(slots)
+        et_bridges_batch(row_ptr=row_ptr, col=col, voff=voff, soff=soff, slots=slots, ctx=self.ctx)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.mask, self.spans, self.counts = et_bridges_batch(row_ptr=row_ptr, col=col, voff=voff, soff=soff,
+                                                                  slots=slots, ctx=self.ctx)
+
+    def replay(self):
+        self.graph.replay()
+        return self.mask, self.counts
+
+    def close(self):
+        torch.cuda.synchronize()
+        self.graph = None
