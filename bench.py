@@ -336,6 +336,21 @@ def _gpu_ms(fn, reps=3):
     return best
 
 
+def _kernel_breakdown(ctx, fn, top=8):
+    """Per-kernel GPU time (ms, summed over launches) of one profiled call
+    of fn(): the ``top`` largest, plus their share of the call's kernel time."""
+    import torch
+    ctx.profile_read()
+    ctx.profile(True)
+    fn()
+    torch.cuda.synchronize()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ks = sorted(((k, v[1]) for k, v in prof.items() if not k.startswith("phase:")), key=lambda kv: -kv[1])
+    total = sum(v for _, v in ks)
+    return {"kernel_ms": {k: round(v, 4) for k, v in ks[:top]}, "kernels_total_ms": total}
+
+
 def query_engines(args, et, ctx, d, d_parent, d_qx, d_qy, grasps):
     """Inlabel against the RMQ engine over the Euler tour (Section 3) on the
     three bench trees and on a 2^log2n scale-free (Barabasi-Albert) tree
@@ -542,6 +557,7 @@ def batched_vs_plain(args, et, ctx, d, dev):
         e1.record(stream)
         torch.cuda.synchronize()
         res[name] = {"gpu_ms": e0.elapsed_time(e1) / reps, "wall_ms": (time.perf_counter() - w0) * 1e3 / reps}
+    res["breakdown"] = _kernel_breakdown(ctx, batched)
     g = et.BatchGraph(d_parent, d_off, d_qt, d_qx, d_qy, ctx=ctx)
     g.replay()
     torch.cuda.synchronize()
@@ -563,7 +579,7 @@ def batched_vs_plain(args, et, ctx, d, dev):
             "plain_nodes_per_s": nodes / (res["plain"]["gpu_ms"] * 1e-3),
             "batched_queries_per_s": q / (res["batched"]["gpu_ms"] * 1e-3),
             "speedup": res["plain"]["gpu_ms"] / res["batched"]["gpu_ms"],
-            "graph_ms": res["graph"]["gpu_ms"], "graph_matches_eager": graph_ok}
+            "graph_ms": res["graph"]["gpu_ms"], "graph_matches_eager": graph_ok, **res["breakdown"]}
 
 
 def bridges_batched_vs_plain(args, et, ctx, d):
@@ -609,6 +625,7 @@ def bridges_batched_vs_plain(args, et, ctx, d):
         res[name] = _gpu_ms(fn, reps)
     ctx.check()
     ok = all(torch.equal(mask_b["m"][a:a + w], masks_p[i][:w]) for i, (a, w) in enumerate(mask_b["spans"]))
+    res["breakdown"] = _kernel_breakdown(ctx, batched)
     g = et.BridgesBatchGraph(rows, cols, voff, soff, slots)
     res["graph"] = _gpu_ms(g.replay, 5)
     graph_ok = bool(torch.equal(g.mask, mask_b["m"]))
@@ -617,7 +634,7 @@ def bridges_batched_vs_plain(args, et, ctx, d):
     return {"graphs": len(graphs), "vertices": nv, "edges": m, "batched_ms": res["batched"],
             "plain_ms": res["plain"], "graph_ms": res["graph"], "batched_edges_per_s": m / (res["batched"] * 1e-3),
             "plain_edges_per_s": m / (res["plain"] * 1e-3), "speedup": res["plain"] / res["batched"],
-            "masks_equal": ok, "graph_matches_eager": graph_ok}
+            "masks_equal": ok, "graph_matches_eager": graph_ok, **res["breakdown"]}
 
 
 def serving(args, dev):

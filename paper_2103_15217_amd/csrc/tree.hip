@@ -264,6 +264,22 @@ __device__ __forceinline__ int32_t tree_of(const int64_t* __restrict__ off, int3
   return lo;
 }
 
+// Per-node passes over a batch: each lane takes kPerLane nodes a block
+// width apart, so its tree id only moves forward; it searches once at its
+// first node and again only when a node lies past its current tree.
+constexpr int kPerLane = 16;
+
+__device__ __forceinline__ int32_t tree_from(const int64_t* __restrict__ off, int32_t t, int32_t T, int64_t v) {
+  if (off[t + 1] > v) return t;
+  int32_t lo = t, hi = T;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 __global__ __launch_bounds__(kB) void k_lca_batch(const int4* __restrict__ rec, const int2* __restrict__ head,
                                                  int32_t n, const int64_t* __restrict__ off, int32_t T,
                                                  const int32_t* __restrict__ qt, const int32_t* __restrict__ qx,
@@ -299,25 +315,30 @@ __global__ __launch_bounds__(kB) void k_lca_batch(const int4* __restrict__ rec, 
 __global__ void k_batch_parent(const int32_t* __restrict__ parent, const int64_t* __restrict__ off, int32_t T,
                                int32_t N, int32_t* __restrict__ gp, int32_t* __restrict__ nroots,
                                int32_t* __restrict__ root_of, uint32_t* __restrict__ status) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v > N) return;
-  if (v == N) {
-    gp[N] = -1;
-    if (off[0] != 0 || off[T] != N) flag(status, ST_BAD_PARENT);
-    return;
-  }
-  const int32_t t = tree_of(off, T, v);
-  const int64_t base = off[t], nt = off[t + 1] - base;
-  const int32_t p = parent[v];
-  if (p == -1) {
-    gp[v] = N;
-    atomicAdd(nroots + t, 1);
-    root_of[t] = (int32_t)v;
-  } else if (p >= 0 && p < nt && base + p != v) {
-    gp[v] = (int32_t)(base + p);
-  } else {
-    flag(status, ST_BAD_PARENT);
-    gp[v] = N;
+  const int64_t first = (int64_t)blockIdx.x * blockDim.x * kPerLane + threadIdx.x;
+  if (first > N) return;
+  int32_t t = tree_of(off, T, min(first, (int64_t)N - 1));
+  for (int i = 0; i < kPerLane; ++i) {
+    const int64_t v = first + (int64_t)i * blockDim.x;
+    if (v > N) break;
+    if (v == N) {
+      gp[N] = -1;
+      if (off[0] != 0 || off[T] != N) flag(status, ST_BAD_PARENT);
+      break;
+    }
+    t = tree_from(off, t, T, v);
+    const int64_t base = off[t], nt = off[t + 1] - base;
+    const int32_t p = parent[v];
+    if (p == -1) {
+      gp[v] = N;
+      atomicAdd(nroots + t, 1);
+      root_of[t] = (int32_t)v;
+    } else if (p >= 0 && p < nt && base + p != v) {
+      gp[v] = (int32_t)(base + p);
+    } else {
+      flag(status, ST_BAD_PARENT);
+      gp[v] = N;
+    }
   }
 }
 
@@ -333,15 +354,20 @@ __global__ void k_export_batch(const int4* __restrict__ rec, const int32_t* __re
                                const int64_t* __restrict__ off, int32_t T, int32_t N,
                                const int32_t* __restrict__ root_of, int32_t* __restrict__ depth,
                                int32_t* __restrict__ pre, int32_t* __restrict__ size) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= N) return;
-  const int32_t t = tree_of(off, T, v);
-  const int32_t r = root_of[t];
-  const int4 rv = rec[v];
-  const int32_t rp = ((uint32_t)r < (uint32_t)N) ? rec[r].w : 0;
-  if (depth) depth[v] = rv.z - 1;
-  if (pre) pre[v] = rv.w - rp;
-  if (size) size[v] = size_in[v];
+  const int64_t first = (int64_t)blockIdx.x * blockDim.x * kPerLane + threadIdx.x;
+  if (first >= N) return;
+  int32_t t = tree_of(off, T, first);
+  for (int i = 0; i < kPerLane; ++i) {
+    const int64_t v = first + (int64_t)i * blockDim.x;
+    if (v >= N) break;
+    t = tree_from(off, t, T, v);
+    const int32_t r = root_of[t];
+    const int4 rv = rec[v];
+    const int32_t rp = ((uint32_t)r < (uint32_t)N) ? rec[r].w : 0;
+    if (depth) depth[v] = rv.z - 1;
+    if (pre) pre[v] = rv.w - rp;
+    if (size) size[v] = size_in[v];
+  }
 }
 
 }  // namespace
@@ -418,7 +444,8 @@ int tree_export(const et_tree* t, int32_t* succ, int32_t* rank, int32_t* depth, 
     if (succ || rank || inl || asc) return ET_EINVAL;  // global tables of a batch are internal
     const int32_t N = t->n - 1;
     if (depth || pre || size)
-      hipLaunchKernelGGL(k_export_batch, dim3(ceil_div(N, kB)), dim3(kB), 0, s, t->d_rec, t->d_size, t->d_off,
+      hipLaunchKernelGGL(k_export_batch, dim3(ceil_div(N, (int64_t)kB * kPerLane)), dim3(kB), 0, s, t->d_rec,
+                         t->d_size, t->d_off,
                          t->batch, N, t->d_root_of, depth, pre, size);
     return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
   }
@@ -454,7 +481,8 @@ int tree_build_batch(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_zero, dim3(ceil_div(T, kB)), dim3(kB), 0, s, nroots, T);
   {
     ET_PROF(c, s, "k_batch_parent");
-    hipLaunchKernelGGL(k_batch_parent, dim3(ceil_div((int64_t)N + 1, kB)), dim3(kB), 0, s, parent, t->d_off, T, N,
+    hipLaunchKernelGGL(k_batch_parent, dim3(ceil_div((int64_t)N + 1, (int64_t)kB * kPerLane)), dim3(kB), 0, s, parent,
+                       t->d_off, T, N,
                        gp, nroots, t->d_root_of, c->d_status);
   }
   hipLaunchKernelGGL(k_batch_check, dim3(ceil_div(T, kB)), dim3(kB), 0, s, t->d_off, T, nroots, c->d_status);
