@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--serve-sweep", default="1000,4000,8000",
                     help="extra arrival rates (jobs/s) replayed for 2 s each to show where each path saturates; "
                          "empty to skip")
+    ap.add_argument("--default-params", action="store_true",
+                    help="run with the library's default launch shapes instead of the autotuned ones")
     ap.add_argument("--no-kernel-times", action="store_true",
                     help="do not bracket kernels with events during the timed steps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -149,6 +151,14 @@ def main():
     d_out = torch.empty(q, dtype=torch.int32, device=dev)
     d_mask = torch.empty(max((len(col) + 31) // 32, 1), dtype=torch.int32, device=dev)
     ctx = et.default_context()
+    # launch shapes picked by the autotuner for this GPU (results never depend on them)
+    from paper_2103_15217_amd import autotune
+    launch = {"single": None, "batch": None}
+    if not args.default_params:
+        launch["single"] = autotune.apply(ctx, "single")
+    bctx = et.Context()
+    if not args.default_params:
+        launch["batch"] = autotune.apply(bctx, "batch")
     work = {"n": n, "q": q, "graph_n": gn, "graph_nnz": len(col), "graph_m": ginfo["m"]}
 
     stream = torch.cuda.current_stream()
@@ -236,7 +246,7 @@ def main():
     if dom and dom in timed:
         launches = timed[dom][0] / args.steps
         avg_ms = timed[dom][1] / timed[dom][0]
-        traffic = measured_traffic(dom)
+        traffic = measured_traffic(dom, launch["single"])
         if dom in ALG_BYTES:
             bpu, unit, units = ALG_BYTES[dom]
             units_per_launch = units(work)
@@ -286,6 +296,7 @@ def main():
             "graph_vertices": gn, "graph_edges": ginfo["m"], "graph_csr_slots": len(col),
             "seed": args.seed,
         },
+        "launch_params": launch,
         "components": components,
         "kernels_ms_per_step": {k: round(v[1], 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1][1])},
         "roofline": roofline,
@@ -294,10 +305,10 @@ def main():
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
     if not args.no_batch:
         log("batched forest: generating")
-        result["components"]["batched"] = batched_vs_plain(args, et, ctx, d, dev)
+        result["components"]["batched"] = batched_vs_plain(args, et, bctx, d, dev)
     if not args.no_batch:
         log("batched graphs: generating")
-        result["components"]["bridges_batched"] = bridges_batched_vs_plain(args, et, ctx, d)
+        result["components"]["bridges_batched"] = bridges_batched_vs_plain(args, et, bctx, d)
     if not args.no_engines:
         log("query engines: Inlabel vs RMQ, scale-free tree")
         result["components"]["query_engines"] = query_engines(args, et, ctx, d, d_parent, d_qx, d_qy, grasps)
@@ -682,9 +693,10 @@ def probe_ceiling(name, log2n=25, field="elements_per_s"):
     return None
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, params=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when none was taken or the kernel's source changed since."""
+    summary, or None when none was taken, the kernel's source changed since,
+    or it was taken with other launch parameters."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_2e24.json")
     if not os.path.exists(path):
@@ -694,6 +706,8 @@ def measured_traffic(kernel):
         return None
     src = os.path.join(ROOT, rec["source"])
     if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
+        return None
+    if rec.get("launch_params") != params:
         return None
     return rec["fetch_kib"] * 1024 * rec["fetch_factor"] + rec["write_kib"] * 1024 * rec["write_factor"]
 

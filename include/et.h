@@ -81,6 +81,10 @@ int et_ctx_status_bits(et_ctx* ctx, hipStream_t s, uint32_t* h_bits);
  *   "lr_per_wave1"  level 1: sublists owned by one wavefront (64..65536, default 256)
  *   "lr_kn_log2"    upper levels: one splitter per 2^v elements (1..10, default 3)
  *   "lr_per_waven"  upper levels: sublists per wavefront (64..65536, default 128)
+ *   "rmq_block_log2"  range-minimum blocks of 2^v positions for the bridge
+ *                   low / high tables and et_tree_rmq_build (5 or 6, default 5)
+ *   "query_block"   threads per workgroup of the LCA query kernels (a power
+ *                   of two in 64..1024, default 256)
  * Results never depend on them. ET_EINVAL for an unknown name or value. */
 int et_ctx_set_param(et_ctx* ctx, const char* name, int64_t value);
 

@@ -142,6 +142,9 @@ int et_ctx_set_param(et_ctx* ctx, const char* name, int64_t value) {
   else if (k == "lr_per_wave1" && value >= 64 && value <= 65536) lr.per_wave1 = (int)value;
   else if (k == "lr_kn_log2" && value >= 1 && value <= 10) lr.kn_log2 = (int)value;
   else if (k == "lr_per_waven" && value >= 64 && value <= 65536) lr.per_waven = (int)value;
+  else if (k == "rmq_block_log2" && (value == 5 || value == 6)) ctx->impl.qs.rmq_log = (int)value;
+  else if (k == "query_block" && value >= 64 && value <= et::kQueryBlockMax && (value & (value - 1)) == 0)
+    ctx->impl.qs.block = (int)value;
   else return ET_EINVAL;
   return ET_OK;
 }

@@ -33,7 +33,6 @@ namespace {
 
 constexpr int kB = 256;
 constexpr int kRowsPerBlock = 256;
-constexpr int kRmqLog = 5;  // 32-element RMQ blocks
 constexpr int kMaxGrid = 1 << 20;  // workgroups of a grid-stride launch (a dispatch holds < 2^32 work-items)
 
 __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
@@ -499,34 +498,38 @@ __global__ __launch_bounds__(kB) void k_minmax(const int32_t* __restrict__ row_p
   }
 }
 
-// In-block RMQ by suffix-extreme bitmasks: for position o of a 32-element
-// block, bit j <= o of mmin[o] is set iff element j is smaller than every
-// element after it up to o. The minimum of [l, o] is then the element at the
-// lowest set bit at or above l: that element is a suffix minimum and no
-// suffix minimum between l and it can be smaller. Likewise for maxima.
-// Lane o of each 32-lane group builds its two masks; lane 31 also yields
-// the block's extremes (level 0 of the sparse table).
+// In-block RMQ by suffix-extreme bitmasks: for position o of a block of
+// B = 2^LOG elements, bit j <= o of mmin[o] is set iff element j is smaller
+// than every element after it up to o. The minimum of [l, o] is then the
+// element at the lowest set bit at or above l: that element is a suffix
+// minimum and no suffix minimum between l and it can be smaller. Likewise
+// for maxima. Lane o of each B-lane group builds its two masks; lane B-1
+// also yields the block's extremes (level 0 of the sparse table).
+template <int LOG>
 __global__ __launch_bounds__(kB) void k_rmq_blocks(const int32_t* __restrict__ amin, const int32_t* __restrict__ amax,
-                                                  int32_t n, uint32_t* __restrict__ mmin, uint32_t* __restrict__ mmax,
+                                                  int32_t n, typename RmqMask<LOG>::type* __restrict__ mmin,
+                                                  typename RmqMask<LOG>::type* __restrict__ mmax,
                                                   int32_t* __restrict__ bmin, int32_t* __restrict__ bmax) {
+  using M = typename RmqMask<LOG>::type;
+  constexpr int B = 1 << LOG;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool ok = i < n;
   const int32_t vmin = ok ? amin[i] : INT32_MAX;
   const int32_t vmax = ok ? amax[i] : INT32_MIN;
-  const int o = __lane_id() & 31;
-  uint32_t fmin = 0, fmax = 0;
+  const int o = __lane_id() & (B - 1);
+  M fmin = 0, fmax = 0;
   int32_t rmin = INT32_MAX, rmax = INT32_MIN;
 #pragma unroll
-  for (int j = 31; j >= 0; --j) {
-    const int32_t x = __shfl(vmin, j, 32);
-    const int32_t y = __shfl(vmax, j, 32);
+  for (int j = B - 1; j >= 0; --j) {
+    const int32_t x = __shfl(vmin, j, B);
+    const int32_t y = __shfl(vmax, j, B);
     if (j <= o) {
       if (x < rmin) {
-        fmin |= 1u << j;
+        fmin |= (M)1 << j;
         rmin = x;
       }
       if (y > rmax) {
-        fmax |= 1u << j;
+        fmax |= (M)1 << j;
         rmax = y;
       }
     }
@@ -535,9 +538,9 @@ __global__ __launch_bounds__(kB) void k_rmq_blocks(const int32_t* __restrict__ a
     mmin[i] = fmin;
     mmax[i] = fmax;
   }
-  if (o == 31 && (i >> kRmqLog) < ((n + 31) >> kRmqLog)) {
-    bmin[i >> kRmqLog] = rmin;
-    bmax[i >> kRmqLog] = rmax;
+  if (o == B - 1 && (i >> LOG) < (((int64_t)n + B - 1) >> LOG)) {
+    bmin[i >> LOG] = rmin;
+    bmax[i >> LOG] = rmax;
   }
 }
 
@@ -550,31 +553,35 @@ __global__ void k_sparse_level(const int32_t* __restrict__ pmn, const int32_t* _
   qmx[b] = (o < nb) ? max(pmx[b], pmx[o]) : pmx[b];
 }
 
+template <int LOG>
 struct Rmq {
   const int32_t *amin, *amax;
-  const uint32_t *mmin, *mmax;
+  const typename RmqMask<LOG>::type *mmin, *mmax;
   const int32_t* stmin;  // sparse table levels concatenated: level k at k * nb
   const int32_t* stmax;
   int32_t nb;
 };
 
-// extremes of [l, r] inside one 32-element block, r's block
-__device__ __forceinline__ void rmq_in_block(const Rmq& q, int32_t l, int32_t r, int32_t* mn, int32_t* mx) {
-  const int32_t base = r & ~31;
-  const uint32_t keep = ~0u << (l - base);
-  *mn = q.amin[base + ctz32(q.mmin[r] & keep)];
-  *mx = q.amax[base + ctz32(q.mmax[r] & keep)];
+// extremes of [l, r] inside one block, r's block
+template <int LOG>
+__device__ __forceinline__ void rmq_in_block(const Rmq<LOG>& q, int32_t l, int32_t r, int32_t* mn, int32_t* mx) {
+  using M = typename RmqMask<LOG>::type;
+  const int32_t base = r & ~((1 << LOG) - 1);
+  const M keep = ~(M)0 << (l - base);
+  *mn = q.amin[base + RmqMask<LOG>::ctz(q.mmin[r] & keep)];
+  *mx = q.amax[base + RmqMask<LOG>::ctz(q.mmax[r] & keep)];
 }
 
-__device__ __forceinline__ void rmq(const Rmq& q, int32_t l, int32_t r, int32_t* lo, int32_t* hi) {
-  const int32_t bl = l >> kRmqLog, br = r >> kRmqLog;
+template <int LOG>
+__device__ __forceinline__ void rmq(const Rmq<LOG>& q, int32_t l, int32_t r, int32_t* lo, int32_t* hi) {
+  const int32_t bl = l >> LOG, br = r >> LOG;
   int32_t mn, mx;
   if (bl == br) {
     rmq_in_block(q, l, r, &mn, &mx);
   } else {
     int32_t a0, a1, b0, b1;
-    rmq_in_block(q, l, (bl << kRmqLog) + 31, &a0, &a1);
-    rmq_in_block(q, br << kRmqLog, r, &b0, &b1);
+    rmq_in_block(q, l, (bl << LOG) + (1 << LOG) - 1, &a0, &a1);
+    rmq_in_block(q, br << LOG, r, &b0, &b1);
     mn = min(a0, b0);
     mx = max(a1, b1);
     if (bl + 1 <= br - 1) {
@@ -592,8 +599,9 @@ __device__ __forceinline__ void rmq(const Rmq& q, int32_t l, int32_t r, int32_t*
 // one lane per preorder position i < (number of non-isolated vertices, the
 // last value of the preorder scan): the subtree interval starts at i, so
 // neighbouring lanes read neighbouring RMQ entries
+template <int LOG>
 __global__ __launch_bounds__(kB) void k_bridge_test(const int4* __restrict__ byp, const uint32_t* __restrict__ I,
-                                                   int32_t Lcap, int32_t n, Rmq q, uint32_t* __restrict__ mask,
+                                                   int32_t Lcap, int32_t n, Rmq<LOG> q, uint32_t* __restrict__ mask,
                                                    int64_t* __restrict__ count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t npre = min((int32_t)I[Lcap - 1], n);
@@ -716,9 +724,10 @@ int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, i
   int4* byp = sc.get<int4>(n);
   int32_t* amin = sc.get<int32_t>(n);
   int32_t* amax = sc.get<int32_t>(n);
-  uint32_t* mmin = sc.get<uint32_t>(n);
-  uint32_t* mmax = sc.get<uint32_t>(n);
-  const int32_t nb = (n + 31) >> kRmqLog;
+  const int rlog = c->qs.rmq_log;                        // range-minimum blocks of 2^rlog vertices
+  uint32_t* mmin = sc.get<uint32_t>((size_t)n << (rlog - 5));
+  uint32_t* mmax = sc.get<uint32_t>((size_t)n << (rlog - 5));
+  const int32_t nb = (int32_t)(((int64_t)n + (1 << rlog) - 1) >> rlog);
   int levels = 1;
   while ((1 << levels) <= nb) ++levels;
   int32_t* stmin = sc.get<int32_t>((size_t)levels * nb);
@@ -813,7 +822,11 @@ int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, i
   // 5. range extremes
   {
     ET_PROF(c, s, "k_rmq_blocks");
-    hipLaunchKernelGGL(k_rmq_blocks, dim3(gn), dim3(kB), 0, s, amin, amax, n, mmin, mmax, stmin, stmax);
+    if (rlog == 6)
+      hipLaunchKernelGGL(k_rmq_blocks<6>, dim3(gn), dim3(kB), 0, s, amin, amax, n, reinterpret_cast<uint64_t*>(mmin),
+                         reinterpret_cast<uint64_t*>(mmax), stmin, stmax);
+    else
+      hipLaunchKernelGGL(k_rmq_blocks<5>, dim3(gn), dim3(kB), 0, s, amin, amax, n, mmin, mmax, stmin, stmax);
   }
   for (int k = 1; k < levels; ++k) {
     ET_PROF(c, s, "k_sparse_level");
@@ -822,10 +835,16 @@ int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, i
                        stmax + (size_t)k * nb);
   }
   // 6. test
-  Rmq q{amin, amax, mmin, mmax, stmin, stmax, nb};
   {
     ET_PROF(c, s, "k_bridge_test");
-    hipLaunchKernelGGL(k_bridge_test, dim3(gn), dim3(kB), 0, s, byp, dw, Lcap, n, q, mask, c->d_bcount);
+    if (rlog == 6) {
+      Rmq<6> q{amin, amax, reinterpret_cast<const uint64_t*>(mmin), reinterpret_cast<const uint64_t*>(mmax), stmin,
+               stmax, nb};
+      hipLaunchKernelGGL(k_bridge_test<6>, dim3(gn), dim3(kB), 0, s, byp, dw, Lcap, n, q, mask, c->d_bcount);
+    } else {
+      Rmq<5> q{amin, amax, mmin, mmax, stmin, stmax, nb};
+      hipLaunchKernelGGL(k_bridge_test<5>, dim3(gn), dim3(kB), 0, s, byp, dw, Lcap, n, q, mask, c->d_bcount);
+    }
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }

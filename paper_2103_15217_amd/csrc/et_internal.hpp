@@ -46,9 +46,17 @@ struct LrShape {
   int per_waven = 128;   // upper levels: sublists per wavefront
 };
 
+// Range-minimum block size and query workgroup size (tunable per context).
+struct QueryShape {
+  int rmq_log = 5;   // range-minimum blocks of 2^rmq_log positions (5 or 6)
+  int block = 256;   // threads per workgroup of the LCA query kernels
+};
+constexpr int kQueryBlockMax = 1024;
+
 struct Ctx {
   int device = 0;
   LrShape lr;
+  QueryShape qs;
   // kernel timing: when enabled, every instrumented launch is bracketed by
   // a pair of events on its stream
   bool profiling = false;
@@ -136,6 +144,22 @@ __host__ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 
 __device__ __forceinline__ int msb32(uint32_t x) { return 31 - __clz((int)x); }
 __device__ __forceinline__ int ctz32(uint32_t x) { return __ffs((int)x) - 1; }
+__device__ __forceinline__ int ctz64(uint64_t x) { return __ffsll((unsigned long long)x) - 1; }
+
+// In-block range-minimum masks: one bit per position of a block of 2^LOG
+// positions (LOG 5: 32-bit words, LOG 6: 64-bit words, one wavefront).
+template <int LOG>
+struct RmqMask;
+template <>
+struct RmqMask<5> {
+  using type = uint32_t;
+  static __device__ __forceinline__ int ctz(uint32_t x) { return ctz32(x); }
+};
+template <>
+struct RmqMask<6> {
+  using type = uint64_t;
+  static __device__ __forceinline__ int ctz(uint64_t x) { return ctz64(x); }
+};
 
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
@@ -239,7 +263,8 @@ struct et_tree {
   int32_t from_edges;  // built by et_tree_build_edges (half-edge ids follow the edge list)
   // optional RMQ query engine (et_tree_rmq_build)
   uint64_t* d_rmq_e;     // [2(n-1)] {depth, node} after every tour half-edge
-  uint32_t* d_rmq_mask;  // [2(n-1)] in-block suffix-minimum masks
-  uint64_t* d_rmq_st;    // sparse table over 32-position block minima, level-major
+  void* d_rmq_mask;      // [2(n-1)] in-block suffix-minimum masks (32- or 64-bit words)
+  uint64_t* d_rmq_st;    // sparse table over the block minima, level-major
   int32_t rmq_nb;        // number of blocks
+  int32_t rmq_log;       // blocks of 2^rmq_log positions
 };

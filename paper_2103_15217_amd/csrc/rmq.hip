@@ -10,18 +10,18 @@
 // non-root nodes the LCA is the node of the smallest key in E between their
 // first visits; the root is the LCA of any pair that contains it.
 //
-// The minimum uses blocks of 32 positions: per position a 32-bit mask of
-// the block positions that are smaller than everything after them up to
-// this one (the minimum of [l, o] inside a block is then at the lowest set
-// bit at or above l), and a sparse table over the block minima. A query
-// reads two ranks, up to four keys, two masks and two table entries.
+// The minimum uses blocks of 2^LOG positions (32 or 64, a tunable of the
+// context): per position a mask of the block positions that are smaller
+// than everything after them up to this one (the minimum of [l, o] inside a
+// block is then at the lowest set bit at or above l), and a sparse table
+// over the block minima. A query reads two ranks, up to four keys, two
+// masks and two table entries.
 #include "et_internal.hpp"
 
 namespace et {
 namespace {
 
 constexpr int kB = 256;
-constexpr int kLog = 5;  // 32-position blocks
 
 __device__ __forceinline__ uint64_t ekey(int32_t depth, int32_t node) {
   return ((uint64_t)(uint32_t)depth << 32) | (uint32_t)node;
@@ -43,24 +43,28 @@ __global__ void k_rmq_euler(const int32_t* __restrict__ rank, const int4* __rest
   E[r.y] = ekey(d - 1, p);
 }
 
+template <int LOG>
 __global__ __launch_bounds__(kB) void k_rmq_masks(const uint64_t* __restrict__ E, int32_t L,
-                                                 uint32_t* __restrict__ mask, uint64_t* __restrict__ bmin) {
+                                                 typename RmqMask<LOG>::type* __restrict__ mask,
+                                                 uint64_t* __restrict__ bmin) {
+  using M = typename RmqMask<LOG>::type;
+  constexpr int B = 1 << LOG;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool ok = i < L;
   const uint64_t v = ok ? E[i] : ~0ull;
-  const int o = __lane_id() & 31;
-  uint32_t f = 0;
+  const int o = __lane_id() & (B - 1);
+  M f = 0;
   uint64_t run = ~0ull;
 #pragma unroll
-  for (int j = 31; j >= 0; --j) {
-    const uint64_t x = __shfl(v, j, 32);
+  for (int j = B - 1; j >= 0; --j) {
+    const uint64_t x = __shfl(v, j, B);
     if (j <= o && x < run) {
-      f |= 1u << j;
+      f |= (M)1 << j;
       run = x;
     }
   }
   if (ok) mask[i] = f;
-  if (o == 31 && (i >> kLog) < (((int64_t)L + 31) >> kLog)) bmin[i >> kLog] = run;
+  if (o == B - 1 && (i >> LOG) < (((int64_t)L + B - 1) >> LOG)) bmin[i >> LOG] = run;
 }
 
 __global__ void k_rmq_level(const uint64_t* __restrict__ prev, int32_t nb, int32_t half,
@@ -71,22 +75,26 @@ __global__ void k_rmq_level(const uint64_t* __restrict__ prev, int32_t nb, int32
   next[b] = (o < nb) ? min(prev[b], prev[o]) : prev[b];
 }
 
+template <int LOG>
 struct RmqTables {
   const uint64_t* E;
-  const uint32_t* mask;
+  const typename RmqMask<LOG>::type* mask;
   const uint64_t* st;  // level k at k * nb
   int32_t nb;
 };
 
-__device__ __forceinline__ uint64_t in_block(const RmqTables& t, int32_t l, int32_t r) {
-  const int32_t base = r & ~31;
-  return t.E[base + ctz32(t.mask[r] & (~0u << (l - base)))];
+template <int LOG>
+__device__ __forceinline__ uint64_t in_block(const RmqTables<LOG>& t, int32_t l, int32_t r) {
+  using M = typename RmqMask<LOG>::type;
+  const int32_t base = r & ~((1 << LOG) - 1);
+  return t.E[base + RmqMask<LOG>::ctz(t.mask[r] & (~(M)0 << (l - base)))];
 }
 
-__device__ __forceinline__ uint64_t range_min(const RmqTables& t, int32_t l, int32_t r) {
-  const int32_t bl = l >> kLog, br = r >> kLog;
+template <int LOG>
+__device__ __forceinline__ uint64_t range_min(const RmqTables<LOG>& t, int32_t l, int32_t r) {
+  const int32_t bl = l >> LOG, br = r >> LOG;
   if (bl == br) return in_block(t, l, r);
-  uint64_t m = min(in_block(t, l, (bl << kLog) + 31), in_block(t, br << kLog, r));
+  uint64_t m = min(in_block(t, l, (bl << LOG) + (1 << LOG) - 1), in_block(t, br << LOG, r));
   if (bl + 1 <= br - 1) {
     const int32_t a = bl + 1, b = br - 1;
     const int k = msb32((uint32_t)(b - a + 1));
@@ -96,10 +104,12 @@ __device__ __forceinline__ uint64_t range_min(const RmqTables& t, int32_t l, int
   return m;
 }
 
-__global__ __launch_bounds__(kB) void k_lca_rmq(RmqTables t, const int32_t* __restrict__ rank, int32_t n,
-                                               const int32_t* __restrict__ sc, int32_t L,
-                                               const int32_t* __restrict__ qx, const int32_t* __restrict__ qy,
-                                               int64_t q, int32_t* __restrict__ out, uint32_t* __restrict__ status) {
+template <int LOG>
+__global__ __launch_bounds__(kQueryBlockMax) void k_lca_rmq(RmqTables<LOG> t, const int32_t* __restrict__ rank,
+                                                           int32_t n, const int32_t* __restrict__ sc, int32_t L,
+                                                           const int32_t* __restrict__ qx,
+                                                           const int32_t* __restrict__ qy, int64_t q,
+                                                           int32_t* __restrict__ out, uint32_t* __restrict__ status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= q) return;
   const int32_t x = qx[i], y = qy[i];
@@ -133,14 +143,16 @@ int tree_rmq_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
   const int32_t n = t->n;
   const int32_t L = 2 * (n - 1);
   if (L == 0) return ET_OK;
-  const int32_t nb = (int32_t)(((int64_t)L + 31) >> kLog);
+  const int lg = c->qs.rmq_log;
+  const int32_t nb = (int32_t)(((int64_t)L + (1 << lg) - 1) >> lg);
   int levels = 1;
   while ((1 << levels) <= nb) ++levels;
   t->d_rmq_e = static_cast<uint64_t*>(pool_get(c, (size_t)L * sizeof(uint64_t)));
-  t->d_rmq_mask = static_cast<uint32_t*>(pool_get(c, (size_t)L * sizeof(uint32_t)));
+  t->d_rmq_mask = pool_get(c, ((size_t)L << (lg - 5)) * sizeof(uint32_t));
   t->d_rmq_st = static_cast<uint64_t*>(pool_get(c, (size_t)levels * nb * sizeof(uint64_t)));
   if (!t->d_rmq_e || !t->d_rmq_mask || !t->d_rmq_st) return ET_ENOMEM;
   t->rmq_nb = nb;
+  t->rmq_log = lg;
   ET_PROF(c, s, "phase:rmq_build");
   {
     ET_PROF(c, s, "k_rmq_euler");
@@ -149,8 +161,13 @@ int tree_rmq_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
   }
   {
     ET_PROF(c, s, "k_rmq_masks");
-    hipLaunchKernelGGL(k_rmq_masks, dim3(ceil_div((int64_t)nb * 32, kB)), dim3(kB), 0, s, t->d_rmq_e, L,
-                       t->d_rmq_mask, t->d_rmq_st);
+    const dim3 grid(ceil_div((int64_t)nb << lg, kB));
+    if (lg == 6)
+      hipLaunchKernelGGL(k_rmq_masks<6>, grid, dim3(kB), 0, s, t->d_rmq_e, L, static_cast<uint64_t*>(t->d_rmq_mask),
+                         t->d_rmq_st);
+    else
+      hipLaunchKernelGGL(k_rmq_masks<5>, grid, dim3(kB), 0, s, t->d_rmq_e, L, static_cast<uint32_t*>(t->d_rmq_mask),
+                         t->d_rmq_st);
   }
   for (int k = 1; k < levels; ++k)
     hipLaunchKernelGGL(k_rmq_level, dim3(ceil_div(nb, kB)), dim3(kB), 0, s, t->d_rmq_st + (size_t)(k - 1) * nb, nb,
@@ -162,12 +179,20 @@ int tree_lca_rmq(Ctx* c, const et_tree* t, const int32_t* qx, const int32_t* qy,
                  hipStream_t s) {
   if (q == 0) return ET_OK;
   const int32_t L = 2 * (t->n - 1);
-  RmqTables tab{t->d_rmq_e, t->d_rmq_mask, t->d_rmq_st, t->rmq_nb};
+  const int bs = c->qs.block;
   ET_PROF(c, s, "k_lca_rmq");
   for (int64_t q0 = 0; q0 < q; q0 += kQueryChunk) {  // one dispatch holds < 2^32 work-items
     const int64_t m = std::min(q - q0, kQueryChunk);
-    hipLaunchKernelGGL(k_lca_rmq, dim3((unsigned)((m + kB - 1) / kB)), dim3(kB), 0, s, tab, t->d_rank, t->n,
-                       t->d_root, L, qx + q0, qy + q0, m, out + q0, c->d_status);
+    const dim3 grid((unsigned)((m + bs - 1) / bs));
+    if (t->rmq_log == 6) {
+      RmqTables<6> tab{t->d_rmq_e, static_cast<const uint64_t*>(t->d_rmq_mask), t->d_rmq_st, t->rmq_nb};
+      hipLaunchKernelGGL(k_lca_rmq<6>, grid, dim3(bs), 0, s, tab, t->d_rank, t->n, t->d_root, L, qx + q0, qy + q0, m,
+                         out + q0, c->d_status);
+    } else {
+      RmqTables<5> tab{t->d_rmq_e, static_cast<const uint32_t*>(t->d_rmq_mask), t->d_rmq_st, t->rmq_nb};
+      hipLaunchKernelGGL(k_lca_rmq<5>, grid, dim3(bs), 0, s, tab, t->d_rank, t->n, t->d_root, L, qx + q0, qy + q0, m,
+                         out + q0, c->d_status);
+    }
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }

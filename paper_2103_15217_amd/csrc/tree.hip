@@ -234,7 +234,7 @@ __device__ __forceinline__ int32_t sv_query(const int4* __restrict__ rec, const 
   return (xd <= yd) ? xv : yv;
 }
 
-__global__ __launch_bounds__(kB) void k_lca(const int4* __restrict__ rec, const int2* __restrict__ head, int32_t n,
+__global__ __launch_bounds__(kQueryBlockMax) void k_lca(const int4* __restrict__ rec, const int2* __restrict__ head, int32_t n,
                                            const int32_t* __restrict__ qx, const int32_t* __restrict__ qy,
                                            int64_t q, int32_t* __restrict__ out, uint32_t* __restrict__ status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -280,7 +280,7 @@ __device__ __forceinline__ int32_t tree_from(const int64_t* __restrict__ off, in
   return lo;
 }
 
-__global__ __launch_bounds__(kB) void k_lca_batch(const int4* __restrict__ rec, const int2* __restrict__ head,
+__global__ __launch_bounds__(kQueryBlockMax) void k_lca_batch(const int4* __restrict__ rec, const int2* __restrict__ head,
                                                  int32_t n, const int64_t* __restrict__ off, int32_t T,
                                                  const int32_t* __restrict__ qt, const int32_t* __restrict__ qx,
                                                  const int32_t* __restrict__ qy, int64_t q, int32_t* __restrict__ out,
@@ -463,10 +463,11 @@ int tree_export(const et_tree* t, int32_t* succ, int32_t* rank, int32_t* depth, 
 int tree_lca_batch(Ctx* c, const et_tree* t, const int32_t* qt, const int32_t* qx, const int32_t* qy, int64_t q,
                    int32_t* out, hipStream_t s) {
   if (q == 0) return ET_OK;
+  const int bs = c->qs.block;
   ET_PROF(c, s, "k_lca_batch");
   for (int64_t q0 = 0; q0 < q; q0 += kQueryChunk) {  // one dispatch holds < 2^32 work-items
     const int64_t m = std::min(q - q0, kQueryChunk);
-    hipLaunchKernelGGL(k_lca_batch, dim3((unsigned)((m + kB - 1) / kB)), dim3(kB), 0, s, t->d_rec, t->d_head, t->n,
+    hipLaunchKernelGGL(k_lca_batch, dim3((unsigned)((m + bs - 1) / bs)), dim3(bs), 0, s, t->d_rec, t->d_head, t->n,
                        t->d_off, t->batch, qt + q0, qx + q0, qy + q0, m, out + q0, c->d_status);
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
@@ -492,10 +493,11 @@ int tree_build_batch(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
 int tree_lca(Ctx* c, const et_tree* t, const int32_t* qx, const int32_t* qy, int64_t q, int32_t* out,
              hipStream_t s) {
   if (q == 0) return ET_OK;
+  const int bs = c->qs.block;
   ET_PROF(c, s, "k_lca");
   for (int64_t q0 = 0; q0 < q; q0 += kQueryChunk) {  // one dispatch holds < 2^32 work-items
     const int64_t m = std::min(q - q0, kQueryChunk);
-    hipLaunchKernelGGL(k_lca, dim3((unsigned)((m + kB - 1) / kB)), dim3(kB), 0, s, t->d_rec, t->d_head, t->n, qx + q0,
+    hipLaunchKernelGGL(k_lca, dim3((unsigned)((m + bs - 1) / bs)), dim3(bs), 0, s, t->d_rec, t->d_head, t->n, qx + q0,
                        qy + q0, m, out + q0, c->d_status);
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;

@@ -24,7 +24,7 @@ import time
 import numpy as np
 import torch
 
-from . import et
+from . import autotune, et
 
 # device bytes per unit used for admission (tables + build scratch)
 TREE_BYTES_PER_NODE = 160
@@ -126,6 +126,7 @@ class PlainExecutor:
     def __init__(self, dpool, keep_results=False):
         self.dpool = dpool
         self.ctx = et.Context()
+        autotune.apply(self.ctx, "single")   # one instance per call
         self.keep = keep_results
         self.results = {}
 
@@ -166,6 +167,7 @@ class ServedExecutor:
         for st in self.streams:
             with torch.cuda.stream(st):
                 self.ctxs.append(et.Context())
+                autotune.apply(self.ctxs[-1], "batch")   # batched builds, queries and bridge calls
         self.build_ctx, self.build_stream = self.ctxs[0], self.streams[0]
         self.budget = budget_bytes
         self.keep = keep_results

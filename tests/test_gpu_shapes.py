@@ -1,0 +1,101 @@
+"""Tunable launch shapes never change results: list-ranking splitter
+spacing and sublists per wavefront, the range-minimum block size (32 or 64
+positions) of the bridge and RMQ-LCA tables, and the query workgroup size.
+Every setting is checked against the oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    import paper_2103_15217_amd as et
+    assert torch.cuda.is_available()
+    return et
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
+
+
+SHAPES = [
+    {},
+    {"rmq_block_log2": 6},
+    {"query_block": 64},
+    {"query_block": 1024, "rmq_block_log2": 6},
+    {"lr_k1_log2": 3, "lr_per_wave1": 64, "lr_kn_log2": 2, "lr_per_waven": 64},
+    {"lr_k1_log2": 6, "lr_per_wave1": 1024, "lr_kn_log2": 5, "lr_per_waven": 512, "query_block": 128},
+]
+
+
+def _ctx(lib, shape):
+    ctx = lib.Context()
+    for k, v in shape.items():
+        ctx.set_param(k, v)
+    return ctx
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: ",".join(f"{k}={v}" for k, v in s.items()) or "default")
+def test_tree_lca_and_rmq(lib, oracle_mod, shape):
+    ctx = _ctx(lib, shape)
+    for n, grasp in [(1, None), (2, None), (63, 1), (64, None), (65, 2), (5000, None), ((1 << 17) + 3, 100)]:
+        parent = gen.random_tree(n, grasp, seed=n)
+        qx, qy = gen.random_queries(n, 20000, seed=n)
+        d_parent = _dev(parent)
+        tree = lib.et_tree_build(d_parent, ctx=ctx).rmq_build(d_parent)
+        ref = oracle_mod.euler_tour(parent)
+        got = tree.export(("depth", "pre", "size"))
+        for k in ("depth", "pre", "size"):
+            assert np.array_equal(got[k].cpu().numpy(), ref[k]), (n, k)
+        want = oracle_mod.lca_offline(parent, qx, qy)
+        dqx, dqy = _dev(qx), _dev(qy)
+        assert np.array_equal(tree.lca(dqx, dqy).cpu().numpy(), want), (n, "inlabel")
+        assert np.array_equal(tree.lca_rmq(dqx, dqy).cpu().numpy(), want), (n, "rmq")
+        tree.free()
+    ctx.check()
+    ctx.close()
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: ",".join(f"{k}={v}" for k, v in s.items()) or "default")
+def test_bridges(lib, oracle_mod, shape):
+    ctx = _ctx(lib, shape)
+    graphs = [gen.random_multigraph(n, m, seed=n + m) for n, m in [(1, 3), (7, 12), (33, 40), (64, 64), (65, 200)]]
+    graphs.append(gen.planted_bridge_graph(n=1 << 16, m=1 << 19, chains=64, max_chain=64, seed=3)[:2])
+    for rp, col in graphs:
+        mask, cnt = lib.et_bridges(_dev(rp), _dev(col), ctx=ctx)
+        ref_mask, ref_cnt = oracle_mod.bridges(rp, col)
+        assert np.array_equal(mask.cpu().numpy().view(np.uint32)[: len(ref_mask)], ref_mask)
+        assert cnt == ref_cnt
+    ctx.check()
+    ctx.close()
+
+
+def test_batch_queries_with_wide_workgroups(lib, oracle_mod):
+    import torch
+    ctx = _ctx(lib, {"query_block": 1024})
+    b = gen.forest_batch(50, seed=8, log2_min=0, log2_max=12, qlog2_min=3, qlog2_max=9)
+    tree = lib.et_tree_build_batch(_dev(b["parent"]), torch.from_numpy(b["offsets"].astype(np.int64)).cuda(), ctx=ctx)
+    got = tree.lca_batch(_dev(b["qtree"]), _dev(b["qx"]), _dev(b["qy"])).cpu().numpy()
+    off = b["offsets"]
+    for t in range(len(b["sizes"])):
+        sel = b["qtree"] == t
+        assert np.array_equal(got[sel], oracle_mod.lca_offline(b["parent"][off[t]:off[t + 1]], b["qx"][sel],
+                                                               b["qy"][sel])), t
+    tree.free()
+    ctx.check()
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,value", [("rmq_block_log2", 4), ("rmq_block_log2", 7), ("query_block", 32),
+                                        ("query_block", 96), ("query_block", 2048), ("lr_k1_log2", 0),
+                                        ("no_such_param", 1)])
+def test_rejected_values(lib, name, value):
+    ctx = lib.Context()
+    with pytest.raises(lib.EtError):
+        ctx.set_param(name, value)
+    ctx.close()
