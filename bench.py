@@ -660,7 +660,7 @@ def serving(args, dev):
     jobs = serve.make_trace(pool, args.serve_rate, args.serve_seconds, seed=args.seed)
     serve.upload_trace(jobs, dev)
     log(f"serving: pool and {len(jobs)}-job trace ready in {time.time() - t0:.1f}s")
-    res = serve.compare(dpool, jobs)
+    res = serve.compare(dpool, jobs, tuned=not args.default_params)
     res["rate_jobs_per_s"] = args.serve_rate
     res["trace_seconds"] = args.serve_seconds
     res["p99_ratio_served_over_plain"] = res["served"]["p99_ms"] / res["plain"]["p99_ms"]
@@ -668,7 +668,7 @@ def serving(args, dev):
     for rate in [float(r) for r in args.serve_sweep.split(",") if r.strip()]:
         jobs = serve.make_trace(pool, rate, 2.0, seed=args.seed + 1)
         serve.upload_trace(jobs, dev)
-        r = serve.compare(dpool, jobs)
+        r = serve.compare(dpool, jobs, tuned=not args.default_params)
         log(f"serving sweep {rate:.0f} jobs/s: plain p99 {r['plain']['p99_ms']:.2f} ms, "
             f"served p99 {r['served']['p99_ms']:.2f} ms")
         sweep.append({"rate_jobs_per_s": rate, "jobs": len(jobs),

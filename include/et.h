@@ -77,10 +77,15 @@ int et_ctx_status(et_ctx* ctx, hipStream_t s);
 int et_ctx_status_bits(et_ctx* ctx, hipStream_t s, uint32_t* h_bits);
 
 /* Tunable launch parameters of this context (used by later calls):
- *   "lr_k1_log2"    list ranking, level 1: one splitter per 2^v ids (1..10, default 4)
- *   "lr_per_wave1"  level 1: sublists owned by one wavefront (64..65536, default 256)
+ *   "lr_k1_log2"    list ranking, level 1: one splitter per 2^v ids at most
+ *                   (1..10, default 4); a list of L elements uses
+ *                   min(v, max(2, (floor(log2 L) - 15) / 2))
+ *   "lr_per_wave1"  level 1: sublists owned by one wavefront at most
+ *                   (64..65536, default 256); fewer when that would leave
+ *                   under 4096 wavefronts, never under 64
  *   "lr_kn_log2"    upper levels: one splitter per 2^v elements (1..10, default 3)
- *   "lr_per_waven"  upper levels: sublists per wavefront (64..65536, default 128)
+ *   "lr_per_waven"  upper levels: sublists per wavefront at most (64..65536,
+ *                   default 128), reduced like lr_per_wave1
  *   "rmq_block_log2"  range-minimum blocks of 2^v positions for the bridge
  *                   low / high tables and et_tree_rmq_build (5 or 6, default 5)
  *   "query_block"   threads per workgroup of the LCA query kernels (a power

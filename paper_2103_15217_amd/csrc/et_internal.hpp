@@ -162,6 +162,14 @@ struct RmqMask<6> {
 };
 
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+inline int floor_log2(long long x) {  // -1 for x < 1
+  int r = -1;
+  while (x > 0) {
+    x >>= 1;
+    ++r;
+  }
+  return r;
+}
 
 // queries per dispatch: a dispatch holds fewer than 2^32 work-items
 constexpr int64_t kQueryChunk = (int64_t)1 << 31;

@@ -397,8 +397,12 @@ int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const 
                    int32_t nheads, bool tree_weights, const int32_t* expected_reach, LRResult* out,
                    hipStream_t s, bool empty_head_ok) {
   const int32_t L = len, H = nheads;
-  // level-1 splitter spacing: K = 16 (a sublist averages 16 elements)
-  const int ks1 = (L >= (1 << 12)) ? c->lr.k1_log2 : 2;
+  // Level-1 splitter spacing K = 2^ks1 (a sublist averages K elements).
+  // Shorter lists keep more, shorter sublists: below about 2^25 elements the
+  // walk is bound by its dependent steps rather than by line fetches, so the
+  // spacing drops by half per factor 4 of length (2^24 -> 16, 2^22 -> 8,
+  // 2^20 -> 4), down to 4; the context's value is the largest spacing used.
+  const int ks1 = std::min(c->lr.k1_log2, std::max(2, (floor_log2(L) - 15) / 2));
   const int32_t S1 = (int32_t)(((int64_t)L + (1 << ks1) - 1) >> ks1);
   const int32_t cont_max = L / kCap + H + 64;
   const int32_t T1 = S1 + H + cont_max;
@@ -410,7 +414,9 @@ int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const 
   hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, ctr + 1, 0);
   hipLaunchKernelGGL(k_fill_int4, dim3(ceil_div(cont_max, 256)), dim3(256), 0, s, rec1, S1 + H, T1,
                      make_int4(-3, 0, 0, 0));
-  const int32_t per_wave1 = c->lr.per_wave1;
+  // sublists per wavefront: the context's value, fewer when that would leave
+  // under 4096 wavefronts (at least 64, one per lane)
+  const int32_t per_wave1 = std::min(c->lr.per_wave1, std::max(64, (S1 + H) >> 12));
   if (tree_weights) {
     ET_PROF(c, s, "k_walk1<true>");
     hipLaunchKernelGGL(k_walk1<true>, dim3(walk_grid(S1 + H, per_wave1)), dim3(kWalkThreads), 0, s, succ, L,
@@ -442,7 +448,7 @@ int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const 
     int4* el = sc.get<int4>((size_t)cur.T);
     int4* rec = sc.get<int4>((size_t)Tn);
     if (sc.failed) return ET_ENOMEM;
-    const int32_t per_wave = c->lr.per_waven;
+    const int32_t per_wave = std::min(c->lr.per_waven, std::max(64, Tn >> 12));
     {
       ET_PROF(c, s, "k_walkN");
       hipLaunchKernelGGL(k_walkN, dim3(walk_grid(Tn, per_wave)), dim3(kWalkThreads), 0, s, cur.rec, cur.T,

@@ -123,10 +123,11 @@ def _stats(lat, wall, njobs):
 class PlainExecutor:
     """FCFS, one job at a time, nothing kept between jobs."""
 
-    def __init__(self, dpool, keep_results=False):
+    def __init__(self, dpool, keep_results=False, tuned=True):
         self.dpool = dpool
         self.ctx = et.Context()
-        autotune.apply(self.ctx, "single")   # one instance per call
+        if tuned:
+            autotune.apply(self.ctx, "single")   # one instance per call
         self.keep = keep_results
         self.results = {}
 
@@ -160,14 +161,15 @@ class ServedExecutor:
     """Continuous batching with a resident-tree cache and memory admission."""
 
     def __init__(self, dpool, streams=4, budget_bytes=8 << 30, keep_results=False, max_batch=64,
-                 bridge_batch=True):
+                 bridge_batch=True, tuned=True):
         self.dpool = dpool
         self.streams = [torch.cuda.Stream() for _ in range(streams)]
         self.ctxs = []
         for st in self.streams:
             with torch.cuda.stream(st):
                 self.ctxs.append(et.Context())
-                autotune.apply(self.ctxs[-1], "batch")   # batched builds, queries and bridge calls
+                if tuned:
+                    autotune.apply(self.ctxs[-1], "batch")   # batched builds, queries and bridge calls
         self.build_ctx, self.build_stream = self.ctxs[0], self.streams[0]
         self.budget = budget_bytes
         self.keep = keep_results
@@ -357,11 +359,11 @@ class ServedExecutor:
         self.resident = 0
 
 
-def compare(dpool, jobs, streams=4, budget_bytes=8 << 30):
+def compare(dpool, jobs, streams=4, budget_bytes=8 << 30, tuned=True):
     """Replay ``jobs`` through the plain and the served executor."""
-    plain = PlainExecutor(dpool)
+    plain = PlainExecutor(dpool, tuned=tuned)
     p = plain.run(jobs)
-    served = ServedExecutor(dpool, streams=streams, budget_bytes=budget_bytes)
+    served = ServedExecutor(dpool, streams=streams, budget_bytes=budget_bytes, tuned=tuned)
     s = served.run(jobs)
     served.close()
     return {"plain": p, "served": s}
