@@ -361,6 +361,8 @@ def et_bridges_batch(graphs=None, *, row_ptr=None, col=None, voff=None, soff=Non
     it, and with ``counts`` a device int64 tensor of bridges per graph."""
     ctx = ctx or default_context()
     if graphs is not None:
+        if len(graphs) == 0:
+            raise ValueError("a batch needs at least one graph")
         rps = [_dev(g[0], torch.int32, "row_ptr") for g in graphs]
         cols = [_dev(g[1], torch.int32, "col") for g in graphs]
         dev = rps[0].device
@@ -382,6 +384,8 @@ def et_bridges_batch(graphs=None, *, row_ptr=None, col=None, voff=None, soff=Non
     T = len(ss)
     n_total = row_ptr.numel() - T
     nnz = col.numel()
+    if T < 1 or n_total < 0 or sum(ss) != nnz:
+        raise ValueError("offsets do not match the concatenated arrays")
     words = [(x + 31) // 32 for x in ss]
     starts = [0]
     for w in words[:-1]:
