@@ -146,11 +146,11 @@ __global__ void k_asc_level(uint32_t* __restrict__ plab, int32_t n, int t, uint3
   plab[I] = up | (1u << t);
 }
 
-__global__ void k_asc(int4* __restrict__ rec, const uint32_t* __restrict__ asc_of_label, int32_t n,
-                      uint32_t* __restrict__ status) {
+__global__ void k_asc(int4* __restrict__ rec, const uint32_t* __restrict__ inl_of,
+                      const uint32_t* __restrict__ asc_of_label, int32_t n, uint32_t* __restrict__ status) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const uint32_t inl = (uint32_t)rec[v].x;
+  const uint32_t inl = inl_of[v];  // the compact copy: a quarter of the record's lines
   uint32_t a = 0;
   if (inl >= 1u && inl <= (uint32_t)n) a = asc_of_label[inl];
   else flag(status, ST_BAD_INDEX);
@@ -433,7 +433,7 @@ int inlabel_phase(Ctx* c, et_tree* t, const int32_t* parent, const uint32_t* inl
   }
   {
     ET_PROF(c, s, "k_asc");
-    hipLaunchKernelGGL(k_asc, dim3(gn), dim3(kB), 0, s, t->d_rec, plab, n, c->d_status);
+    hipLaunchKernelGGL(k_asc, dim3(gn), dim3(kB), 0, s, t->d_rec, inl, plab, n, c->d_status);
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }
