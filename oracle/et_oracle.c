@@ -258,9 +258,9 @@ out:
     return rc;
 }
 
-static uint32_t trailing_zeros(uint32_t x) {
+static uint32_t trailing_zeros(uint32_t x) { /* x != 0 */
     uint32_t t = 0;
-    while (!(x & 1u)) { x >>= 1; t++; }
+    while (t < 31 && !(x & 1u)) { x >>= 1; t++; }
     return t;
 }
 
@@ -284,6 +284,7 @@ int oracle_sv_tables(const int32_t* parent, const int32_t* depth, const int32_t*
             uint32_t m = (hi >> t) << t; /* largest multiple of 2^t not above hi */
             if (m >= lo && m != 0) best = m;
         }
+        if (!best) return ORC_EINPUT; /* [pre+1, pre+size] always holds a nonzero member */
         inlabel[v] = best;
     }
     /* nodes in preorder, so every parent comes before its children */

@@ -60,6 +60,21 @@ MUTANTS = {
                        "if (rank[e] > rank[tw]) {                          /* down into dst[e] */"),
     # list ranks start at 1
     "list_rank_origin": ("int32_t r = 0;\n        while (e != -1) {", "int32_t r = 1;\n        while (e != -1) {"),
+    # only the first list of a multi-list input is walked
+    "list_rank_heads": ("for (int32_t h = 0; h < nheads; ++h) {", "for (int32_t h = 0; h < nheads && h < 1; ++h) {"),
+    # low values not passed up from a finished child
+    "bridge_low_up": ("if (low[u] < low[p]) low[p] = low[u];", "(void)low[p];"),
+    # only the parent-to-child slot of a bridge marked
+    "bridge_one_slot": ("mask[b >> 5] |= 1u << (b & 31);", "(void)b;"),
+    # head table records the path top instead of its parent
+    "head_parent": ("head_parent[inlabel[v]] = p;", "head_parent[inlabel[v]] = v;"),
+    # inlabel interval taken as (pre, pre + size] without its first member
+    "inlabel_lo": ("if (m >= lo && m != 0) best = m;", "if (m > lo && m != 0) best = m;"),
+    # the edge-list tour cut after the root's first half-edge instead of before it
+    "dcel_cut": ("if (succ[e] == head) { succ[e] = -1; break; }", "if (e == head) { succ[e] = -1; break; }"),
+    # the lexicographic order of B built by source only (the target sort dropped)
+    "dcel_sort": ("for (int64_t h = 0; h < L; ++h) tmp[cnt[dst[h]]++] = (int32_t)h;",
+                  "for (int64_t h = 0; h < L; ++h) tmp[h] = (int32_t)h;"),
 }
 
 
