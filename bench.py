@@ -41,6 +41,14 @@ ALG_BYTES = {
     "k_lca": (76, "query", lambda w: w["q"]),
     # first hooking round: row pointers (8 B) and up to two columns (8 B) per vertex
     "k_hook_sample": (16, "vertex", lambda w: w["graph_n"]),
+    # path tops: 16-B record, parent and the parent's gathered inlabel read; about half the
+    # nodes are tops and write an 8-B head entry and a 4-B parent-path label
+    "k_head": (30, "node", lambda w: w["n"]),
+    # successor: parent and child read per grouped position, succ(2c+1) and (at the first
+    # child) succ(2p) written
+    "k_succ": (14, "node", lambda w: w["n"]),
+    # ascendant into the node record: inlabel read, label ascendant gathered, 4 B written
+    "k_asc": (12, "node", lambda w: w["n"]),
     # node statistics: the 8-B records of 2c and 2c+1 and their two 8-B sublist offsets
     # read; rank pair (8 B), pre, size, inlabel (4 B each) and the 16-B node record written
     "k_node": (68, "node", lambda w: w["n"]),
@@ -246,34 +254,14 @@ def main():
     if dom and dom in timed:
         launches = timed[dom][0] / args.steps
         avg_ms = timed[dom][1] / timed[dom][0]
-        traffic = measured_traffic(dom, launch["single"])
-        if dom in ALG_BYTES:
-            bpu, unit, units = ALG_BYTES[dom]
-            units_per_launch = units(work)
-            achieved = bpu * units_per_launch / (avg_ms * 1e-3) / 1e9
-            roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                        "alg_bytes_per_unit": bpu, "unit_name": unit, "units_per_launch": units_per_launch,
-                        "avg_launch_ms": avg_ms, "launches_per_step": launches}
-            if traffic:
-                # what the memory system actually moves: every random access costs a whole line
-                rate = traffic / (avg_ms * 1e-3) / 1e9
-                roofline["traffic_GBps"] = rate
-                roofline["traffic_frac"] = rate / HBM_PEAK_GBS
-                copy = probe_ceiling("copy", 27, "GB_per_s")        # measured stream-copy peak
-                if copy:
-                    roofline["copy_GBps"] = copy
-                    roofline["traffic_frac_of_copy"] = rate / copy
-            # the walk is a dependent random read per unit: compare with the
-            # measured random-access ceiling of this GPU (probe/ceiling.hip)
-            ceil = probe_ceiling("chase+w8" if dom.startswith("k_walk1") else "gather")
-            if ceil:
-                roofline["units_per_s"] = units_per_launch / (avg_ms * 1e-3)
-                roofline["random_ceiling_per_s"] = ceil
-                roofline["random_frac"] = roofline["units_per_s"] / ceil
-        else:
-            roofline = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": None, "traffic": traffic, "avg_launch_ms": avg_ms}
+        roofline = kernel_roofline(dom, avg_ms, launches, work, launch["single"])
+    # list ranking and LCA queries, and the largest kernels of the build and
+    # of the bridges, from the profiled steps
+    kernel_rooflines = {}
+    for k in ("k_walk1<true>", "k_lca", "k_node", "k_head", "k_succ", "k_asc", "k_minmax"):
+        if k in kernels and kernels[k][0] > 0:
+            kernel_rooflines[k] = kernel_roofline(k, kernels[k][1] / kernels[k][0], kernels[k][0] / prof_steps,
+                                                  work, launch["single"])
 
     result = {
         "metric": METRIC,
@@ -300,6 +288,7 @@ def main():
         "components": components,
         "kernels_ms_per_step": {k: round(v[1], 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1][1])},
         "roofline": roofline,
+        "kernel_rooflines": kernel_rooflines,
     }
 
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
@@ -676,6 +665,39 @@ def serving(args, dev):
                          for m in ("p50_ms", "p99_ms", "jobs_per_s", "wall_s")}})
     res["sweep"] = sweep
     return res
+
+
+def kernel_roofline(kernel, avg_ms, launches, work, params):
+    """Roofline figures of one kernel from its average launch time: the
+    algorithmic bytes per launch over that time against 8 TB/s, the
+    counter-measured HBM bytes (when a current summary exists) against 8 TB/s
+    and against the measured copy rate, and its units per second against
+    the measured random-access ceiling of its access pattern."""
+    r = {"kernel": kernel, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+         "traffic": measured_traffic(kernel, params), "avg_launch_ms": avg_ms, "launches_per_step": launches}
+    if kernel not in ALG_BYTES:
+        return r
+    bpu, unit, units = ALG_BYTES[kernel]
+    upl = units(work)
+    r.update({"achieved": bpu * upl / (avg_ms * 1e-3) / 1e9, "alg_bytes_per_unit": bpu, "unit_name": unit,
+              "units_per_launch": upl})
+    r["frac"] = r["achieved"] / HBM_PEAK_GBS
+    if r["traffic"]:
+        # what the memory system actually moves: every random access costs a whole line
+        rate = r["traffic"] / (avg_ms * 1e-3) / 1e9
+        r["traffic_GBps"] = rate
+        r["traffic_frac"] = rate / HBM_PEAK_GBS
+        copy = probe_ceiling("copy", 27, "GB_per_s")        # measured stream-copy peak
+        if copy:
+            r["copy_GBps"] = copy
+            r["traffic_frac_of_copy"] = rate / copy
+    # dependent walks against chase + store, the rest against independent gathers
+    ceil = probe_ceiling("chase+w8" if kernel.startswith("k_walk1") else "gather")
+    if ceil:
+        r["units_per_s"] = upl / (avg_ms * 1e-3)
+        r["random_ceiling_per_s"] = ceil
+        r["random_frac"] = r["units_per_s"] / ceil
+    return r
 
 
 def probe_ceiling(name, log2n=25, field="elements_per_s"):
