@@ -32,6 +32,24 @@ __device__ __forceinline__ int32_t owner(const O* __restrict__ off, int32_t T, i
   return lo;
 }
 
+// the owner of k given the owner t of an earlier element: forward search,
+// binary only when k lies past instance t
+template <typename O>
+__device__ __forceinline__ int32_t owner_from(const O* __restrict__ off, int32_t t, int32_t T, int64_t k) {
+  if ((int64_t)off[t + 1] > k) return t;
+  int32_t lo = t, hi = T;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if ((int64_t)off[mid] <= k) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// element passes: each lane takes kPerLane elements a block width apart, so
+// its owner only moves forward (one binary search per lane, not per element)
+constexpr int kPerLane = 16;
+
 // per instance: offsets non-decreasing and the local row pointers run from
 // 0 to the instance's slot count; wc[t] = mask words of instance t
 // (wc[T] = 0, so an exclusive scan gives the word offsets and the total)
@@ -61,34 +79,41 @@ __global__ void k_gb_check(const int32_t* __restrict__ rows, const int64_t* __re
 __global__ void k_gb_rows(const int32_t* __restrict__ rows, const int64_t* __restrict__ voff,
                           const int64_t* __restrict__ soff, int32_t T, int32_t V, int32_t nnz,
                           int32_t* __restrict__ row_g, uint32_t* __restrict__ status) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v > V) return;
-  if (v == V) {
-    row_g[V] = nnz;
-    return;
+  const int64_t first = (int64_t)blockIdx.x * blockDim.x * kPerLane + threadIdx.x;
+  if (first > V) return;
+  int32_t t = owner(voff, T, min(first, (int64_t)V - 1));
+  for (int i = 0; i < kPerLane; ++i) {
+    const int64_t v = first + (int64_t)i * blockDim.x;
+    if (v > V) break;
+    if (v == V) {
+      row_g[V] = nnz;
+      break;
+    }
+    t = owner_from(voff, t, T, v);
+    const int32_t r = rows[v + t];
+    const int64_t g = soff[t] + (int64_t)r;
+    if (r < 0 || g > soff[t + 1] || g > nnz) {
+      flag(status, ST_BAD_CSR);
+      row_g[v] = 0;  // keeps the union's row pointers in range
+    } else {
+      row_g[v] = (int32_t)g;
+    }
   }
-  const int32_t t = owner(voff, T, v);
-  const int32_t r = rows[v + t];
-  const int64_t s0 = soff[t];
-  const int64_t g = s0 + (int64_t)r;
-  if (r < 0 || g > soff[t + 1] || g > nnz) {
-    flag(status, ST_BAD_CSR);
-    row_g[v] = 0;  // keeps the union's row pointers in range
-    return;
-  }
-  row_g[v] = (int32_t)g;
 }
 
 // union columns: col_g[k] = voff[t] + the local column of slot k
 __global__ void k_gb_cols(const int32_t* __restrict__ col, const int64_t* __restrict__ voff,
                           const int64_t* __restrict__ soff, int32_t T, int32_t V, int32_t nnz,
                           int32_t* __restrict__ col_g, uint32_t* __restrict__ status) {
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t t = owner(soff, T, k);
+  const int64_t first = (int64_t)blockIdx.x * blockDim.x * kPerLane + threadIdx.x;
+  if (first >= nnz) return;
+  int32_t t = owner(soff, T, first);
+  for (int i = 0; i < kPerLane; ++i) {
+    const int64_t k = first + (int64_t)i * blockDim.x;
+    if (k >= nnz) break;
+    t = owner_from(soff, t, T, k);
     const int32_t w = col[k];
-    const int64_t v0 = voff[t];
-    const int64_t g = v0 + (int64_t)w;
+    const int64_t g = voff[t] + (int64_t)w;
     if (w < 0 || g >= voff[t + 1] || g >= V) {
       flag(status, ST_BAD_CSR);  // a column outside its own graph
       col_g[k] = 0;
@@ -157,12 +182,12 @@ int bridges_batch_run(Ctx* c, const int32_t* rows, const int32_t* col, const int
   if (rc) return rc;
   {
     ET_PROF(c, s, "k_gb_rows");
-    hipLaunchKernelGGL(k_gb_rows, dim3(ceil_div((int64_t)V + 1, kB)), dim3(kB), 0, s, rows, voff, soff, T, V, nnz,
-                       row_g, c->d_status);
+    hipLaunchKernelGGL(k_gb_rows, dim3(ceil_div((int64_t)V + 1, (int64_t)kB * kPerLane)), dim3(kB), 0, s, rows, voff,
+                       soff, T, V, nnz, row_g, c->d_status);
   }
   if (nnz > 0) {
     ET_PROF(c, s, "k_gb_cols");
-    hipLaunchKernelGGL(k_gb_cols, dim3(std::min(ceil_div(nnz, kB), 1 << 16)), dim3(kB), 0, s, col, voff, soff, T, V,
+    hipLaunchKernelGGL(k_gb_cols, dim3(ceil_div(nnz, (int64_t)kB * kPerLane)), dim3(kB), 0, s, col, voff, soff, T, V,
                        nnz, col_g, c->d_status);
   }
   rc = bridges_run(c, row_g, col_g, V, nnz, umask, s, kAlgoTV);
