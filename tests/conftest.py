@@ -18,3 +18,23 @@ def oracle_mod():
     import oracle
     oracle._load()
     return oracle
+
+
+@pytest.fixture
+def bench_ctx():
+    """Make contexts in the launch configuration bench.py times: the
+    autotuned shapes of this GPU for the given workload ("single" or
+    "batch"), the library defaults when none are stored."""
+    made = []
+
+    def make(workload="single"):
+        import paper_2103_15217_amd as et
+        from paper_2103_15217_amd import autotune
+        ctx = et.Context()
+        autotune.apply(ctx, workload)
+        made.append(ctx)
+        return ctx
+
+    yield make
+    for ctx in made:
+        ctx.close()

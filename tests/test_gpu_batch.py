@@ -22,10 +22,10 @@ def _dev(a, dtype=np.int32):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
 
 
-def check_batch(lib, oracle_mod, batch, trees_to_check=None):
-    ctx = lib.default_context()
+def check_batch(lib, oracle_mod, batch, trees_to_check=None, ctx=None):
+    ctx = ctx or lib.default_context()
     T = len(batch["sizes"])
-    tree = lib.et_tree_build_batch(_dev(batch["parent"]), _dev(batch["offsets"], np.int64))
+    tree = lib.et_tree_build_batch(_dev(batch["parent"]), _dev(batch["offsets"], np.int64), ctx=ctx)
     got = {k: v.cpu().numpy() for k, v in tree.export().items()}
     out = tree.lca_batch(_dev(batch["qtree"]), _dev(batch["qx"]), _dev(batch["qy"])).cpu().numpy()
     ctx.check()
@@ -101,7 +101,7 @@ def test_malformed_batches_flagged(lib):
     ctx.close()
 
 
-def test_full_size_4096_trees(lib, oracle_mod):
+def test_full_size_4096_trees(lib, oracle_mod, bench_ctx):
     # 4096 trees, sizes log-uniform in [2^6, 2^18], grasp from {1, 64, n},
     # 2^10..2^14 queries each; a seeded sample of 96 trees is checked in full
     import time
@@ -111,5 +111,5 @@ def test_full_size_4096_trees(lib, oracle_mod):
           f"generated in {time.time() - t0:.1f}s", flush=True)
     rng = np.random.default_rng(5)
     sample = sorted(rng.choice(4096, size=96, replace=False).tolist())
-    check_batch(lib, oracle_mod, batch, trees_to_check=sample)
+    check_batch(lib, oracle_mod, batch, trees_to_check=sample, ctx=bench_ctx("batch"))
     print(f"[batch] compared in {time.time() - t0:.1f}s", flush=True)

@@ -22,9 +22,9 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
 
 
-def compare(lib, oracle_mod, row_ptr, col):
-    ctx = lib.default_context()
-    mask, cnt = lib.et_bridges(_dev(row_ptr), _dev(col))
+def compare(lib, oracle_mod, row_ptr, col, ctx=None):
+    ctx = ctx or lib.default_context()
+    mask, cnt = lib.et_bridges(_dev(row_ptr), _dev(col), ctx=ctx)
     ctx.check()
     ref_mask, ref_cnt = oracle_mod.bridges(row_ptr, col)
     got = mask.cpu().numpy().view(np.uint32)[: len(ref_mask)]
@@ -76,13 +76,13 @@ def test_planted_medium(lib, oracle_mod):
     assert cnt >= len(info["chain_edges"])
 
 
-def test_full_size_planted(lib, oracle_mod):
+def test_full_size_planted(lib, oracle_mod, bench_ctx):
     # 2^22 vertices, ~2^25 edges, 4096 planted chains of length 1..512
     import time
     t0 = time.time()
     rp, col, info = gen.planted_bridge_graph(seed=0)
     print(f"\n[full-size bridges] graph {time.time() - t0:.1f}s", flush=True)
-    cnt = compare(lib, oracle_mod, rp, col)
+    cnt = compare(lib, oracle_mod, rp, col, ctx=bench_ctx("single"))
     print(f"[full-size bridges] compared in {time.time() - t0:.1f}s, {cnt} bridges", flush=True)
     assert cnt >= len(info["chain_edges"])
 

@@ -24,9 +24,9 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
 
 
-def compare(lib, oracle_mod, row_ptr, col, spanning):
-    ctx = lib.default_context()
-    mask, cnt = lib.et_bridges_ck(_dev(row_ptr), _dev(col), spanning=spanning)
+def compare(lib, oracle_mod, row_ptr, col, spanning, ctx=None):
+    ctx = ctx or lib.default_context()
+    mask, cnt = lib.et_bridges_ck(_dev(row_ptr), _dev(col), spanning=spanning, ctx=ctx)
     ctx.check()
     ref_mask, ref_cnt = oracle_mod.bridges(row_ptr, col)
     got = mask.cpu().numpy().view(np.uint32)[: len(ref_mask)]
@@ -82,12 +82,12 @@ def test_planted_medium(lib, oracle_mod, spanning):
 
 
 @pytest.mark.parametrize("spanning", SPANNING)
-def test_full_size_planted(lib, oracle_mod, spanning):
+def test_full_size_planted(lib, oracle_mod, bench_ctx, spanning):
     import time
     t0 = time.time()
     rp, col, info = gen.planted_bridge_graph(seed=0)
     print(f"\n[bridges {spanning}] graph {time.time() - t0:.1f}s", flush=True)
-    cnt = compare(lib, oracle_mod, rp, col, spanning)
+    cnt = compare(lib, oracle_mod, rp, col, spanning, ctx=bench_ctx("single"))
     print(f"[bridges {spanning}] compared in {time.time() - t0:.1f}s, {cnt} bridges", flush=True)
 
 

@@ -42,11 +42,11 @@ def shuffled_edges(parent, seed):
     return u[order], v[order]
 
 
-def compare(lib, oracle_mod, n, u, v, root, queries=None):
+def compare(lib, oracle_mod, n, u, v, root, queries=None, ctx=None):
     import torch
-    ctx = lib.default_context()
+    ctx = ctx or lib.default_context()
     par = torch.empty(n, dtype=torch.int32, device="cuda")
-    tree = lib.et_tree_build_edges(_dev(u), _dev(v), n, root, parent_out=par)
+    tree = lib.et_tree_build_edges(_dev(u), _dev(v), n, root, parent_out=par, ctx=ctx)
     got = {k: _np(t) for k, t in tree.export().items()}
     got_parent = _np(par)
     ctx.check()
@@ -102,12 +102,12 @@ def test_special_shapes(lib, oracle_mod, kind):
 
 
 @pytest.mark.parametrize("grasp", [None, 1000, 1])
-def test_full_size_2e24(lib, oracle_mod, grasp):
+def test_full_size_2e24(lib, oracle_mod, bench_ctx, grasp):
     n = 1 << 24
     print(f"[edges] n=2^24 grasp={grasp}", flush=True)
     parent = gen.random_tree(n, grasp, seed=21)
     u, v = shuffled_edges(parent, 21)
-    compare(lib, oracle_mod, n, u, v, 12345, gen.random_queries(n, 1 << 20, seed=21))
+    compare(lib, oracle_mod, n, u, v, 12345, gen.random_queries(n, 1 << 20, seed=21), ctx=bench_ctx("single"))
 
 
 @pytest.mark.parametrize("bad", ["cycle", "self_loop", "out_of_range", "repeated"])

@@ -27,10 +27,10 @@ def _np(t):
     return t.cpu().numpy()
 
 
-def both_engines(lib, oracle_mod, parent, qx, qy):
-    ctx = lib.default_context()
+def both_engines(lib, oracle_mod, parent, qx, qy, ctx=None):
+    ctx = ctx or lib.default_context()
     d_parent = _dev(parent)
-    tree = lib.et_tree_build(d_parent).rmq_build(d_parent)
+    tree = lib.et_tree_build(d_parent, ctx=ctx).rmq_build(d_parent)
     rmq = _np(tree.lca_rmq(_dev(qx), _dev(qy)))
     sv = _np(tree.lca(_dev(qx), _dev(qy)))
     tree.free()
@@ -74,14 +74,14 @@ def test_scale_free_trees(lib, oracle_mod, n):
 
 
 @pytest.mark.parametrize("grasp", [None, 1000, 1])
-def test_full_size_2e24(lib, oracle_mod, grasp):
+def test_full_size_2e24(lib, oracle_mod, bench_ctx, grasp):
     n = 1 << 24
     print(f"[rmq] n=2^24 grasp={grasp}", flush=True)
     parent = gen.random_tree(n, grasp, seed=31)
     qx, qy = gen.random_queries(n, 1 << 24, seed=31)
-    ctx = lib.default_context()
+    ctx = bench_ctx("single")
     d_parent = _dev(parent)
-    tree = lib.et_tree_build(d_parent).rmq_build(d_parent)
+    tree = lib.et_tree_build(d_parent, ctx=ctx).rmq_build(d_parent)
     dqx, dqy = _dev(qx), _dev(qy)
     rmq = tree.lca_rmq(dqx, dqy)
     sv = tree.lca(dqx, dqy)
@@ -94,11 +94,11 @@ def test_full_size_2e24(lib, oracle_mod, grasp):
     assert np.array_equal(rmq[:k], oracle_mod.lca_offline(parent, qx[:k], qy[:k]))
 
 
-def test_full_size_scale_free(lib, oracle_mod):
+def test_full_size_scale_free(lib, oracle_mod, bench_ctx):
     n = 1 << 24
     parent = gen.ba_tree(n, seed=24)
     qx, qy = gen.random_queries(n, 1 << 20, seed=24)
-    both_engines(lib, oracle_mod, parent, qx, qy)
+    both_engines(lib, oracle_mod, parent, qx, qy, ctx=bench_ctx("single"))
 
 
 def test_rejected_uses(lib):

@@ -29,12 +29,12 @@ def _np(t):
     return t.cpu().numpy()
 
 
-def build_and_compare(lib, oracle_mod, parent, queries=None, check_tables=True):
+def build_and_compare(lib, oracle_mod, parent, queries=None, check_tables=True, ctx=None):
     """Build on the GPU and compare every exported table with the oracle."""
     parent = np.ascontiguousarray(parent, dtype=np.int32)
     n = parent.shape[0]
-    ctx = lib.default_context()
-    tree = lib.et_tree_build(_dev(parent))
+    ctx = ctx or lib.default_context()
+    tree = lib.et_tree_build(_dev(parent), ctx=ctx)
     got = {k: _np(v) for k, v in tree.export().items()}
     ctx.check()
     ref = oracle_mod.euler_tour(parent)
@@ -179,7 +179,7 @@ def test_bad_queries_flagged(lib):
 
 
 @pytest.mark.parametrize("grasp", [None, 1000, 1])
-def test_full_size_2e24(lib, oracle_mod, grasp):
+def test_full_size_2e24(lib, oracle_mod, bench_ctx, grasp):
     # the 2^24-node configuration (grasp n, 1000, 1) with 2^24 uniform
     # queries, in the launch configuration the benchmark times
     import time
@@ -188,5 +188,6 @@ def test_full_size_2e24(lib, oracle_mod, grasp):
     parent = gen.random_tree(n, grasp, seed=0)
     qx, qy = gen.random_queries(n, n, seed=0)
     print(f"\n[full-size grasp={grasp}] inputs {time.time() - t0:.1f}s", flush=True)
-    build_and_compare(lib, oracle_mod, parent, (qx, qy), check_tables=True)
+    ctx = bench_ctx("single")
+    build_and_compare(lib, oracle_mod, parent, (qx, qy), check_tables=True, ctx=ctx)
     print(f"[full-size grasp={grasp}] compared in {time.time() - t0:.1f}s", flush=True)
