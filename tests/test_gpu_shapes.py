@@ -99,3 +99,27 @@ def test_rejected_values(lib, name, value):
     with pytest.raises(lib.EtError):
         ctx.set_param(name, value)
     ctx.close()
+
+
+@pytest.mark.parametrize("log2n,k1", [(25, 5), (27, 6)])
+def test_wide_spacings_on_long_lists(lib, log2n, k1):
+    # splitter spacings of 32 and 64 only occur on lists of at least 2^25 and
+    # 2^27 elements; the ranks of one random list of that length are checked
+    # by properties that fix them: head at 0, succ one further, all distinct
+    import torch
+    n = 1 << log2n
+    order = np.random.default_rng(log2n).permutation(n).astype(np.int32)
+    succ = np.empty(n, dtype=np.int32)
+    succ[order[:-1]] = order[1:]
+    succ[order[-1]] = -1
+    print(f"[shapes] list of 2^{log2n}, spacing 2^{k1}", flush=True)
+    ctx = _ctx(lib, {"lr_k1_log2": k1, "lr_per_wave1": 1024})
+    d_succ = torch.from_numpy(succ).cuda()
+    del succ
+    rank = lib.et_list_rank(d_succ, _dev(order[:1]), ctx=ctx)
+    ctx.check()
+    assert int(rank[int(order[0])]) == 0
+    nxt = d_succ >= 0
+    assert torch.equal(rank[d_succ[nxt].long()], rank[nxt] + 1)
+    assert int(rank.min()) == 0 and int(rank.max()) == n - 1
+    ctx.close()
