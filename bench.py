@@ -84,7 +84,7 @@ def parse():
                     help="skip the naive (climbing) LCA comparison and its depth and q:n sweeps")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=4.0)
-    ap.add_argument("--serve-sweep", default="1000,4000,8000",
+    ap.add_argument("--serve-sweep", default="1000,4000,8000,16000",
                     help="extra arrival rates (jobs/s) replayed for 2 s each to show where each path saturates; "
                          "empty to skip")
     ap.add_argument("--default-params", action="store_true",
