@@ -121,7 +121,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
-              "(this path runs on a single MI355X; see DESIGN.md for how it would shard)",
+              "(this path runs on a single MI355X; it has no multi-GPU sharding)",
               file=sys.stderr)
         sys.exit(2)
 
