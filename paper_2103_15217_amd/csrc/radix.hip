@@ -5,8 +5,9 @@
 // parent array as input the half-edges of node x are its children, and a
 // stable sort of the child ids by parent id puts every node's children next
 // to each other in ascending id order, which is all the successor step
-// needs. This is an LSD radix sort with 8-bit digits over the
-// ceil(log2 n) key bits (3 passes at n = 2^24):
+// needs. This is an LSD radix sort over the ceil(log2 n) key bits with 8-bit
+// digits (3 passes at n = 2^24, 4 at 2^27), or 9-bit digits for short
+// arrays where that saves a pass (2 passes of 9 and 8 bits at 2^17):
 //
 //   upsweep    per 4096-element tile, a digit histogram (one LDS histogram
 //              per wavefront), stored digit-major so that one exclusive scan
@@ -31,21 +32,23 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kRounds = 16;
 constexpr int kTile = kThreads * kRounds;  // 4096 keys per tile
+constexpr int kMaxBits = 9;                // widest digit
+constexpr int kMaxDigits = 1 << kMaxBits;  // kernels are built for 256 or 512 digits
 
 __device__ __forceinline__ uint32_t parent_key(int32_t p, int32_t n) {
   return (p >= 0 && p < n) ? (uint32_t)p : 0xffffffffu;
 }
 
 // scalars[0] = root id, scalars[1] = number of roots
-template <bool FIRST>
+template <bool FIRST, int DIG>
 __global__ __launch_bounds__(kThreads) void k_upsweep(const void* __restrict__ keys_in, int32_t n, int shift,
                                                       int nbits, int32_t ntiles, uint32_t* __restrict__ hist,
                                                       int32_t* __restrict__ succ, int32_t* __restrict__ scalars,
                                                       uint32_t* __restrict__ status) {
-  __shared__ uint32_t h[kWaves][256];
+  __shared__ uint32_t h[kWaves][DIG];
   const int wave = threadIdx.x >> 6;
   const uint32_t mask = (1u << nbits) - 1u;
-  for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&h[0][0])[i] = 0;
+  for (int i = threadIdx.x; i < kWaves * DIG; i += kThreads) (&h[0][0])[i] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kTile;
   bool bad = false;
@@ -76,21 +79,23 @@ __global__ __launch_bounds__(kThreads) void k_upsweep(const void* __restrict__ k
     hist[(int64_t)d * ntiles + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
-template <bool FIRST>
-__global__ __launch_bounds__(kThreads) void k_downsweep(const void* __restrict__ keys_in,
+// (four wavefronts per SIMD: the register budget of the 8-bit form)
+template <bool FIRST, int DIG>
+__global__ __launch_bounds__(kThreads, 4) void k_downsweep(const void* __restrict__ keys_in,
                                                         const int32_t* __restrict__ vals_in, int32_t n, int shift,
                                                         int nbits, int32_t ntiles,
                                                         const uint32_t* __restrict__ offsets,
                                                         uint32_t* __restrict__ keys_out,
                                                         int32_t* __restrict__ vals_out) {
-  __shared__ uint32_t cnt[kWaves][256];
-  __shared__ uint32_t lstart[256];   // tile-local start of each digit's run
-  __shared__ uint32_t gstart[256];   // global start of this tile's run of each digit
+  constexpr int kPer = DIG / kThreads;  // digits owned by one thread in the tile scan
+  __shared__ uint32_t cnt[kWaves][DIG];
+  __shared__ uint32_t lstart[DIG];   // tile-local start of each digit's run
+  __shared__ uint32_t gstart[DIG];   // global start of this tile's run of each digit
   __shared__ uint32_t skey[kTile];
   __shared__ int32_t sval[kTile];
   const int wave = threadIdx.x >> 6;
   const uint32_t mask = (1u << nbits) - 1u;
-  for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&cnt[0][0])[i] = 0;
+  for (int i = threadIdx.x; i < kWaves * DIG; i += kThreads) (&cnt[0][0])[i] = 0;
   __syncthreads();
   const int64_t tbase = (int64_t)blockIdx.x * kTile;
   const int64_t wbase = tbase + (int64_t)wave * (64 * kRounds) + __lane_id();
@@ -123,20 +128,28 @@ __global__ __launch_bounds__(kThreads) void k_downsweep(const void* __restrict__
   }
   __syncthreads();
   // per digit: chain the wave counters, then an exclusive scan over digits
-  // gives each digit's run inside the tile
+  // gives each digit's run inside the tile; thread t owns digits kPer*t ..
+  // kPer*t + kPer - 1
   {
-    const int d = threadIdx.x;  // kThreads == 256 digits
+    uint32_t tots[kPer];
     uint32_t tot = 0;
-    if (d <= (int)mask) {
 #pragma unroll
-      for (int w = 0; w < kWaves; ++w) {
-        const uint32_t c = cnt[w][d];
-        cnt[w][d] = tot;  // exclusive prefix over the waves
-        tot += c;
+    for (int q = 0; q < kPer; ++q) {
+      const int d = kPer * threadIdx.x + q;
+      uint32_t td = 0;
+      if (d <= (int)mask) {
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+          const uint32_t c = cnt[w][d];
+          cnt[w][d] = td;  // exclusive prefix over the waves
+          td += c;
+        }
+        gstart[d] = offsets[(int64_t)d * ntiles + blockIdx.x];
       }
-      gstart[d] = offsets[(int64_t)d * ntiles + blockIdx.x];
+      tots[q] = td;
+      tot += td;
     }
-    // block exclusive scan of tot over the 256 digits (4 waves)
+    // block exclusive scan of the per-thread totals over the 256 threads (4 waves)
     uint32_t inc = tot;
     const int lane = __lane_id();
 #pragma unroll
@@ -147,9 +160,13 @@ __global__ __launch_bounds__(kThreads) void k_downsweep(const void* __restrict__
     __shared__ uint32_t wsum[kWaves];
     if (lane == 63) wsum[wave] = inc;
     __syncthreads();
-    uint32_t before = 0;
-    for (int w = 0; w < wave; ++w) before += wsum[w];
-    lstart[d] = before + inc - tot;
+    uint32_t run = inc - tot;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      lstart[kPer * threadIdx.x + q] = run;
+      run += tots[q];
+    }
   }
   __syncthreads();
   // place every key at its tile-local sorted position
@@ -184,6 +201,18 @@ __global__ void k_reset_root(int32_t* __restrict__ scalars) {
   scalars[1] = 0;
 }
 
+// Digit widths of the passes over `bits` key bits of n keys, balanced. A
+// 9-bit pass costs about 40 % more than an 8-bit one (shorter runs per
+// tile, three workgroups per CU instead of four), so 9-bit digits are used
+// only for sorts of at most 2^21 keys, where the number of passes (each a
+// few launches) matters more than their bandwidth.
+int plan_passes(int bits, int64_t n, int* width) {
+  const int p8 = (bits + 7) / 8, p9 = (bits + kMaxBits - 1) / kMaxBits;
+  const int passes = (n <= (1 << 21)) ? std::min(p8, p9) : p8;
+  for (int p = 0; p < passes; ++p) width[p] = bits / passes + (p < bits % passes ? 1 : 0);
+  return passes;
+}
+
 }  // namespace
 
 // keys_out / vals_out receive the stable order; scalars[0] = root, scalars[1]
@@ -193,41 +222,45 @@ int group_by_parent_impl(Ctx* c, const int32_t* parent, int32_t n, uint32_t* key
                          int32_t* succ, int32_t* scalars, hipStream_t s) {
   int bits = 1;
   while (bits < 31 && (1ll << bits) < n) ++bits;
-  const int passes = (bits + 7) / 8;
+  int width[8];
+  const int passes = plan_passes(bits, n, width);
   const int32_t ntiles = ceil_div(n, kTile);
   Scratch sc(c);
-  uint32_t* hist = sc.get<uint32_t>((size_t)256 * ntiles);
+  uint32_t* hist = sc.get<uint32_t>((size_t)kMaxDigits * ntiles);
   uint32_t* tk = sc.get<uint32_t>((size_t)n);
   int32_t* tv = sc.get<int32_t>((size_t)n);
   if (sc.failed) return ET_ENOMEM;
   hipLaunchKernelGGL(k_reset_root, dim3(1), dim3(1), 0, s, scalars);
   const void* kin = parent;
   const int32_t* vin = nullptr;
-  for (int p = 0; p < passes; ++p) {
-    const int shift = 8 * p;
-    const int nbits = std::min(8, bits - shift);
+  for (int p = 0, shift = 0; p < passes; shift += width[p], ++p) {
+    const int nbits = width[p];
     const bool to_out = ((passes - 1 - p) % 2) == 0;
     uint32_t* kout = to_out ? keys_out : tk;
     int32_t* vout = to_out ? vals_out : tv;
     if (p == 0) {
       ET_PROF(c, s, "k_upsweep<true>");
-      hipLaunchKernelGGL(k_upsweep<true>, dim3(ntiles), dim3(kThreads), 0, s, kin, n, shift, nbits, ntiles, hist,
-                         succ, scalars, c->d_status);
+      const auto kern = (nbits > 8) ? k_upsweep<true, 512> : k_upsweep<true, 256>;
+      hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kThreads), 0, s, kin, n, shift, nbits, ntiles, hist, succ, scalars,
+                         c->d_status);
     } else {
       ET_PROF(c, s, "k_upsweep<false>");
-      hipLaunchKernelGGL(k_upsweep<false>, dim3(ntiles), dim3(kThreads), 0, s, kin, n, shift, nbits, ntiles,
-                         hist, succ, scalars, c->d_status);
+      const auto kern = (nbits > 8) ? k_upsweep<false, 512> : k_upsweep<false, 256>;
+      hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kThreads), 0, s, kin, n, shift, nbits, ntiles, hist, succ, scalars,
+                         c->d_status);
     }
     int rc = scan_u32(c, hist, hist, (int64_t)(1 << nbits) * ntiles, ScanOp::Add, true, s);
     if (rc) return rc;
     if (p == 0) {
       ET_PROF(c, s, "k_downsweep<true>");
-      hipLaunchKernelGGL(k_downsweep<true>, dim3(ntiles), dim3(kThreads), 0, s, kin, vin, n, shift, nbits, ntiles,
-                         hist, kout, vout);
+      const auto kern = (nbits > 8) ? k_downsweep<true, 512> : k_downsweep<true, 256>;
+      hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kThreads), 0, s, kin, vin, n, shift, nbits, ntiles, hist, kout,
+                         vout);
     } else {
       ET_PROF(c, s, "k_downsweep<false>");
-      hipLaunchKernelGGL(k_downsweep<false>, dim3(ntiles), dim3(kThreads), 0, s, kin, vin, n, shift, nbits,
-                         ntiles, hist, kout, vout);
+      const auto kern = (nbits > 8) ? k_downsweep<false, 512> : k_downsweep<false, 256>;
+      hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kThreads), 0, s, kin, vin, n, shift, nbits, ntiles, hist, kout,
+                         vout);
     }
     kin = kout;
     vin = vout;
@@ -242,32 +275,34 @@ int sort_pairs_u32(Ctx* c, const uint32_t* keys, const int32_t* vals, int32_t n,
                    int32_t* vals_out, hipStream_t s) {
   if (n <= 0) return ET_OK;
   bits = std::max(1, std::min(bits, 32));
-  const int passes = (bits + 7) / 8;
+  int width[8];
+  const int passes = plan_passes(bits, n, width);
   const int32_t ntiles = ceil_div(n, kTile);
   Scratch sc(c);
-  uint32_t* hist = sc.get<uint32_t>((size_t)256 * ntiles);
+  uint32_t* hist = sc.get<uint32_t>((size_t)kMaxDigits * ntiles);
   uint32_t* tk = sc.get<uint32_t>((size_t)n);
   int32_t* tv = sc.get<int32_t>((size_t)n);
   if (sc.failed) return ET_ENOMEM;
   const void* kin = keys;
   const int32_t* vin = vals;
-  for (int p = 0; p < passes; ++p) {
-    const int shift = 8 * p;
-    const int nbits = std::min(8, bits - shift);
+  for (int p = 0, shift = 0; p < passes; shift += width[p], ++p) {
+    const int nbits = width[p];
     const bool to_out = ((passes - 1 - p) % 2) == 0;
     uint32_t* kout = to_out ? keys_out : tk;
     int32_t* vout = to_out ? vals_out : tv;
     {
       ET_PROF(c, s, "k_upsweep<false>");
-      hipLaunchKernelGGL(k_upsweep<false>, dim3(ntiles), dim3(kThreads), 0, s, kin, n, shift, nbits, ntiles, hist,
-                         nullptr, nullptr, c->d_status);
+      const auto kern = (nbits > 8) ? k_upsweep<false, 512> : k_upsweep<false, 256>;
+      hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kThreads), 0, s, kin, n, shift, nbits, ntiles, hist, nullptr,
+                         nullptr, c->d_status);
     }
     int rc = scan_u32(c, hist, hist, (int64_t)(1 << nbits) * ntiles, ScanOp::Add, true, s);
     if (rc) return rc;
     {
       ET_PROF(c, s, "k_downsweep<false>");
-      hipLaunchKernelGGL(k_downsweep<false>, dim3(ntiles), dim3(kThreads), 0, s, kin, vin, n, shift, nbits, ntiles,
-                         hist, kout, vout);
+      const auto kern = (nbits > 8) ? k_downsweep<false, 512> : k_downsweep<false, 256>;
+      hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kThreads), 0, s, kin, vin, n, shift, nbits, ntiles, hist, kout,
+                         vout);
     }
     kin = kout;
     vin = vout;
