@@ -199,13 +199,18 @@ int et_ctx_profile_read(et_ctx* ctx, hipStream_t s, char* h_buf, int32_t buflen)
   return ET_OK;
 }
 
+// clears the status word with a kernel rather than a memset node, so the
+// stream's work stays free of memset operations
+__global__ void k_clear_status(uint32_t* status) { *status = 0u; }
+
 int et_ctx_status_bits(et_ctx* ctx, hipStream_t s, uint32_t* h_bits) {
   if (!ctx || !h_bits) return ET_EINVAL;
   Ctx* c = &ctx->impl;
   uint32_t bits = 0;
   if (hipMemcpyAsync(&bits, c->d_status, sizeof(bits), hipMemcpyDeviceToHost, s) != hipSuccess) return ET_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) return ET_EHIP;
-  if (hipMemsetAsync(c->d_status, 0, sizeof(uint32_t), s) != hipSuccess) return ET_EHIP;
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, c->d_status);
+  if (hipGetLastError() != hipSuccess) return ET_EHIP;
   *h_bits = bits;
   return ET_OK;
 }
