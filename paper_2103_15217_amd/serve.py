@@ -261,7 +261,9 @@ class ServedExecutor:
             ev = torch.cuda.Event()
             ev.record(st)
         for j, (start, words) in zip(batch, spans):
-            inflight.append((j, ev, None, mask[start:start + words]))
+            # a graph without slots gets the one zero word et_bridges returns for it
+            out = mask[start:start + words] if words else torch.zeros(1, dtype=mask.dtype, device=mask.device)
+            inflight.append((j, ev, None, out))
         self.active += len(batch)
         return rest
 
