@@ -204,6 +204,15 @@ int et_tree_build_batch(et_ctx* ctx, const int32_t* d_parent, const int64_t* d_o
 int et_lca_batch(const et_tree* tree, const int32_t* d_qtree, const int32_t* d_qx,
                  const int32_t* d_qy, int64_t q, int32_t* d_out, hipStream_t s);
 
+/*
+ * The tour itself as an array (Section 2: the Euler tour as the sequence of
+ * its half-edges, the inverse of the rank): d_tour[r] = the half-edge id at
+ * tour position r, for r in [0, 2(n-1)). Half-edge ids as for d_rank of
+ * et_tree_export (2c / 2c+1 for a parent-array tree, 2i / 2i+1 for an
+ * edge-list tree). ET_EINVAL for a batch.
+ */
+int et_tree_export_tour(const et_tree* tree, int32_t* d_tour, hipStream_t s);
+
 /* Number of nodes of a built tree or batch (host value). */
 int32_t et_tree_size(const et_tree* tree);
 

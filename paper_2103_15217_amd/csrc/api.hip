@@ -13,6 +13,7 @@ namespace et {
 int tree_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s);
 int tree_export(const et_tree* t, int32_t* succ, int32_t* rank, int32_t* depth, int32_t* pre, int32_t* size,
                 uint32_t* inl, uint32_t* asc, hipStream_t s);
+int tree_export_tour(Ctx* c, const et_tree* t, int32_t* tour, hipStream_t s);
 int tree_lca(Ctx* c, const et_tree* t, const int32_t* qx, const int32_t* qy, int64_t q, int32_t* out,
              hipStream_t s);
 int tree_build_batch(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s);
@@ -342,6 +343,11 @@ int et_lca_batch(const et_tree* tree, const int32_t* d_qtree, const int32_t* d_q
 }
 
 int32_t et_tree_batch_size(const et_tree* tree) { return tree ? tree->batch : -1; }
+
+int et_tree_export_tour(const et_tree* tree, int32_t* d_tour, hipStream_t s) {
+  if (!tree || (tree->n > 1 && !d_tour)) return ET_EINVAL;
+  return et::tree_export_tour(&tree->ctx->impl, tree, d_tour, s);
+}
 
 int32_t et_tree_size(const et_tree* tree) {
   if (!tree) return -1;

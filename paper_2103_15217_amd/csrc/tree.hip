@@ -460,6 +460,33 @@ int tree_export(const et_tree* t, int32_t* succ, int32_t* rank, int32_t* depth, 
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }
 
+namespace {
+// tour[rank(e)] = e for every half-edge on the tour
+__global__ void k_tour(const int32_t* __restrict__ rank, int64_t E, int32_t L, int32_t* __restrict__ tour,
+                       uint32_t* __restrict__ status) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int32_t r = rank[e];
+  if (r < 0) return;  // the root's two unused ids
+  if (r >= L) {
+    flag(status, ST_BAD_INDEX);
+    return;
+  }
+  tour[r] = (int32_t)e;
+}
+}  // namespace
+
+int tree_export_tour(Ctx* c, const et_tree* t, int32_t* tour, hipStream_t s) {
+  if (t->batch) return ET_EINVAL;  // the combined tour of a batch is internal
+  const int32_t L = 2 * (t->n - 1);
+  if (L == 0) return ET_OK;
+  // a parent-array tree numbers its half-edges 2c / 2c+1 over all n nodes,
+  // an edge-list tree 2i / 2i+1 over its n-1 edges
+  const int64_t E = t->from_edges ? (int64_t)L : 2 * (int64_t)t->n;
+  hipLaunchKernelGGL(k_tour, dim3(ceil_div(E, kB)), dim3(kB), 0, s, t->d_rank, E, L, tour, c->d_status);
+  return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+}
+
 int tree_lca_batch(Ctx* c, const et_tree* t, const int32_t* qt, const int32_t* qx, const int32_t* qy, int64_t q,
                    int32_t* out, hipStream_t s) {
   if (q == 0) return ET_OK;

@@ -41,6 +41,7 @@ _SIG = {
     "et_lca_batch": ([_P, _P, _P, _P, _i64, _P, _P], ctypes.c_int),
     "et_tree_export": ([_P, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "et_tree_free": ([_P, _P], None),
+    "et_tree_export_tour": ([_P, _P, _P], ctypes.c_int),
     "et_lca": ([_P, _P, _P, _i64, _P, _P], ctypes.c_int),
     "et_bridges": ([_P, _P, _P, _i32, _i32, _P, ctypes.POINTER(_i64), _P], ctypes.c_int),
     "et_bridges_count": ([_P, _P, _P], ctypes.c_int),
@@ -227,6 +228,14 @@ class Tree:
         _check(_lib.et_tree_export(self._h, *[_ptr(out[k]) for k in
                                               ("succ", "rank", "depth", "pre", "size", "inlabel", "asc")],
                                    _stream()), "et_tree_export")
+        return out
+
+    def tour(self, out=None):
+        """The half-edge at every tour position (2(n-1) entries)."""
+        if out is None:
+            out = torch.empty(max(2 * (self.n - 1), 0), dtype=torch.int32,
+                              device=torch.device("cuda", self.ctx.device))
+        _check(_lib.et_tree_export_tour(self._h, _ptr(out), _stream()), "et_tree_export_tour")
         return out
 
     def lca_batch(self, qtree, qx, qy, out=None):

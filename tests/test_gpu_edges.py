@@ -54,6 +54,7 @@ def compare(lib, oracle_mod, n, u, v, root, queries=None, ctx=None):
     L = 2 * (n - 1)
     assert np.array_equal(got["succ"][:L], ref["succ"]), "tour successor"
     assert np.array_equal(got["rank"][:L], ref["rank"]), "tour rank"
+    assert np.array_equal(_np(tree.tour()), ref["tour"]), "tour array"
     for k in ("depth", "pre", "size"):
         assert np.array_equal(got[k], ref[k]), k
     assert np.array_equal(got_parent, ref["parent"]), "parent"

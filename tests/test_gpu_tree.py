@@ -191,3 +191,40 @@ def test_full_size_2e24(lib, oracle_mod, bench_ctx, grasp):
     ctx = bench_ctx("single")
     build_and_compare(lib, oracle_mod, parent, (qx, qy), check_tables=True, ctx=ctx)
     print(f"[full-size grasp={grasp}] compared in {time.time() - t0:.1f}s", flush=True)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 65, 4097, (1 << 17) + 11])
+@pytest.mark.parametrize("grasp", [None, 1])
+def test_tour_array(lib, oracle_mod, n, grasp):
+    parent = gen.random_tree(n, grasp, seed=n + 3)
+    tree = lib.et_tree_build(_dev(parent))
+    got = _np(tree.tour())
+    tree.free()
+    lib.default_context().check()
+    assert np.array_equal(got, oracle_mod.euler_tour(parent)["tour"])
+
+
+def test_tour_array_full_size(lib, bench_ctx):
+    # 2^24 nodes: the tour is the inverse of the exported rank
+    import torch
+    n = 1 << 24
+    parent = gen.random_tree(n, 1000, seed=9)
+    ctx = bench_ctx("single")
+    tree = lib.et_tree_build(_dev(parent), ctx=ctx)
+    tour = tree.tour()
+    rank = tree.export(("rank",))["rank"]
+    ctx.check()
+    L = 2 * (n - 1)
+    assert tour.numel() == L
+    assert torch.equal(rank[tour.long()], torch.arange(L, dtype=torch.int32, device=tour.device))
+    tree.free()
+
+
+def test_tour_array_rejected_for_batches(lib):
+    import torch
+    b = gen.forest_batch(5, seed=2, log2_min=2, log2_max=6)
+    offs = torch.from_numpy(b["offsets"].astype(np.int64)).cuda()
+    tree = lib.et_tree_build_batch(_dev(b["parent"]), offs)
+    with pytest.raises(lib.EtError):
+        tree.tour()
+    tree.free()
