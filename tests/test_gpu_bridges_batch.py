@@ -173,3 +173,33 @@ def test_rejected_inputs(lib):
     lib.et_bridges_batch([(_dev(a[0]), _dev(a[1]))], ctx=ctx)
     ctx.check()
     ctx.close()
+
+
+def test_hundred_thousand_tiny_graphs(lib, oracle_mod):
+    # many more graphs than lanes per search: owners found by binary search
+    # over 10^5 offsets; every graph checked against the oracle
+    rng = np.random.default_rng(123)
+    graphs = []
+    for t in range(100000):
+        n = int(rng.integers(0, 9))
+        if n == 0:
+            graphs.append(_empty_graph(0))
+        else:
+            graphs.append(gen.random_multigraph(n, int(rng.integers(0, 12)), seed=t, loops=True, multi=True))
+    print(f"[bridges batch] {len(graphs)} tiny graphs", flush=True)
+    rows = np.concatenate([g[0] for g in graphs])
+    col = np.concatenate([g[1] for g in graphs])
+    slots = [len(g[1]) for g in graphs]
+    voff = np.concatenate([[0], np.cumsum([len(g[0]) - 1 for g in graphs])])
+    soff = np.concatenate([[0], np.cumsum(slots)])
+    ctx = lib.default_context()
+    mask, spans, counts = lib.et_bridges_batch(row_ptr=_dev(rows), col=_dev(col), voff=_dev(voff, np.int64),
+                                               soff=_dev(soff, np.int64), slots=slots, ctx=ctx)
+    ctx.check()
+    mask = mask.cpu().numpy().view(np.uint32)
+    counts = counts.cpu().numpy()
+    for t, (rp, c) in enumerate(graphs):
+        ref_mask, ref_cnt = oracle_mod.bridges(rp, c)
+        start, words = spans[t]
+        assert np.array_equal(mask[start:start + words], ref_mask), t
+        assert counts[t] == ref_cnt, t
