@@ -4,7 +4,8 @@
 // ranking, into an array scan (Section 2.2). This is a three-kernel
 // reduce-then-scan: each workgroup owns a contiguous range of 4096-element
 // chunks, reduces it, one workgroup scans the per-range totals, and each
-// range is scanned again with its carry. Inside a chunk every lane holds 16
+// range is scanned again with its carry. Arrays of at most four chunks are
+// scanned by one workgroup in one launch. Inside a chunk every lane holds 16
 // consecutive items (four 16-byte loads), scans them serially, and the lane
 // totals are combined across the wavefront with shuffles and across the
 // four wavefronts through LDS.
@@ -17,6 +18,7 @@ constexpr int kThreads = 256;
 constexpr int kItems = 16;
 constexpr int kChunk = kThreads * kItems;
 constexpr int kMaxRanges = 4096;
+constexpr int kSmallChunks = 4;  // arrays of at most 16K items take the one-launch path
 
 template <ScanOp OP>
 __device__ __forceinline__ uint32_t combine(uint32_t a, uint32_t b) {
@@ -133,7 +135,7 @@ __global__ __launch_bounds__(kThreads) void k_range_scan(const uint32_t* __restr
                                                          uint32_t* __restrict__ out, int64_t n,
                                                          int64_t chunks_per_range,
                                                          const uint32_t* __restrict__ partial) {
-  uint32_t carry = partial[blockIdx.x];
+  uint32_t carry = partial ? partial[blockIdx.x] : 0u;
   const int64_t c0 = (int64_t)blockIdx.x * chunks_per_range;
   for (int64_t c = c0; c < c0 + chunks_per_range; ++c) {
     if (c * kChunk >= n) break;
@@ -165,6 +167,16 @@ template <ScanOp OP>
 int scan_impl(Ctx* c, const uint32_t* in, uint32_t* out, int64_t n, bool exclusive, hipStream_t s) {
   if (n <= 0) return ET_OK;
   int64_t chunks = (n + kChunk - 1) / kChunk;
+  if (chunks <= kSmallChunks) {
+    // short arrays: one workgroup scans the few chunks in order, so the
+    // reduce and carry launches are skipped
+    ET_PROF(c, s, OP == ScanOp::Add ? "k_range_scan<add>" : "k_range_scan<xor>");
+    if (exclusive)
+      hipLaunchKernelGGL((k_range_scan<OP, true>), dim3(1), dim3(kThreads), 0, s, in, out, n, chunks, nullptr);
+    else
+      hipLaunchKernelGGL((k_range_scan<OP, false>), dim3(1), dim3(kThreads), 0, s, in, out, n, chunks, nullptr);
+    return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+  }
   int64_t per = (chunks + kMaxRanges - 1) / kMaxRanges;
   int nranges = (int)((chunks + per - 1) / per);
   Scratch sc(c);

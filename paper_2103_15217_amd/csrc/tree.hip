@@ -146,6 +146,30 @@ __global__ void k_asc_level(uint32_t* __restrict__ plab, int32_t n, int t, uint3
   plab[I] = up | (1u << t);
 }
 
+// The levels hi .. lo, each holding at most blockDim.x labels, in one
+// workgroup: one label per lane per level, a barrier between levels (the
+// labels of a level are read by the next one down).
+constexpr int kAscTop = 1024;
+
+__global__ __launch_bounds__(kAscTop) void k_asc_top(uint32_t* __restrict__ plab, int32_t n, int hi, int lo,
+                                                    uint32_t* __restrict__ status) {
+  for (int t = hi; t >= lo; --t) {
+    const int64_t I = ((2 * (int64_t)threadIdx.x + 1) << t);
+    if (I <= n) {
+      const uint32_t pl = plab[I];
+      if (pl != kUnused) {
+        uint32_t up = 0;
+        if (pl != 0) {
+          if (pl <= (uint32_t)n && ctz32(pl) > t) up = plab[pl];
+          else flag(status, ST_BAD_INDEX);
+        }
+        plab[I] = up | (1u << t);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void k_asc(int4* __restrict__ rec, const uint32_t* __restrict__ inl_of,
                       const uint32_t* __restrict__ asc_of_label, int32_t n, uint32_t* __restrict__ status) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -426,8 +450,12 @@ int inlabel_phase(Ctx* c, et_tree* t, const int32_t* parent, const uint32_t* inl
     ET_PROF(c, s, "k_asc_level");
     int top = 0;
     while ((2ll << top) <= n) ++top;  // highest level a label <= n can have
-    for (int lv = top; lv >= 0; --lv) {
-      const int64_t cand = ((int64_t)n >> lv) / 2 + 1;  // labels (2k+1) 2^lv <= n
+    // labels (2k+1) 2^lv <= n of level lv: (n >> lv) / 2 + 1 candidates
+    int lo = top;
+    while (lo > 0 && (((int64_t)n >> (lo - 1)) / 2 + 1) <= kAscTop) --lo;
+    hipLaunchKernelGGL(k_asc_top, dim3(1), dim3(kAscTop), 0, s, plab, n, top, lo, c->d_status);
+    for (int lv = lo - 1; lv >= 0; --lv) {
+      const int64_t cand = ((int64_t)n >> lv) / 2 + 1;
       hipLaunchKernelGGL(k_asc_level, dim3(ceil_div(cand, kB)), dim3(kB), 0, s, plab, n, lv, c->d_status);
     }
   }
