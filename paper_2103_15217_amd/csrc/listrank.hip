@@ -42,12 +42,18 @@ __device__ __forceinline__ int32_t splitter_of_chunk(int32_t i, int ks, uint32_t
   return (int32_t)(((uint32_t)i << ks) + (mix32((uint32_t)i ^ salt) & m));
 }
 
-__global__ void k_fill_int4(int4* __restrict__ p, int32_t begin, int32_t end, int4 v) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + begin;
-  if (i < end) p[i] = v;
-}
-
 __global__ void k_set_scalar(int32_t* __restrict__ p, int32_t v) { *p = v; }
+
+// start of a ranking: the continuation counter and the reached-element
+// count at zero, the continuation records [begin, end) marked unused
+__global__ void k_lr_init(int32_t* __restrict__ ctr, int4* __restrict__ rec, int32_t begin, int32_t end) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    ctr[0] = 0;
+    ctr[1] = 0;
+  }
+  if (begin + i < end) rec[begin + i] = make_int4(-3, 0, 0, 0);
+}
 
 // ------------------------------------------------------------------ level 1
 template <bool TREE>
@@ -245,6 +251,7 @@ constexpr int kFinalPer = kLdsMax / kFinalThreads;
 __global__ __launch_bounds__(kFinalThreads) void k_final_lds(const int4* __restrict__ rec, int32_t T,
                                                              int32_t hb, int32_t H, int2* __restrict__ off,
                                                              int32_t* __restrict__ reached,
+                                                             const int32_t* __restrict__ expected,
                                                              uint32_t* __restrict__ status) {
   __shared__ int32_t pred[kLdsMax];
   __shared__ int32_t acl[kLdsMax];
@@ -308,6 +315,10 @@ __global__ __launch_bounds__(kFinalThreads) void k_final_lds(const int4* __restr
   if (unreached) flag(status, ST_UNREACHED);
   for (int dd = 32; dd >= 1; dd >>= 1) mine += __shfl_xor(mine, dd, 64);
   if (__lane_id() == 0) atomicAdd(reached, mine);
+  // every element must be reached from a head: the whole count is in once
+  // all wavefronts have added theirs
+  __syncthreads();
+  if (threadIdx.x == 0 && expected && atomicAdd(reached, 0) != *expected) flag(status, ST_UNREACHED);
 }
 
 // Final level when many heads keep the list above kLdsMax: one lane per
@@ -410,10 +421,7 @@ int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const 
   int4* rec1 = sc.get<int4>((size_t)T1);
   int32_t* ctr = sc.get<int32_t>(4);
   if (sc.failed) return ET_ENOMEM;
-  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, ctr, 0);
-  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, ctr + 1, 0);
-  hipLaunchKernelGGL(k_fill_int4, dim3(ceil_div(cont_max, 256)), dim3(256), 0, s, rec1, S1 + H, T1,
-                     make_int4(-3, 0, 0, 0));
+  hipLaunchKernelGGL(k_lr_init, dim3(ceil_div(cont_max, 256)), dim3(256), 0, s, ctr, rec1, S1 + H, T1);
   // sublists per wavefront: the context's value, fewer when that would leave
   // under 4096 wavefronts (at least 64, one per lane)
   const int32_t per_wave1 = std::min(c->lr.per_wave1, std::max(64, (S1 + H) >> 12));
@@ -466,7 +474,7 @@ int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const 
     {
       ET_PROF(c, s, "k_final_lds");
       hipLaunchKernelGGL(k_final_lds, dim3(1), dim3(kFinalThreads), 0, s, top.rec, top.T, top.hb, H, top.off,
-                         ctr + 1, c->d_status);
+                         ctr + 1, expected_reach, c->d_status);
     }
   } else {
     {
@@ -474,8 +482,8 @@ int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const 
       hipLaunchKernelGGL(k_final_walk, dim3(ceil_div(H, 256)), dim3(256), 0, s, top.rec, top.T, top.hb, H,
                          top.off, ctr + 1, c->d_status);
     }
+    hipLaunchKernelGGL(k_check_reached, dim3(1), dim3(1), 0, s, ctr + 1, expected_reach, c->d_status);
   }
-  hipLaunchKernelGGL(k_check_reached, dim3(1), dim3(1), 0, s, ctr + 1, expected_reach, c->d_status);
   for (int k = (int)lv.size() - 2; k >= 0; --k) {
     {
       ET_PROF(c, s, "k_push_down");
