@@ -4,8 +4,9 @@
 // ranking, into an array scan (Section 2.2). This is a three-kernel
 // reduce-then-scan: each workgroup owns a contiguous range of 4096-element
 // chunks, reduces it, one workgroup scans the per-range totals, and each
-// range is scanned again with its carry. Arrays of at most four chunks are
-// scanned by one workgroup in one launch. Inside a chunk every lane holds 16
+// range is scanned again with its carry (with at most 512 ranges each range
+// adds up the totals before it and the middle launch is skipped). Arrays of
+// at most four chunks are scanned by one workgroup in one launch. Inside a chunk every lane holds 16
 // consecutive items (four 16-byte loads), scans them serially, and the lane
 // totals are combined across the wavefront with shuffles and across the
 // four wavefronts through LDS.
@@ -19,6 +20,7 @@ constexpr int kItems = 16;
 constexpr int kChunk = kThreads * kItems;
 constexpr int kMaxRanges = 4096;
 constexpr int kSmallChunks = 4;  // arrays of at most 16K items take the one-launch path
+constexpr int kRawRanges = 512;  // up to this many ranges sum their carries themselves
 
 template <ScanOp OP>
 __device__ __forceinline__ uint32_t combine(uint32_t a, uint32_t b) {
@@ -134,8 +136,17 @@ template <ScanOp OP, bool EXCL>
 __global__ __launch_bounds__(kThreads) void k_range_scan(const uint32_t* __restrict__ in,
                                                          uint32_t* __restrict__ out, int64_t n,
                                                          int64_t chunks_per_range,
-                                                         const uint32_t* __restrict__ partial) {
-  uint32_t carry = partial ? partial[blockIdx.x] : 0u;
+                                                         const uint32_t* __restrict__ partial, bool raw) {
+  // carry into this range: none for a single range, the scanned partial, or
+  // (raw partials of a few ranges) their combination over the ranges before
+  uint32_t carry = 0u;
+  if (partial && !raw) {
+    carry = partial[blockIdx.x];
+  } else if (partial) {
+    uint32_t acc = 0u;
+    for (int r = threadIdx.x; r < (int)blockIdx.x; r += kThreads) acc = combine<OP>(acc, partial[r]);
+    (void)block_exclusive<OP>(acc, &carry);
+  }
   const int64_t c0 = (int64_t)blockIdx.x * chunks_per_range;
   for (int64_t c = c0; c < c0 + chunks_per_range; ++c) {
     if (c * kChunk >= n) break;
@@ -172,9 +183,11 @@ int scan_impl(Ctx* c, const uint32_t* in, uint32_t* out, int64_t n, bool exclusi
     // reduce and carry launches are skipped
     ET_PROF(c, s, OP == ScanOp::Add ? "k_range_scan<add>" : "k_range_scan<xor>");
     if (exclusive)
-      hipLaunchKernelGGL((k_range_scan<OP, true>), dim3(1), dim3(kThreads), 0, s, in, out, n, chunks, nullptr);
+      hipLaunchKernelGGL((k_range_scan<OP, true>), dim3(1), dim3(kThreads), 0, s, in, out, n, chunks, nullptr,
+                         false);
     else
-      hipLaunchKernelGGL((k_range_scan<OP, false>), dim3(1), dim3(kThreads), 0, s, in, out, n, chunks, nullptr);
+      hipLaunchKernelGGL((k_range_scan<OP, false>), dim3(1), dim3(kThreads), 0, s, in, out, n, chunks, nullptr,
+                         false);
     return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
   }
   int64_t per = (chunks + kMaxRanges - 1) / kMaxRanges;
@@ -186,18 +199,20 @@ int scan_impl(Ctx* c, const uint32_t* in, uint32_t* out, int64_t n, bool exclusi
     ET_PROF(c, s, OP == ScanOp::Add ? "k_range_reduce<add>" : "k_range_reduce<xor>");
     hipLaunchKernelGGL(k_range_reduce<OP>, dim3(nranges), dim3(kThreads), 0, s, in, n, per, partial);
   }
-  {
+  // a few ranges: each adds up the raw totals before it, one launch fewer
+  const bool raw = nranges <= kRawRanges;
+  if (!raw) {
     ET_PROF(c, s, OP == ScanOp::Add ? "k_scan_partials<add>" : "k_scan_partials<xor>");
     hipLaunchKernelGGL(k_scan_partials<OP>, dim3(1), dim3(1024), 0, s, partial, nranges);
   }
   if (exclusive) {
     ET_PROF(c, s, OP == ScanOp::Add ? "k_range_scan<add,excl>" : "k_range_scan<xor,excl>");
     hipLaunchKernelGGL((k_range_scan<OP, true>), dim3(nranges), dim3(kThreads), 0, s, in, out, n, per,
-                       partial);
+                       partial, raw);
   } else {
     ET_PROF(c, s, OP == ScanOp::Add ? "k_range_scan<add,incl>" : "k_range_scan<xor,incl>");
     hipLaunchKernelGGL((k_range_scan<OP, false>), dim3(nranges), dim3(kThreads), 0, s, in, out, n, per,
-                       partial);
+                       partial, raw);
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }
