@@ -127,6 +127,24 @@ int et_list_rank(et_ctx* ctx, const int32_t* d_succ, int32_t len, const int32_t*
                  int32_t n_heads, int32_t* d_rank, hipStream_t s);
 
 /*
+ * Weighted list ranking: prefix sums along lists (Section 2.2: list ranking
+ * with weights on the elements, the form that gives depth from +1 / -1
+ * weights on a tour).
+ *   d_succ[len], d_heads[n_heads]  as for et_list_rank
+ *   d_weight[len]    weight of each element (int32)
+ *   d_sum[len]       output: the sum of the weights from the element's list
+ *                    head through the element itself, in 32-bit two's
+ *                    complement (sums wrap); 0 for unused slots
+ *   d_rank[len]      optional output (may be NULL): as for et_list_rank
+ * Same sublist ranking, with the weight sums carried next to the lengths;
+ * the walk stores each element's local sum in a scratch array of len
+ * int32. len < 2^31 - 2^20. Malformed lists set ET_EINPUT in the status
+ * word.
+ */
+int et_list_scan(et_ctx* ctx, const int32_t* d_succ, const int32_t* d_weight, int32_t len,
+                 const int32_t* d_heads, int32_t n_heads, int32_t* d_rank, int32_t* d_sum, hipStream_t s);
+
+/*
  * Euler tour and node statistics of a rooted tree (Section 2, Section 2.2),
  * plus the Inlabel tables for LCA queries (Section 3.1).
  *   d_parent[n]  parent id of every node; exactly one node (the root) has

@@ -32,6 +32,7 @@ def _bind(path):
     sig = {
         "oracle_euler_tour": [P, i32, P, P, P, P, P, P],
         "oracle_list_rank": [P, i32, P, i32, P],
+        "oracle_list_scan": [P, P, i32, P, i32, P, P],
         "oracle_lca_climb": [P, P, i32, P, P, i64, P],
         "oracle_lca_offline": [P, i32, P, P, i64, P],
         "oracle_sv_tables": [P, P, P, P, i32, P, P, P, P],
@@ -148,6 +149,18 @@ def list_rank(succ, heads):
     rc = _load().oracle_list_rank(_ptr(succ), succ.shape[0], _ptr(heads), heads.shape[0], _ptr(rank))
     _check(rc, "list_rank")
     return rank
+
+
+def list_scan(succ, weight, heads):
+    """Weighted list ranking: per element the 32-bit wrapping sum of the
+    weights from its list head through it, and its rank."""
+    succ, weight, heads = _i32(succ), _i32(weight), _i32(heads)
+    n = succ.shape[0]
+    rank = np.empty(n, dtype=np.int32)
+    out = np.empty(n, dtype=np.int32)
+    rc = _load().oracle_list_scan(_ptr(succ), _ptr(weight), n, _ptr(heads), heads.shape[0], _ptr(rank), _ptr(out))
+    _check(rc, "list_scan")
+    return out, rank
 
 
 def lca_climb(parent, depth, qx, qy):

@@ -171,6 +171,25 @@ int oracle_list_rank(const int32_t* succ, int32_t len, const int32_t* heads, int
     return used == ranked ? ORC_OK : ORC_EINPUT;
 }
 
+/* Weighted list ranking (Section 2.2): sum[e] = the weights from the head
+ * of e's list through e, added in 32-bit two's complement; rank as in
+ * oracle_list_rank. Unused slots (succ == -2) get rank -1 and sum 0. */
+int oracle_list_scan(const int32_t* succ, const int32_t* weight, int32_t len, const int32_t* heads,
+                     int32_t nheads, int32_t* rank, int32_t* sum) {
+    if (len < 0 || (len > 0 && (!weight || !sum))) return ORC_EINVAL;
+    int rc = oracle_list_rank(succ, len, heads, nheads, rank);
+    if (rc) return rc;
+    for (int32_t e = 0; e < len; ++e) sum[e] = 0;
+    for (int32_t k = 0; k < nheads; ++k) {
+        uint32_t acc = 0;
+        for (int32_t e = heads[k]; e != -1; e = succ[e]) {
+            acc += (uint32_t)weight[e];
+            sum[e] = (int32_t)acc;
+        }
+    }
+    return ORC_OK;
+}
+
 /* LCA by climbing: lift the deeper endpoint to the other's depth, then lift
  * both until they meet. depth[] must be the true depths. */
 int oracle_lca_climb(const int32_t* parent, const int32_t* depth, int32_t n,

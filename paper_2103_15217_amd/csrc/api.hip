@@ -232,6 +232,15 @@ int et_list_rank(et_ctx* ctx, const int32_t* d_succ, int32_t len, const int32_t*
   return et::list_rank_generic(&ctx->impl, d_succ, len, d_heads, n_heads, d_rank, s);
 }
 
+int et_list_scan(et_ctx* ctx, const int32_t* d_succ, const int32_t* d_weight, int32_t len, const int32_t* d_heads,
+                 int32_t n_heads, int32_t* d_rank, int32_t* d_sum, hipStream_t s) {
+  if (!ctx || len < 0 || n_heads < 0 || len > 0x7fffffff - (1 << 20)) return ET_EINVAL;
+  if (len > 0 && (!d_succ || !d_weight || !d_sum)) return ET_EINVAL;
+  if (n_heads > 0 && !d_heads) return ET_EINVAL;
+  if (len > 0 && n_heads == 0) return ET_EINVAL;
+  return et::list_scan_generic(&ctx->impl, d_succ, d_weight, len, d_heads, n_heads, d_rank, d_sum, s);
+}
+
 static et_tree* tree_alloc(et_ctx* ctx, int32_t n, int32_t batch) {
   Ctx* c = &ctx->impl;
   et_tree* t = new (std::nothrow) et_tree();

@@ -205,9 +205,12 @@ struct LRResult {
 };
 // tree_weights: element e counts as "down" iff e is even (tree half-edges).
 // expected_reach: number of elements the heads must reach (device scalar or null)
+// weights / wloc: sum these per-element weights instead (inclusive local sums
+// to wloc, sublist sums in the second channel of out->off)
 int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const int32_t* heads,
                    int32_t nheads, bool tree_weights, const int32_t* expected_reach,
-                   LRResult* out, hipStream_t s, bool empty_head_ok = false);
+                   LRResult* out, hipStream_t s, bool empty_head_ok = false, const int32_t* weights = nullptr,
+                   int32_t* wloc = nullptr);
 // radix.hip: stable sort of (key, value) pairs by the low `bits` key bits
 int sort_pairs_u32(Ctx* c, const uint32_t* keys, const int32_t* vals, int32_t n, int bits, uint32_t* keys_out,
                    int32_t* vals_out, hipStream_t s);
@@ -247,6 +250,8 @@ int lca_naive_run(Ctx* c, const int32_t* parent, const int32_t* level, int32_t n
                   const int32_t* qy, int64_t q, int32_t* out, hipStream_t s);
 int list_rank_generic(Ctx* c, const int32_t* succ, int32_t len, const int32_t* heads,
                       int32_t nheads, int32_t* rank, hipStream_t s);
+int list_scan_generic(Ctx* c, const int32_t* succ, const int32_t* weights, int32_t len, const int32_t* heads,
+                      int32_t nheads, int32_t* rank, int32_t* sum, hipStream_t s);
 
 }  // namespace et
 

@@ -44,6 +44,11 @@ __device__ __forceinline__ int32_t splitter_of_chunk(int32_t i, int ks, uint32_t
 
 __global__ void k_set_scalar(int32_t* __restrict__ p, int32_t v) { *p = v; }
 
+// The second channel (down counts of a tour, or element weights) adds in
+// 32-bit two's complement: weight sums wrap instead of overflowing.
+__device__ __forceinline__ int32_t wadd(int32_t a, int32_t b) { return (int32_t)((uint32_t)a + (uint32_t)b); }
+__device__ __forceinline__ int32_t wsub(int32_t a, int32_t b) { return (int32_t)((uint32_t)a - (uint32_t)b); }
+
 // start of a ranking: the continuation counter and the reached-element
 // count at zero, the continuation records [begin, end) marked unused
 __global__ void k_lr_init(int32_t* __restrict__ ctr, int4* __restrict__ rec, int32_t begin, int32_t end) {
@@ -56,12 +61,16 @@ __global__ void k_lr_init(int32_t* __restrict__ ctr, int4* __restrict__ rec, int
 }
 
 // ------------------------------------------------------------------ level 1
-template <bool TREE>
-__global__ __launch_bounds__(kWalkThreads) void k_walk1(
+// TREE: even ids count as "down" (tree half-edges) and a leaf's two
+// half-edges share one load and one store. W: the weight of every element
+// is summed instead (wrapping in 32 bits); each element's inclusive local
+// sum goes to wloc, since it does not fit the record's 16-bit field.
+template <bool TREE, bool W>
+__device__ __forceinline__ void walk1_body(
     const int32_t* __restrict__ succ, int32_t L, const int32_t* __restrict__ heads, int32_t H, int ks,
     uint32_t salt, int32_t S, int32_t per_wave, uint64_t* __restrict__ packed, int4* __restrict__ srec,
     int32_t* __restrict__ cont_ctr, int32_t cont_base, int32_t cont_max, bool empty_ok,
-    uint32_t* __restrict__ status) {
+    uint32_t* __restrict__ status, const int32_t* __restrict__ wt, int32_t* __restrict__ wloc) {
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int32_t total = S + H;
   int32_t next_id = (int32_t)min<int64_t>(wave * per_wave, total);
@@ -128,6 +137,10 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk1(
       }
       if (!pair) {
         if (TREE) d += ((cur & 1) == 0);
+        if (W) {
+          d = (int32_t)((uint32_t)d + (uint32_t)wt[cur]);
+          wloc[cur] = d;
+        }
         packed[cur] = (uint64_t)(uint32_t)sub | ((uint64_t)(uint32_t)j << 32) | ((uint64_t)(uint32_t)d << 48);
         ++j;
         ++steps;
@@ -164,6 +177,26 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk1(
       }
     }
   }
+}
+
+template <bool TREE>
+__global__ __launch_bounds__(kWalkThreads) void k_walk1(
+    const int32_t* __restrict__ succ, int32_t L, const int32_t* __restrict__ heads, int32_t H, int ks,
+    uint32_t salt, int32_t S, int32_t per_wave, uint64_t* __restrict__ packed, int4* __restrict__ srec,
+    int32_t* __restrict__ cont_ctr, int32_t cont_base, int32_t cont_max, bool empty_ok,
+    uint32_t* __restrict__ status) {
+  walk1_body<TREE, false>(succ, L, heads, H, ks, salt, S, per_wave, packed, srec, cont_ctr, cont_base, cont_max,
+                          empty_ok, status, nullptr, nullptr);
+}
+
+// the same walk summing per-element weights
+__global__ __launch_bounds__(kWalkThreads) void k_walk1w(
+    const int32_t* __restrict__ succ, int32_t L, const int32_t* __restrict__ heads, int32_t H, int ks,
+    uint32_t salt, int32_t S, int32_t per_wave, uint64_t* __restrict__ packed, int4* __restrict__ srec,
+    int32_t* __restrict__ cont_ctr, int32_t cont_base, int32_t cont_max, bool empty_ok,
+    uint32_t* __restrict__ status, const int32_t* __restrict__ wt, int32_t* __restrict__ wloc) {
+  walk1_body<false, true>(succ, L, heads, H, ks, salt, S, per_wave, packed, srec, cont_ctr, cont_base, cont_max,
+                          empty_ok, status, wt, wloc);
 }
 
 // ------------------------------------------------------------------ level k >= 2
@@ -215,7 +248,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_walkN(
       const int4 r = rec[cur];
       el[cur] = make_int4(sub, al, ad, 0);
       al += r.y;
-      ad += r.z;
+      ad = wadd(ad, r.z);
       ++steps;
       const int32_t nx = r.x;
       bool stop = true;
@@ -289,7 +322,7 @@ __global__ __launch_bounds__(kFinalThreads) void k_final_lds(const int4* __restr
       if (p >= 0) {
         np[k] = pred[p];
         nl[k] = acl[e] + acl[p];
-        nd[k] = acd[e] + acd[p];
+        nd[k] = wadd(acd[e], acd[p]);
         nt[k] = top[p];
       } else {
         np[k] = p; nl[k] = acl[e]; nd[k] = acd[e]; nt[k] = top[e];
@@ -310,7 +343,7 @@ __global__ __launch_bounds__(kFinalThreads) void k_final_lds(const int4* __restr
     const bool from_head = (top[e] >= hb && top[e] < hb + H && pred[e] < 0);
     if (used[k] && !from_head) unreached = true;
     if (from_head) mine += wl[k];
-    off[e] = make_int2(acl[e] - wl[k], acd[e] - wd[k]);
+    off[e] = make_int2(acl[e] - wl[k], wsub(acd[e], wd[k]));
   }
   if (unreached) flag(status, ST_UNREACHED);
   for (int dd = 32; dd >= 1; dd >>= 1) mine += __shfl_xor(mine, dd, 64);
@@ -338,7 +371,7 @@ __global__ void k_final_walk(const int4* __restrict__ rec, int32_t T, int32_t hb
     const int4 r = rec[e];
     off[e] = make_int2(al, ad);
     al += r.y;
-    ad += r.z;
+    ad = wadd(ad, r.z);
     e = r.x;
   }
   atomicAdd(reached, al);
@@ -363,7 +396,33 @@ __global__ void k_push_down(const int4* __restrict__ rec, const int4* __restrict
     return;
   }
   const int2 o = off_up[x.x];
-  off[e] = make_int2(o.x + x.y, o.y + x.z);
+  off[e] = make_int2(o.x + x.y, wadd(o.y, x.z));
+}
+
+// weighted list prefix sums: sum[e] = the weight sum before e's sublist +
+// the inclusive local sum; rank as in k_rank_fix (rank may be null); unused
+// slots get rank -1 and sum 0
+__global__ void k_scan_fix(const int32_t* __restrict__ succ, const uint64_t* __restrict__ packed,
+                           const int32_t* __restrict__ wloc, int32_t L, const int2* __restrict__ off, int32_t T1,
+                           int32_t* __restrict__ rank, int32_t* __restrict__ sum, uint32_t* __restrict__ status) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= L) return;
+  if (succ[e] == -2) {
+    if (rank) rank[e] = -1;
+    sum[e] = 0;
+    return;
+  }
+  const uint64_t p = packed[e];
+  const uint32_t sub = (uint32_t)p;
+  if (sub >= (uint32_t)T1) {
+    flag(status, ST_BAD_INDEX);
+    if (rank) rank[e] = -1;
+    sum[e] = 0;
+    return;
+  }
+  const int2 o = off[sub];
+  if (rank) rank[e] = o.x + (int32_t)((p >> 32) & 0xffffu);
+  sum[e] = wadd(o.y, wloc[e]);
 }
 
 // generic rank: rank[e] = off[sub] + local rank, -1 for unused slots
@@ -406,7 +465,7 @@ int walk_grid(int32_t total, int32_t per_wave) {
 
 int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const int32_t* heads,
                    int32_t nheads, bool tree_weights, const int32_t* expected_reach, LRResult* out,
-                   hipStream_t s, bool empty_head_ok) {
+                   hipStream_t s, bool empty_head_ok, const int32_t* weights, int32_t* wloc) {
   const int32_t L = len, H = nheads;
   // Level-1 splitter spacing K = 2^ks1 (a sublist averages K elements).
   // Shorter lists keep more, shorter sublists: below about 2^25 elements the
@@ -430,6 +489,11 @@ int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const 
     hipLaunchKernelGGL(k_walk1<true>, dim3(walk_grid(S1 + H, per_wave1)), dim3(kWalkThreads), 0, s, succ, L,
                        heads, H, ks1, kSalt, S1, per_wave1, packed, rec1, ctr, S1 + H, cont_max,
                        empty_head_ok, c->d_status);
+  } else if (weights) {
+    ET_PROF(c, s, "k_walk1w");
+    hipLaunchKernelGGL(k_walk1w, dim3(walk_grid(S1 + H, per_wave1)), dim3(kWalkThreads), 0, s, succ, L, heads, H,
+                       ks1, kSalt, S1, per_wave1, packed, rec1, ctr, S1 + H, cont_max, empty_head_ok, c->d_status,
+                       weights, wloc);
   } else {
     ET_PROF(c, s, "k_walk1<false>");
     hipLaunchKernelGGL(k_walk1<false>, dim3(walk_grid(S1 + H, per_wave1)), dim3(kWalkThreads), 0, s, succ,
@@ -516,6 +580,30 @@ int list_rank_generic(Ctx* c, const int32_t* succ, int32_t len, const int32_t* h
     ET_PROF(c, s, "k_rank_fix");
     hipLaunchKernelGGL(k_rank_fix, dim3(ceil_div(len, 256)), dim3(256), 0, s, succ, r.packed, len, r.off,
                        r.nsub, rank, c->d_status);
+  }
+  return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+}
+
+int list_scan_generic(Ctx* c, const int32_t* succ, const int32_t* weights, int32_t len, const int32_t* heads,
+                      int32_t nheads, int32_t* rank, int32_t* sum, hipStream_t s) {
+  if (len == 0) return ET_OK;
+  Scratch sc(c);
+  int32_t* expected = sc.get<int32_t>(1);
+  int32_t* wloc = sc.get<int32_t>((size_t)len);
+  if (sc.failed) return ET_ENOMEM;
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, expected, 0);
+  {
+    ET_PROF(c, s, "k_count_used");
+    hipLaunchKernelGGL(k_count_used, dim3(std::min(ceil_div(len, 256), 2048)), dim3(256), 0, s, succ, len,
+                       expected);
+  }
+  LRResult r;
+  int rc = list_rank_core(c, sc, succ, len, heads, nheads, false, expected, &r, s, false, weights, wloc);
+  if (rc) return rc;
+  {
+    ET_PROF(c, s, "k_scan_fix");
+    hipLaunchKernelGGL(k_scan_fix, dim3(ceil_div(len, 256)), dim3(256), 0, s, succ, r.packed, wloc, len, r.off,
+                       r.nsub, rank, sum, c->d_status);
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }

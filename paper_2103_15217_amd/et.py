@@ -34,6 +34,7 @@ _SIG = {
     "et_ctx_set_param": ([_P, ctypes.c_char_p, _i64], ctypes.c_int),
     "et_ctx_profile_read": ([_P, _P, ctypes.c_char_p, _i32], ctypes.c_int),
     "et_list_rank": ([_P, _P, _i32, _P, _i32, _P, _P], ctypes.c_int),
+    "et_list_scan": ([_P, _P, _P, _i32, _P, _i32, _P, _P, _P], ctypes.c_int),
     "et_tree_build": ([_P, _P, _i32, _P, ctypes.POINTER(_P)], ctypes.c_int),
     "et_tree_size": ([_P], _i32),
     "et_tree_batch_size": ([_P], _i32),
@@ -288,6 +289,23 @@ class Tree:
             self.free()
         except Exception:
             pass
+
+
+def et_list_scan(succ, weight, heads, rank=False, ctx=None):
+    """Prefix sums of ``weight`` along the lists starting at ``heads``: the
+    sum from each element's head through the element (int32, wrapping);
+    with ``rank`` also the ranks (returns (sum, rank) then)."""
+    ctx = ctx or default_context()
+    succ = _dev(succ, torch.int32, "succ")
+    weight = _dev(weight, torch.int32, "weight")
+    heads = _dev(heads, torch.int32, "heads")
+    if weight.numel() != succ.numel():
+        raise ValueError("succ and weight differ in length")
+    out = torch.empty_like(succ)
+    r = torch.empty_like(succ) if rank else None
+    _check(_lib.et_list_scan(ctx.handle, _ptr(succ), _ptr(weight), succ.numel(), _ptr(heads), heads.numel(),
+                             _ptr(r), _ptr(out), _stream()), "et_list_scan")
+    return (out, r) if rank else out
 
 
 def et_tree_build(parent, ctx=None):

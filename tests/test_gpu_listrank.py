@@ -91,3 +91,46 @@ def test_malformed_lists_set_status(lib, bad):
     with pytest.raises(lib.EtError):
         ctx.check()
     ctx.close()
+
+
+@pytest.mark.parametrize("L,nlists,unused,seed", [
+    (1, 1, 0.0, 20), (15, 3, 0.2, 21), (4097, 7, 0.1, 22), (100003, 1000, 0.3, 23), (1 << 20, 1, 0.0, 24),
+    (1 << 20, 20000, 0.05, 25)])
+def test_list_scan_random_weights(lib, oracle_mod, L, nlists, unused, seed):
+    # weights over all of int32: sums wrap modulo 2^32 on both sides
+    succ, heads = random_lists(L, nlists, unused, seed)
+    w = np.random.default_rng(seed).integers(-(1 << 31), 1 << 31, size=L).astype(np.int32)
+    ctx = lib.default_context()
+    s, r = lib.et_list_scan(_dev(succ), _dev(w), _dev(heads), rank=True)
+    ctx.check()
+    ref_s, ref_r = oracle_mod.list_scan(succ, w, heads)
+    assert np.array_equal(s.cpu().numpy(), ref_s)
+    assert np.array_equal(r.cpu().numpy(), ref_r)
+
+
+@pytest.mark.parametrize("grasp", [None, 1000, 1])
+def test_list_scan_tour_weights_give_depth_2e24(lib, oracle_mod, bench_ctx, grasp):
+    # +1 on down half-edges and -1 on up ones along the 2^24-node tour: the
+    # sum at 2c is depth(c) (Section 2)
+    import gen
+    n = 1 << 24
+    parent = gen.random_tree(n, grasp, seed=41)
+    succ, head = oracle_mod.tree_succ(parent)
+    w = np.where(np.arange(2 * n) % 2 == 0, 1, -1).astype(np.int32)
+    ctx = bench_ctx("single")
+    s = lib.et_list_scan(_dev(succ), _dev(w), _dev([head]), ctx=ctx).cpu().numpy()
+    ctx.check()
+    depth = oracle_mod.euler_tour(parent)["depth"]
+    c = np.flatnonzero(parent >= 0)
+    assert np.array_equal(s[2 * c], depth[c])
+    assert np.array_equal(s[2 * c + 1], depth[c] - 1)
+
+
+def test_list_scan_malformed_list_flagged(lib):
+    succ, heads = random_lists(10000, 1, 0.0, 30)
+    succ[succ[heads[0]]] = heads[0]
+    ctx = lib.Context()
+    lib.et_list_scan(_dev(succ), _dev(np.ones(10000, np.int32)), _dev(heads), ctx=ctx)
+    with pytest.raises(lib.EtError):
+        ctx.check()
+    ctx.close()

@@ -62,6 +62,9 @@ MUTANTS = {
     "list_rank_origin": ("int32_t r = 0;\n        while (e != -1) {", "int32_t r = 1;\n        while (e != -1) {"),
     # only the first list of a multi-list input is walked
     "list_rank_heads": ("for (int32_t h = 0; h < nheads; ++h) {", "for (int32_t h = 0; h < nheads && h < 1; ++h) {"),
+    # list scan exclusive instead of inclusive
+    "list_scan_excl": ("acc += (uint32_t)weight[e];\n            sum[e] = (int32_t)acc;",
+                       "sum[e] = (int32_t)acc;\n            acc += (uint32_t)weight[e];"),
     # low values not passed up from a finished child
     "bridge_low_up": ("if (low[u] < low[p]) low[p] = low[u];", "(void)low[p];"),
     # only the parent-to-child slot of a bridge marked
@@ -88,6 +91,8 @@ def battery(mod):
         lambda: pins.test_tour_invariants(mod, 2000, None, 2),
         lambda: pins.test_tour_matches_networkx_dfs(mod, 0),
         *[lambda s=s: pins.test_list_rank_vs_pointer_jumping(mod, s) for s in range(4)],
+        *[lambda s=s: pins.test_list_scan_unit_weights_are_ranks_plus_one(mod, s) for s in range(2)],
+        *[lambda g=g: pins.test_list_scan_of_tour_weights_gives_depth(mod, g) for g in (None, 1)],
         *[lambda s=s: pins.test_lca_bruteforce_all_pairs(mod, s) for s in range(12)],
         lambda: pins.test_lca_closed_forms(mod),
         *[lambda s=s: pins.test_sv_tables_and_query(mod, s) for s in range(20)],

@@ -233,6 +233,64 @@ def test_list_rank_vs_pointer_jumping(oracle_mod, seed):
     assert np.array_equal(r, brute.list_rank_pointer_jumping(succ, heads))
 
 
+def _random_lists(seed):
+    rng = np.random.default_rng(seed)
+    L = int(rng.integers(1, 3000))
+    nlists = int(rng.integers(1, min(L, 9) + 1))
+    unused = rng.random(L) < 0.1
+    ids = rng.permutation(np.nonzero(~unused)[0])
+    if ids.shape[0] < nlists:
+        ids = rng.permutation(L)
+    cuts = np.sort(rng.choice(np.arange(1, ids.shape[0]), size=nlists - 1, replace=False)) if nlists > 1 else []
+    succ = np.full(L, -2, dtype=np.int32)
+    heads = []
+    for part in np.split(ids, cuts):
+        succ[part[:-1]] = part[1:]
+        succ[part[-1]] = -1
+        heads.append(int(part[0]))
+    return succ, np.array(heads, np.int32), rng
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_list_scan_unit_weights_are_ranks_plus_one(oracle_mod, seed):
+    succ, heads, _ = _random_lists(100 + seed)
+    s, r = oracle_mod.list_scan(succ, np.ones_like(succ), heads)
+    used = succ != -2
+    assert np.array_equal(s[used], r[used] + 1)
+    assert np.array_equal(r, brute.list_rank_pointer_jumping(succ, list(heads)))
+    assert not s[~used].any()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_list_scan_random_weights_by_walking(oracle_mod, seed):
+    # weights anywhere in int32, sums wrapping modulo 2^32: each list walked in Python
+    succ, heads, rng = _random_lists(200 + seed)
+    w = rng.integers(-(1 << 31), 1 << 31, size=succ.shape[0]).astype(np.int32)
+    s, _ = oracle_mod.list_scan(succ, w, heads)
+    want = np.zeros_like(succ)
+    for h in heads:
+        acc, e = 0, int(h)
+        while e != -1:
+            acc = (acc + int(w[e])) % (1 << 32)
+            want[e] = acc - (1 << 32) if acc >= (1 << 31) else acc
+            e = int(succ[e])
+    assert np.array_equal(s, want)
+
+
+@pytest.mark.parametrize("grasp", [None, 5, 1])
+def test_list_scan_of_tour_weights_gives_depth(oracle_mod, grasp):
+    # +1 on every down half-edge, -1 on every up one: the sum at 2c is the
+    # depth of c (Section 2), which the DFS tour computes on its own
+    parent = gen.random_tree(5000, grasp, seed=7)
+    succ, head = oracle_mod.tree_succ(parent)
+    w = np.where(np.arange(succ.shape[0]) % 2 == 0, 1, -1).astype(np.int32)
+    s, _ = oracle_mod.list_scan(succ, w, np.array([head], np.int32))
+    depth = oracle_mod.euler_tour(parent)["depth"]
+    c = np.flatnonzero(parent >= 0)
+    assert np.array_equal(s[2 * c], depth[c])
+    assert np.array_equal(s[2 * c + 1], depth[c] - 1)
+
+
 def test_list_rank_rejects_bad_lists(oracle_mod):
     with pytest.raises(oracle_mod.OracleInputError):   # cycle reachable from the head
         oracle_mod.list_rank(np.array([1, 2, 1], np.int32), np.array([0], np.int32))
