@@ -82,6 +82,8 @@ def parse():
                     help="skip the edge-list (DCEL construction) build comparison")
     ap.add_argument("--no-naive", action="store_true",
                     help="skip the naive (climbing) LCA comparison and its depth and q:n sweeps")
+    ap.add_argument("--no-lists", action="store_true",
+                    help="skip the plain vs weighted list ranking of the tours and of a random list")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--serve-sweep", default="1000,4000,8000,16000",
@@ -310,6 +312,9 @@ def main():
     if not args.no_naive:
         log("naive LCA: levels and climbing queries")
         result["components"]["naive_lca"] = naive_vs_inlabel(args, et, ctx, d, d_parent, d_qx, d_qy, grasps)
+    if not args.no_lists:
+        log("list ranking: plain and weighted")
+        result["components"]["list_ranking"] = list_ranking(args, et, ctx, d, d_parent)
     if not args.no_serve:
         log("serving: generating the job pool")
         result["components"]["serving"] = serving(args, dev)
@@ -511,6 +516,57 @@ def naive_vs_inlabel(args, et, ctx, d, d_parent, d_qx, d_qy, grasps):
         nv, il = both(parent, 1 << lq)
         res["q_sweep"].append({"n": m, "grasp": m, "q": 1 << lq, "naive_ms": nv, "inlabel_ms": il})
     ctx.check()
+    return res
+
+
+def list_ranking(args, et, ctx, d, d_parent):
+    """List ranking on its own (Section 2.2): the tours of the three bench
+    trees ranked plain and with weights +1 on down and -1 on up half-edges
+    (the weighted sum at a down half-edge is that child's depth, checked
+    against the build's depth), and one random list of 2^(log2n+1)
+    elements with weights in [-2^20, 2^20)."""
+    import numpy as np
+    import torch
+    res = {"tours": {}}
+    for name, parent in zip(["n", "1000", "1"], d_parent):
+        tree = et.et_tree_build(parent, ctx=ctx)
+        t = tree.export(["succ", "depth"])
+        head = tree.tour()[:1].clone()
+        tree.free()
+        succ = t["succ"]
+        w = (1 - 2 * (torch.arange(succ.numel(), device=succ.device, dtype=torch.int32) & 1)).to(torch.int32)
+        L = succ.numel() - 2
+        r = {"elements": L}
+        r["rank_ms"] = _gpu_ms(lambda: et.et_list_rank(succ, head, ctx=ctx))
+        r["scan_ms"] = _gpu_ms(lambda: et.et_list_scan(succ, w, head, ctx=ctx))
+        r["scan_and_rank_ms"] = _gpu_ms(lambda: et.et_list_scan(succ, w, head, rank=True, ctx=ctx))
+        sums = et.et_list_scan(succ, w, head, ctx=ctx)
+        down = sums[0::2]
+        used = succ[0::2] != -2
+        r["depth_matches_build"] = bool(torch.equal(down[used], t["depth"][used]))
+        r["rank_elements_per_s"] = L / (r["rank_ms"] * 1e-3)
+        r["scan_elements_per_s"] = L / (r["scan_ms"] * 1e-3)
+        res["tours"][name] = r
+        ctx.check()
+    L = 1 << (args.log2n + 1)
+    rng = np.random.default_rng(args.seed + 11)
+    order = rng.permutation(L).astype(np.int32)
+    succ = np.empty(L, dtype=np.int32)
+    succ[order[:-1]] = order[1:]
+    succ[order[-1]] = -1
+    dsucc, head = d(succ), d(order[:1].copy())
+    dw = d(rng.integers(-(1 << 20), 1 << 20, L, dtype=np.int32))
+    r = {"elements": L}
+    r["rank_ms"] = _gpu_ms(lambda: et.et_list_rank(dsucc, head, ctx=ctx))
+    r["scan_ms"] = _gpu_ms(lambda: et.et_list_scan(dsucc, dw, head, ctx=ctx))
+    rank = et.et_list_rank(dsucc, head, ctx=ctx)
+    r["rank_is_position"] = bool(torch.equal(rank[d(order).long()],
+                                             torch.arange(L, dtype=torch.int32, device=rank.device)))
+    r["rank_elements_per_s"] = L / (r["rank_ms"] * 1e-3)
+    r["scan_elements_per_s"] = L / (r["scan_ms"] * 1e-3)
+    res["random_list"] = r
+    ctx.check()
+    log(f"list ranking 2^{args.log2n + 1}: rank {r['rank_ms']:.3f} ms, weighted {r['scan_ms']:.3f} ms")
     return res
 
 

@@ -62,15 +62,17 @@ __global__ void k_lr_init(int32_t* __restrict__ ctr, int4* __restrict__ rec, int
 
 // ------------------------------------------------------------------ level 1
 // TREE: even ids count as "down" (tree half-edges) and a leaf's two
-// half-edges share one load and one store. W: the weight of every element
-// is summed instead (wrapping in 32 bits); each element's inclusive local
-// sum goes to wloc, since it does not fit the record's 16-bit field.
+// half-edges share one load and one store. W: succ holds {successor, weight}
+// pairs (one 8-byte load per step) and the weights are summed instead
+// (wrapping in 32 bits); the record is then 16 bytes per element, its second
+// word the inclusive local sum, which does not fit the 16-bit field.
 template <bool TREE, bool W>
 __device__ __forceinline__ void walk1_body(
     const int32_t* __restrict__ succ, int32_t L, const int32_t* __restrict__ heads, int32_t H, int ks,
     uint32_t salt, int32_t S, int32_t per_wave, uint64_t* __restrict__ packed, int4* __restrict__ srec,
     int32_t* __restrict__ cont_ctr, int32_t cont_base, int32_t cont_max, bool empty_ok,
-    uint32_t* __restrict__ status, const int32_t* __restrict__ wt, int32_t* __restrict__ wloc) {
+    uint32_t* __restrict__ status) {
+  constexpr int kStride = W ? 2 : 1;  // int32 words per element in succ
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int32_t total = S + H;
   int32_t next_id = (int32_t)min<int64_t>(wave * per_wave, total);
@@ -86,7 +88,7 @@ __device__ __forceinline__ void walk1_body(
         if (id < end_id) {
           if (id < S) {
             const int32_t e = splitter_of_chunk(id, ks, salt);
-            if (e >= L || succ[e] == -2) {
+            if (e >= L || succ[kStride * (int64_t)e] == -2) {
               srec[id] = make_int4(-3, 0, 0, 0);  // no element here
             } else {
               cur = e; sub = id; j = 0; d = 0;
@@ -95,7 +97,7 @@ __device__ __forceinline__ void walk1_body(
             const int32_t e = heads[id - S];
             if (e == -1 && empty_ok) {
               srec[id] = make_int4(-1, 0, 0, 0);  // an empty list
-            } else if (e < 0 || e >= L || succ[e] == -2) {
+            } else if (e < 0 || e >= L || succ[kStride * (int64_t)e] == -2) {
               flag(status, ST_BAD_HEAD);
               srec[id] = make_int4(-1, 0, 0, 0);
             } else if (is_splitter(e, ks, salt)) {
@@ -132,15 +134,19 @@ __device__ __forceinline__ void walk1_body(
           nx = sp.y;
           pair = true;
         }
+      } else if (W) {
+        const int2 sw = *reinterpret_cast<const int2*>(succ + 2 * (int64_t)cur);
+        nx = sw.x;
+        d = wadd(d, sw.y);
+        *reinterpret_cast<ulonglong2*>(packed + 2 * (int64_t)cur) =
+            make_ulonglong2((uint64_t)(uint32_t)sub | ((uint64_t)(uint32_t)j << 32), (uint64_t)(uint32_t)d);
+        ++j;
+        ++steps;
       } else {
         nx = succ[cur];
       }
-      if (!pair) {
+      if (!pair && !W) {
         if (TREE) d += ((cur & 1) == 0);
-        if (W) {
-          d = (int32_t)((uint32_t)d + (uint32_t)wt[cur]);
-          wloc[cur] = d;
-        }
         packed[cur] = (uint64_t)(uint32_t)sub | ((uint64_t)(uint32_t)j << 32) | ((uint64_t)(uint32_t)d << 48);
         ++j;
         ++steps;
@@ -186,17 +192,17 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk1(
     int32_t* __restrict__ cont_ctr, int32_t cont_base, int32_t cont_max, bool empty_ok,
     uint32_t* __restrict__ status) {
   walk1_body<TREE, false>(succ, L, heads, H, ks, salt, S, per_wave, packed, srec, cont_ctr, cont_base, cont_max,
-                          empty_ok, status, nullptr, nullptr);
+                          empty_ok, status);
 }
 
-// the same walk summing per-element weights
+// the same walk over {successor, weight} pairs, summing the weights
 __global__ __launch_bounds__(kWalkThreads) void k_walk1w(
-    const int32_t* __restrict__ succ, int32_t L, const int32_t* __restrict__ heads, int32_t H, int ks,
+    const int32_t* __restrict__ sw, int32_t L, const int32_t* __restrict__ heads, int32_t H, int ks,
     uint32_t salt, int32_t S, int32_t per_wave, uint64_t* __restrict__ packed, int4* __restrict__ srec,
     int32_t* __restrict__ cont_ctr, int32_t cont_base, int32_t cont_max, bool empty_ok,
-    uint32_t* __restrict__ status, const int32_t* __restrict__ wt, int32_t* __restrict__ wloc) {
-  walk1_body<false, true>(succ, L, heads, H, ks, salt, S, per_wave, packed, srec, cont_ctr, cont_base, cont_max,
-                          empty_ok, status, wt, wloc);
+    uint32_t* __restrict__ status) {
+  walk1_body<false, true>(sw, L, heads, H, ks, salt, S, per_wave, packed, srec, cont_ctr, cont_base, cont_max,
+                          empty_ok, status);
 }
 
 // ------------------------------------------------------------------ level k >= 2
@@ -400,19 +406,20 @@ __global__ void k_push_down(const int4* __restrict__ rec, const int4* __restrict
 }
 
 // weighted list prefix sums: sum[e] = the weight sum before e's sublist +
-// the inclusive local sum; rank as in k_rank_fix (rank may be null); unused
-// slots get rank -1 and sum 0
-__global__ void k_scan_fix(const int32_t* __restrict__ succ, const uint64_t* __restrict__ packed,
-                           const int32_t* __restrict__ wloc, int32_t L, const int2* __restrict__ off, int32_t T1,
-                           int32_t* __restrict__ rank, int32_t* __restrict__ sum, uint32_t* __restrict__ status) {
+// the inclusive local sum (the 16-byte record's second word); rank as in
+// k_rank_fix (rank may be null); unused slots get rank -1 and sum 0
+__global__ void k_scan_fix(const int2* __restrict__ sw, const ulonglong2* __restrict__ packed, int32_t L,
+                           const int2* __restrict__ off, int32_t T1, int32_t* __restrict__ rank,
+                           int32_t* __restrict__ sum, uint32_t* __restrict__ status) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= L) return;
-  if (succ[e] == -2) {
+  if (sw[e].x == -2) {
     if (rank) rank[e] = -1;
     sum[e] = 0;
     return;
   }
-  const uint64_t p = packed[e];
+  const ulonglong2 pk = packed[e];
+  const uint64_t p = pk.x;
   const uint32_t sub = (uint32_t)p;
   if (sub >= (uint32_t)T1) {
     flag(status, ST_BAD_INDEX);
@@ -422,7 +429,7 @@ __global__ void k_scan_fix(const int32_t* __restrict__ succ, const uint64_t* __r
   }
   const int2 o = off[sub];
   if (rank) rank[e] = o.x + (int32_t)((p >> 32) & 0xffffu);
-  sum[e] = wadd(o.y, wloc[e]);
+  sum[e] = wadd(o.y, (int32_t)(uint32_t)pk.y);
 }
 
 // generic rank: rank[e] = off[sub] + local rank, -1 for unused slots
@@ -456,6 +463,23 @@ __global__ void k_count_used(const int32_t* __restrict__ succ, int32_t L, int32_
   if (threadIdx.x == 0) atomicAdd(count, part[0] + part[1] + part[2] + part[3]);
 }
 
+// {successor, weight} pairs for the weighted walk, and the number of used
+// elements (successor other than -2) as in k_count_used
+__global__ void k_pair_count(const int32_t* __restrict__ succ, const int32_t* __restrict__ w, int32_t L,
+                             int2* __restrict__ sw, int32_t* __restrict__ count) {
+  __shared__ int32_t part[4];
+  int32_t c = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < L; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t x = succ[e];
+    sw[e] = make_int2(x, w[e]);
+    c += (x != -2);
+  }
+  for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+  if (__lane_id() == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(count, part[0] + part[1] + part[2] + part[3]);
+}
+
 int walk_grid(int32_t total, int32_t per_wave) {
   const int64_t waves = (total + (int64_t)per_wave - 1) / per_wave;
   return (int)((waves * 64 + kWalkThreads - 1) / kWalkThreads);
@@ -465,7 +489,7 @@ int walk_grid(int32_t total, int32_t per_wave) {
 
 int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const int32_t* heads,
                    int32_t nheads, bool tree_weights, const int32_t* expected_reach, LRResult* out,
-                   hipStream_t s, bool empty_head_ok, const int32_t* weights, int32_t* wloc) {
+                   hipStream_t s, bool empty_head_ok, bool weighted) {
   const int32_t L = len, H = nheads;
   // Level-1 splitter spacing K = 2^ks1 (a sublist averages K elements).
   // Shorter lists keep more, shorter sublists: below about 2^25 elements the
@@ -476,7 +500,7 @@ int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const 
   const int32_t S1 = (int32_t)(((int64_t)L + (1 << ks1) - 1) >> ks1);
   const int32_t cont_max = L / kCap + H + 64;
   const int32_t T1 = S1 + H + cont_max;
-  uint64_t* packed = sc.get<uint64_t>((size_t)L);
+  uint64_t* packed = sc.get<uint64_t>((size_t)L * (weighted ? 2 : 1));
   int4* rec1 = sc.get<int4>((size_t)T1);
   int32_t* ctr = sc.get<int32_t>(4);
   if (sc.failed) return ET_ENOMEM;
@@ -489,11 +513,10 @@ int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const 
     hipLaunchKernelGGL(k_walk1<true>, dim3(walk_grid(S1 + H, per_wave1)), dim3(kWalkThreads), 0, s, succ, L,
                        heads, H, ks1, kSalt, S1, per_wave1, packed, rec1, ctr, S1 + H, cont_max,
                        empty_head_ok, c->d_status);
-  } else if (weights) {
+  } else if (weighted) {
     ET_PROF(c, s, "k_walk1w");
     hipLaunchKernelGGL(k_walk1w, dim3(walk_grid(S1 + H, per_wave1)), dim3(kWalkThreads), 0, s, succ, L, heads, H,
-                       ks1, kSalt, S1, per_wave1, packed, rec1, ctr, S1 + H, cont_max, empty_head_ok, c->d_status,
-                       weights, wloc);
+                       ks1, kSalt, S1, per_wave1, packed, rec1, ctr, S1 + H, cont_max, empty_head_ok, c->d_status);
   } else {
     ET_PROF(c, s, "k_walk1<false>");
     hipLaunchKernelGGL(k_walk1<false>, dim3(walk_grid(S1 + H, per_wave1)), dim3(kWalkThreads), 0, s, succ,
@@ -589,21 +612,22 @@ int list_scan_generic(Ctx* c, const int32_t* succ, const int32_t* weights, int32
   if (len == 0) return ET_OK;
   Scratch sc(c);
   int32_t* expected = sc.get<int32_t>(1);
-  int32_t* wloc = sc.get<int32_t>((size_t)len);
+  int2* sw = sc.get<int2>((size_t)len);
   if (sc.failed) return ET_ENOMEM;
   hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, expected, 0);
   {
-    ET_PROF(c, s, "k_count_used");
-    hipLaunchKernelGGL(k_count_used, dim3(std::min(ceil_div(len, 256), 2048)), dim3(256), 0, s, succ, len,
-                       expected);
+    ET_PROF(c, s, "k_pair_count");
+    hipLaunchKernelGGL(k_pair_count, dim3(std::min(ceil_div(len, 256), 2048)), dim3(256), 0, s, succ, weights,
+                       len, sw, expected);
   }
   LRResult r;
-  int rc = list_rank_core(c, sc, succ, len, heads, nheads, false, expected, &r, s, false, weights, wloc);
+  int rc = list_rank_core(c, sc, reinterpret_cast<const int32_t*>(sw), len, heads, nheads, false, expected, &r, s,
+                          false, true);
   if (rc) return rc;
   {
     ET_PROF(c, s, "k_scan_fix");
-    hipLaunchKernelGGL(k_scan_fix, dim3(ceil_div(len, 256)), dim3(256), 0, s, succ, r.packed, wloc, len, r.off,
-                       r.nsub, rank, sum, c->d_status);
+    hipLaunchKernelGGL(k_scan_fix, dim3(ceil_div(len, 256)), dim3(256), 0, s, sw,
+                       reinterpret_cast<const ulonglong2*>(r.packed), len, r.off, r.nsub, rank, sum, c->d_status);
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }

@@ -95,7 +95,7 @@ def test_malformed_lists_set_status(lib, bad):
 
 @pytest.mark.parametrize("L,nlists,unused,seed", [
     (1, 1, 0.0, 20), (15, 3, 0.2, 21), (4097, 7, 0.1, 22), (100003, 1000, 0.3, 23), (1 << 20, 1, 0.0, 24),
-    (1 << 20, 20000, 0.05, 25)])
+    (1 << 20, 20000, 0.05, 25), (1 << 25, 3, 0.01, 26)])
 def test_list_scan_random_weights(lib, oracle_mod, L, nlists, unused, seed):
     # weights over all of int32: sums wrap modulo 2^32 on both sides
     succ, heads = random_lists(L, nlists, unused, seed)
