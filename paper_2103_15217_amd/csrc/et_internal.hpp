@@ -205,12 +205,13 @@ struct LRResult {
 };
 // tree_weights: element e counts as "down" iff e is even (tree half-edges).
 // expected_reach: number of elements the heads must reach (device scalar or null)
-// weighted: succ holds {successor, weight} int32 pairs and the weights are
-// summed instead; packed then has two words per element, the second the
-// inclusive local sum, and the sublist sums are the second channel of out->off
+// weighted 1 or 2: succ holds {successor, weight} int32 pairs and the
+// weights are summed instead (sublist sums in the second channel of
+// out->off); packed then holds {sublist, inclusive local sum} per element
+// (1), or two words {sublist | local rank << 32, inclusive local sum} (2)
 int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const int32_t* heads,
                    int32_t nheads, bool tree_weights, const int32_t* expected_reach,
-                   LRResult* out, hipStream_t s, bool empty_head_ok = false, bool weighted = false);
+                   LRResult* out, hipStream_t s, bool empty_head_ok = false, int weighted = 0);
 // radix.hip: stable sort of (key, value) pairs by the low `bits` key bits
 int sort_pairs_u32(Ctx* c, const uint32_t* keys, const int32_t* vals, int32_t n, int bits, uint32_t* keys_out,
                    int32_t* vals_out, hipStream_t s);

@@ -62,17 +62,19 @@ __global__ void k_lr_init(int32_t* __restrict__ ctr, int4* __restrict__ rec, int
 
 // ------------------------------------------------------------------ level 1
 // TREE: even ids count as "down" (tree half-edges) and a leaf's two
-// half-edges share one load and one store. W: succ holds {successor, weight}
-// pairs (one 8-byte load per step) and the weights are summed instead
-// (wrapping in 32 bits); the record is then 16 bytes per element, its second
-// word the inclusive local sum, which does not fit the 16-bit field.
-template <bool TREE, bool W>
+// half-edges share one load and one store. W > 0: succ holds {successor,
+// weight} pairs (one 8-byte load per step) and the weights are summed
+// instead (wrapping in 32 bits); the inclusive local sum does not fit the
+// 16-bit field, so the record is {sublist, local sum} (W = 1, 8 bytes) or,
+// when ranks are wanted too, {sublist | local rank << 32, local sum}
+// (W = 2, 16 bytes).
+template <bool TREE, int W>
 __device__ __forceinline__ void walk1_body(
     const int32_t* __restrict__ succ, int32_t L, const int32_t* __restrict__ heads, int32_t H, int ks,
     uint32_t salt, int32_t S, int32_t per_wave, uint64_t* __restrict__ packed, int4* __restrict__ srec,
     int32_t* __restrict__ cont_ctr, int32_t cont_base, int32_t cont_max, bool empty_ok,
     uint32_t* __restrict__ status) {
-  constexpr int kStride = W ? 2 : 1;  // int32 words per element in succ
+  constexpr int kStride = W > 0 ? 2 : 1;  // int32 words per element in succ
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int32_t total = S + H;
   int32_t next_id = (int32_t)min<int64_t>(wave * per_wave, total);
@@ -134,18 +136,21 @@ __device__ __forceinline__ void walk1_body(
           nx = sp.y;
           pair = true;
         }
-      } else if (W) {
+      } else if (W > 0) {
         const int2 sw = *reinterpret_cast<const int2*>(succ + 2 * (int64_t)cur);
         nx = sw.x;
         d = wadd(d, sw.y);
-        *reinterpret_cast<ulonglong2*>(packed + 2 * (int64_t)cur) =
-            make_ulonglong2((uint64_t)(uint32_t)sub | ((uint64_t)(uint32_t)j << 32), (uint64_t)(uint32_t)d);
+        if (W == 1)
+          packed[cur] = (uint64_t)(uint32_t)sub | ((uint64_t)(uint32_t)d << 32);
+        else
+          *reinterpret_cast<ulonglong2*>(packed + 2 * (int64_t)cur) =
+              make_ulonglong2((uint64_t)(uint32_t)sub | ((uint64_t)(uint32_t)j << 32), (uint64_t)(uint32_t)d);
         ++j;
         ++steps;
       } else {
         nx = succ[cur];
       }
-      if (!pair && !W) {
+      if (!pair && W == 0) {
         if (TREE) d += ((cur & 1) == 0);
         packed[cur] = (uint64_t)(uint32_t)sub | ((uint64_t)(uint32_t)j << 32) | ((uint64_t)(uint32_t)d << 48);
         ++j;
@@ -191,18 +196,20 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk1(
     uint32_t salt, int32_t S, int32_t per_wave, uint64_t* __restrict__ packed, int4* __restrict__ srec,
     int32_t* __restrict__ cont_ctr, int32_t cont_base, int32_t cont_max, bool empty_ok,
     uint32_t* __restrict__ status) {
-  walk1_body<TREE, false>(succ, L, heads, H, ks, salt, S, per_wave, packed, srec, cont_ctr, cont_base, cont_max,
-                          empty_ok, status);
+  walk1_body<TREE, 0>(succ, L, heads, H, ks, salt, S, per_wave, packed, srec, cont_ctr, cont_base, cont_max,
+                      empty_ok, status);
 }
 
-// the same walk over {successor, weight} pairs, summing the weights
+// the same walk over {successor, weight} pairs, summing the weights; RANK:
+// the records keep the local ranks too
+template <bool RANK>
 __global__ __launch_bounds__(kWalkThreads) void k_walk1w(
     const int32_t* __restrict__ sw, int32_t L, const int32_t* __restrict__ heads, int32_t H, int ks,
     uint32_t salt, int32_t S, int32_t per_wave, uint64_t* __restrict__ packed, int4* __restrict__ srec,
     int32_t* __restrict__ cont_ctr, int32_t cont_base, int32_t cont_max, bool empty_ok,
     uint32_t* __restrict__ status) {
-  walk1_body<false, true>(sw, L, heads, H, ks, salt, S, per_wave, packed, srec, cont_ctr, cont_base, cont_max,
-                          empty_ok, status);
+  walk1_body<false, RANK ? 2 : 1>(sw, L, heads, H, ks, salt, S, per_wave, packed, srec, cont_ctr, cont_base,
+                                  cont_max, empty_ok, status);
 }
 
 // ------------------------------------------------------------------ level k >= 2
@@ -406,30 +413,39 @@ __global__ void k_push_down(const int4* __restrict__ rec, const int4* __restrict
 }
 
 // weighted list prefix sums: sum[e] = the weight sum before e's sublist +
-// the inclusive local sum (the 16-byte record's second word); rank as in
-// k_rank_fix (rank may be null); unused slots get rank -1 and sum 0
-__global__ void k_scan_fix(const int2* __restrict__ sw, const ulonglong2* __restrict__ packed, int32_t L,
+// the inclusive local sum; RANK: also rank as in k_rank_fix (16-byte
+// records). Unused slots get rank -1 and sum 0.
+template <bool RANK>
+__global__ void k_scan_fix(const int2* __restrict__ sw, const uint64_t* __restrict__ packed, int32_t L,
                            const int2* __restrict__ off, int32_t T1, int32_t* __restrict__ rank,
                            int32_t* __restrict__ sum, uint32_t* __restrict__ status) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= L) return;
   if (sw[e].x == -2) {
-    if (rank) rank[e] = -1;
+    if (RANK) rank[e] = -1;
     sum[e] = 0;
     return;
   }
-  const ulonglong2 pk = packed[e];
-  const uint64_t p = pk.x;
-  const uint32_t sub = (uint32_t)p;
+  uint32_t sub, lsum, lrank = 0;
+  if (RANK) {
+    const ulonglong2 pk = reinterpret_cast<const ulonglong2*>(packed)[e];
+    sub = (uint32_t)pk.x;
+    lrank = (uint32_t)(pk.x >> 32) & 0xffffu;
+    lsum = (uint32_t)pk.y;
+  } else {
+    const uint64_t p = packed[e];
+    sub = (uint32_t)p;
+    lsum = (uint32_t)(p >> 32);
+  }
   if (sub >= (uint32_t)T1) {
     flag(status, ST_BAD_INDEX);
-    if (rank) rank[e] = -1;
+    if (RANK) rank[e] = -1;
     sum[e] = 0;
     return;
   }
   const int2 o = off[sub];
-  if (rank) rank[e] = o.x + (int32_t)((p >> 32) & 0xffffu);
-  sum[e] = wadd(o.y, (int32_t)(uint32_t)pk.y);
+  if (RANK) rank[e] = o.x + (int32_t)lrank;
+  sum[e] = wadd(o.y, (int32_t)lsum);
 }
 
 // generic rank: rank[e] = off[sub] + local rank, -1 for unused slots
@@ -489,7 +505,7 @@ int walk_grid(int32_t total, int32_t per_wave) {
 
 int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const int32_t* heads,
                    int32_t nheads, bool tree_weights, const int32_t* expected_reach, LRResult* out,
-                   hipStream_t s, bool empty_head_ok, bool weighted) {
+                   hipStream_t s, bool empty_head_ok, int weighted) {
   const int32_t L = len, H = nheads;
   // Level-1 splitter spacing K = 2^ks1 (a sublist averages K elements).
   // Shorter lists keep more, shorter sublists: below about 2^25 elements the
@@ -500,7 +516,7 @@ int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const 
   const int32_t S1 = (int32_t)(((int64_t)L + (1 << ks1) - 1) >> ks1);
   const int32_t cont_max = L / kCap + H + 64;
   const int32_t T1 = S1 + H + cont_max;
-  uint64_t* packed = sc.get<uint64_t>((size_t)L * (weighted ? 2 : 1));
+  uint64_t* packed = sc.get<uint64_t>((size_t)L * (weighted == 2 ? 2 : 1));
   int4* rec1 = sc.get<int4>((size_t)T1);
   int32_t* ctr = sc.get<int32_t>(4);
   if (sc.failed) return ET_ENOMEM;
@@ -514,8 +530,9 @@ int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const 
                        heads, H, ks1, kSalt, S1, per_wave1, packed, rec1, ctr, S1 + H, cont_max,
                        empty_head_ok, c->d_status);
   } else if (weighted) {
-    ET_PROF(c, s, "k_walk1w");
-    hipLaunchKernelGGL(k_walk1w, dim3(walk_grid(S1 + H, per_wave1)), dim3(kWalkThreads), 0, s, succ, L, heads, H,
+    ET_PROF(c, s, weighted == 2 ? "k_walk1w<true>" : "k_walk1w<false>");
+    const auto kern = weighted == 2 ? k_walk1w<true> : k_walk1w<false>;
+    hipLaunchKernelGGL(kern, dim3(walk_grid(S1 + H, per_wave1)), dim3(kWalkThreads), 0, s, succ, L, heads, H,
                        ks1, kSalt, S1, per_wave1, packed, rec1, ctr, S1 + H, cont_max, empty_head_ok, c->d_status);
   } else {
     ET_PROF(c, s, "k_walk1<false>");
@@ -622,12 +639,13 @@ int list_scan_generic(Ctx* c, const int32_t* succ, const int32_t* weights, int32
   }
   LRResult r;
   int rc = list_rank_core(c, sc, reinterpret_cast<const int32_t*>(sw), len, heads, nheads, false, expected, &r, s,
-                          false, true);
+                          false, rank ? 2 : 1);
   if (rc) return rc;
   {
-    ET_PROF(c, s, "k_scan_fix");
-    hipLaunchKernelGGL(k_scan_fix, dim3(ceil_div(len, 256)), dim3(256), 0, s, sw,
-                       reinterpret_cast<const ulonglong2*>(r.packed), len, r.off, r.nsub, rank, sum, c->d_status);
+    ET_PROF(c, s, rank ? "k_scan_fix<true>" : "k_scan_fix<false>");
+    const auto kern = rank ? k_scan_fix<true> : k_scan_fix<false>;
+    hipLaunchKernelGGL(kern, dim3(ceil_div(len, 256)), dim3(256), 0, s, sw, r.packed, len, r.off, r.nsub, rank, sum,
+                       c->d_status);
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }

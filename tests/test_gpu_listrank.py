@@ -102,10 +102,12 @@ def test_list_scan_random_weights(lib, oracle_mod, L, nlists, unused, seed):
     w = np.random.default_rng(seed).integers(-(1 << 31), 1 << 31, size=L).astype(np.int32)
     ctx = lib.default_context()
     s, r = lib.et_list_scan(_dev(succ), _dev(w), _dev(heads), rank=True)
+    s_only = lib.et_list_scan(_dev(succ), _dev(w), _dev(heads))  # the sums-only records
     ctx.check()
     ref_s, ref_r = oracle_mod.list_scan(succ, w, heads)
     assert np.array_equal(s.cpu().numpy(), ref_s)
     assert np.array_equal(r.cpu().numpy(), ref_r)
+    assert np.array_equal(s_only.cpu().numpy(), ref_s)
 
 
 @pytest.mark.parametrize("grasp", [None, 1000, 1])
