@@ -277,6 +277,29 @@ def test_list_scan_random_weights_by_walking(oracle_mod, seed):
     assert np.array_equal(s, want)
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_list_scan_by_doubling_and_cumsum(oracle_mod, seed):
+    # another route to the same sums: every element finds its list's tail by
+    # pointer doubling, elements are ordered by (tail, pointer-jumping rank),
+    # and the weights are summed by numpy's cumsum within each list
+    succ, heads, rng = _random_lists(300 + seed)
+    w = rng.integers(-(1 << 31), 1 << 31, size=succ.shape[0]).astype(np.int32)
+    s, r = oracle_mod.list_scan(succ, w, heads)
+    used = np.flatnonzero(succ != -2)
+    tail = np.where(succ == -1, np.arange(succ.shape[0]), succ).astype(np.int64)
+    for _ in range(int(np.ceil(np.log2(max(2, succ.shape[0])))) + 1):
+        tail = np.where(tail >= 0, tail[np.maximum(tail, 0)], tail)
+    rank = brute.list_rank_pointer_jumping(succ, list(heads))
+    order = used[np.lexsort((rank[used], tail[used]))]
+    csum = np.cumsum(w[order].astype(np.int64))
+    starts = np.flatnonzero(np.r_[True, tail[order][1:] != tail[order][:-1]])
+    base = np.repeat(np.r_[0, csum][starts], np.diff(np.r_[starts, order.shape[0]]))
+    want = np.zeros_like(succ)
+    want[order] = ((csum - base) % (1 << 32)).astype(np.uint32).view(np.int32)
+    assert np.array_equal(s, want)
+    assert np.array_equal(r, rank)
+
+
 @pytest.mark.parametrize("grasp", [None, 5, 1])
 def test_list_scan_of_tour_weights_gives_depth(oracle_mod, grasp):
     # +1 on every down half-edge, -1 on every up one: the sum at 2c is the
