@@ -136,10 +136,11 @@ int et_list_rank(et_ctx* ctx, const int32_t* d_succ, int32_t len, const int32_t*
  *                    head through the element itself, in 32-bit two's
  *                    complement (sums wrap); 0 for unused slots
  *   d_rank[len]      optional output (may be NULL): as for et_list_rank
- * Same sublist ranking, with the weight sums carried next to the lengths;
- * the walk stores each element's local sum in a scratch array of len
- * int32. len < 2^31 - 2^20. Malformed lists set ET_EINPUT in the status
- * word.
+ * Same sublist ranking, with the weight sums carried next to the lengths.
+ * Scratch from the context's pool: {successor, weight} pairs (8 bytes per
+ * element) that the walk reads with one load per step, and one record per
+ * element of 8 bytes (16 with d_rank) holding its local sum. len < 2^31 -
+ * 2^20. Malformed lists set ET_EINPUT in the status word.
  */
 int et_list_scan(et_ctx* ctx, const int32_t* d_succ, const int32_t* d_weight, int32_t len,
                  const int32_t* d_heads, int32_t n_heads, int32_t* d_rank, int32_t* d_sum, hipStream_t s);
