@@ -15,7 +15,10 @@ determine the result at any size (the oracle would take minutes here):
   climbing;
 * a graph of a 2^29-vertex cycle and a (2^29 - 1)-vertex path (n = 2^30 - 1
   vertices, nnz = 2^31 - 4 slots), relabelled: exactly the path edges are
-  bridges.
+  bridges;
+* one list of 2^31 - 2^20 - 1 elements (the longest et_list_rank and
+  et_list_scan accept) visiting e_i = i * a mod L: rank(e_i) = i, and the
+  weighted sums equal a cumulative sum taken in list order by torch.
 """
 import numpy as np
 import pytest
@@ -90,6 +93,44 @@ def test_path_at_the_node_limit(lib, ctx):
     assert np.array_equal(got, np.where(pos[qx] <= pos[qy], qx, qy))
     tree.free()
     log("path checked")
+
+
+def test_lists_at_the_length_limit(lib, ctx):
+    import math
+    L = (1 << 31) - (1 << 20) - 1
+    a = 1_000_003
+    assert math.gcd(a, L) == 1
+    i = torch.arange(L, dtype=torch.int64, device="cuda")
+    order = (i * a) % L                                   # element at list position i
+    succ = torch.empty(L, dtype=torch.int32, device="cuda")
+    succ[order[:-1]] = order[1:].to(torch.int32)
+    succ[order[-1]] = -1
+    head = order[:1].to(torch.int32)
+    pos = i.to(torch.int32)
+    del i
+    log(f"list L={L} generated")
+    torch.cuda.empty_cache()                               # leave the library's pool room
+    rank = lib.et_list_rank(succ, head, ctx=ctx)
+    ctx.check()
+    assert torch.equal(rank[order], pos)
+    log("ranks checked")
+    e = torch.arange(L, dtype=torch.int64, device="cuda")
+    w = (((e * 2654435761) >> 13) % 65536 - 32768).to(torch.int32)   # weight of element e, in [-2^15, 2^15)
+    del e
+    torch.cuda.empty_cache()                               # leave the library's pool room
+    s = lib.et_list_scan(succ, w, head, ctx=ctx)
+    ctx.check()
+    want = torch.cumsum(w[order].to(torch.int64), 0)
+    want = ((want + (1 << 31)) % (1 << 32) - (1 << 31)).to(torch.int32)
+    assert torch.equal(s[order], want)
+    del s
+    log("sums checked")
+    torch.cuda.empty_cache()                               # leave the library's pool room
+    s, r = lib.et_list_scan(succ, w, head, rank=True, ctx=ctx)
+    ctx.check()
+    assert torch.equal(r, rank)
+    assert torch.equal(s[order], want)
+    log("sums with ranks checked")
 
 
 def test_star_with_random_root(lib, ctx):
