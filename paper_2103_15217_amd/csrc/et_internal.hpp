@@ -192,7 +192,8 @@ int scan_u32(Ctx* c, const uint32_t* in, uint32_t* out, int64_t n, ScanOp op, bo
 // radix.hip: stable grouping of child ids by parent id (LSD radix sort of
 // (parent, child) pairs). keys_out / vals_out receive the sorted parents and
 // children; scalars[0] = root id, scalars[1] = number of roots; succ[2c] of
-// every non-root c is set to 2c+1 and both root ids to -2.
+// every non-root c is set to 2c+1 and succ[2c+1] to -2 (the successor step
+// writes it), both root ids to -2.
 int group_by_parent_impl(Ctx* c, const int32_t* parent, int32_t n, uint32_t* keys_out,
                          int32_t* vals_out, int32_t* succ, int32_t* scalars, hipStream_t s);
 

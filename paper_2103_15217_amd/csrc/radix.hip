@@ -66,7 +66,10 @@ __global__ __launch_bounds__(kThreads) void k_upsweep(const void* __restrict__ k
         succ[2 * idx + 1] = -2;
       } else {
         if (p < 0 || p >= n || p == idx) bad = true;
-        succ[2 * idx] = (int32_t)(2 * idx + 1);  // leaf unless overwritten by the successor step
+        // succ(2c) = 2c+1 (a leaf unless the successor step writes the first
+        // child); succ(2c+1) is always written by that step, so the pair is
+        // stored whole: one full 8-byte store instead of a strided 4-byte one
+        reinterpret_cast<int2*>(succ)[idx] = make_int2((int32_t)(2 * idx + 1), -2);
       }
     } else {
       key = static_cast<const uint32_t*>(keys_in)[idx];
@@ -116,7 +119,9 @@ __global__ __launch_bounds__(kThreads, 4) void k_downsweep(const void* __restric
     }
     const uint32_t dg = (key[r] >> shift) & mask;
     uint64_t peers = __ballot(valid);
-    for (int b = 0; b < nbits; ++b) {
+#pragma unroll
+    for (int b = 0; b < (DIG > 256 ? 9 : 8); ++b) {
+      if (b >= nbits) break;
       const bool bit = (dg >> b) & 1u;
       const uint64_t bal = __ballot(bit);
       peers &= bit ? bal : ~bal;
@@ -216,8 +221,8 @@ int plan_passes(int bits, int64_t n, int* width) {
 }  // namespace
 
 // keys_out / vals_out receive the stable order; scalars[0] = root, scalars[1]
-// = number of roots; succ[2c] of every non-root c is set to 2c+1 and both
-// root ids to -2.
+// = number of roots; succ[2c] of every non-root c is set to 2c+1 and
+// succ[2c+1] to -2 (the successor step writes it), both root ids to -2.
 int group_by_parent_impl(Ctx* c, const int32_t* parent, int32_t n, uint32_t* keys_out, int32_t* vals_out,
                          int32_t* succ, int32_t* scalars, hipStream_t s) {
   int bits = 1;
