@@ -46,6 +46,8 @@ def test_host_argument_checks():
     assert lib.et_tree_build(None, None, 10, None, ctypes.byref(out)) == -1
     lib.et_list_rank.argtypes = [P, P, ctypes.c_int32, P, ctypes.c_int32, P, P]
     assert lib.et_list_rank(None, None, 5, None, 1, None, None) == -1
+    lib.et_list_scan.argtypes = [P, P, P, ctypes.c_int32, P, ctypes.c_int32, P, P, P]
+    assert lib.et_list_scan(None, None, None, 5, None, 1, None, None, None) == -1
     lib.et_lca.argtypes = [P, P, P, ctypes.c_int64, P, P]
     assert lib.et_lca(None, None, None, 5, None, None) == -1
     lib.et_bridges.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_int32, P, P, P]
