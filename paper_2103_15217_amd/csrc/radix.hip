@@ -52,12 +52,20 @@ __global__ __launch_bounds__(kThreads) void k_upsweep(const void* __restrict__ k
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kTile;
   bool bad = false;
+  // all of a lane's loads first (guarded, not cut short), then the counts
+  uint32_t raw[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t idx = base + r * kThreads + threadIdx.x;
+    raw[r] = idx < n ? static_cast<const uint32_t*>(keys_in)[idx] : 0u;
+  }
+#pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const int64_t idx = base + r * kThreads + threadIdx.x;
     if (idx >= n) break;
     uint32_t key;
     if (FIRST) {
-      const int32_t p = static_cast<const int32_t*>(keys_in)[idx];
+      const int32_t p = (int32_t)raw[r];
       key = parent_key(p, n);
       if (p == -1) {
         atomicAdd(&scalars[1], 1);
@@ -72,7 +80,7 @@ __global__ __launch_bounds__(kThreads) void k_upsweep(const void* __restrict__ k
         reinterpret_cast<int2*>(succ)[idx] = make_int2((int32_t)(2 * idx + 1), -2);
       }
     } else {
-      key = static_cast<const uint32_t*>(keys_in)[idx];
+      key = raw[r];
     }
     atomicAdd(&h[wave][(key >> shift) & mask], 1u);
   }
