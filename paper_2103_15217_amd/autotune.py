@@ -147,6 +147,39 @@ def batch_workload(et, ctx, trees, graphs):
     return [forest, graph_batch]
 
 
+def coordinate_search(cost, grid=None, start=None, rounds=2, log=print):
+    """Coordinate descent over ``grid`` from ``start``: each round tries every
+    other value of every parameter with the rest held, and keeps a trial
+    that is at least 0.5 % faster. The winner is then timed once more
+    against ``start``; if it is not faster there, ``start`` is kept, so a
+    pick that only won through noise is dropped. Returns (best, its cost,
+    the start's cost, [(params, cost)] of every trial)."""
+    grid = GRID if grid is None else grid
+    start = dict(DEFAULT if start is None else start)
+    best = dict(start)
+    best_ms = cost(best)
+    log(f"default {best} -> {best_ms:.3f} ms")
+    table = [(dict(best), best_ms)]
+    for _ in range(rounds):
+        improved = False
+        for name, values in grid.items():
+            for v in values:
+                if v == best[name]:
+                    continue
+                trial = dict(best, **{name: v})
+                ms = cost(trial)
+                table.append((trial, ms))
+                log(f"  {name}={v}: {ms:.3f} ms")
+                if ms < best_ms * 0.995:
+                    best, best_ms, improved = trial, ms, True
+        if not improved:
+            break
+    final, default = cost(best), cost(start)
+    if final >= default:
+        best, final = dict(start), default
+    return best, final, default, table
+
+
 def tune(workload="single", log2n=24, graph_log2n=22, batch_trees=4096, batch_graphs=1024, reps=3, rounds=2,
          log=print):
     import paper_2103_15217_amd as et
@@ -161,28 +194,7 @@ def tune(workload="single", log2n=24, graph_log2n=22, batch_trees=4096, batch_gr
             ctx.set_param(k, v)
         return sum(_best_ms(f, reps) for f in parts)
 
-    best = dict(DEFAULT)
-    best_ms = cost(best)
-    log(f"default {best} -> {best_ms:.3f} ms")
-    table = [(dict(best), best_ms)]
-    for _ in range(rounds):
-        improved = False
-        for name, values in GRID.items():
-            for v in values:
-                if v == best[name]:
-                    continue
-                trial = dict(best, **{name: v})
-                ms = cost(trial)
-                table.append((trial, ms))
-                log(f"  {name}={v}: {ms:.3f} ms")
-                if ms < best_ms * 0.995:
-                    best, best_ms, improved = trial, ms, True
-        if not improved:
-            break
-    # the winner against the default once more, so that a noisy pick is not kept
-    final, default = cost(best), cost(DEFAULT)
-    if final >= default:
-        best, final = dict(DEFAULT), default
+    best, final, default, table = coordinate_search(cost, rounds=rounds, log=log)
     ctx.check()
     log(f"best {best} -> {final:.3f} ms (default {default:.3f} ms)")
     return best, final, default, table

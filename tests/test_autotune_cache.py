@@ -51,3 +51,29 @@ def test_missing_cache_means_library_defaults(tmp_path, monkeypatch, workload):
     monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "absent.json"))
     ctx = _FakeCtx()
     assert autotune.apply(ctx, workload) is None and ctx.params == {}
+
+
+def test_coordinate_search_finds_a_separable_minimum():
+    grid = {"a": [1, 2, 3, 4], "b": [10, 20, 30], "c": [0, 1]}
+    target = {"a": 3, "b": 10, "c": 1}
+    calls = []
+
+    def cost(p):
+        calls.append(dict(p))
+        return 100.0 + sum(abs(grid[k].index(p[k]) - grid[k].index(target[k])) for k in grid)
+    best, ms, default, table = autotune.coordinate_search(cost, grid, {"a": 1, "b": 30, "c": 0},
+                                                          log=lambda m: None)
+    assert best == target and ms == 100.0 and default == 105.0
+    assert len(table) == len(calls) - 2          # the winner and the start timed again at the end
+
+
+def test_coordinate_search_drops_a_pick_that_does_not_hold_up():
+    # a trial that looks fast once but not when timed again is not kept
+    grid = {"a": [1, 2]}
+    seen = {}
+
+    def cost(p):
+        seen[p["a"]] = seen.get(p["a"], 0) + 1
+        return 50.0 if (p["a"] == 2 and seen[2] == 1) else 100.0
+    best, ms, default, _ = autotune.coordinate_search(cost, grid, {"a": 1}, log=lambda m: None)
+    assert best == {"a": 1} and ms == default == 100.0
