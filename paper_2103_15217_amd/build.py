@@ -2,9 +2,12 @@
 
 Every HIP translation unit under ``csrc/`` is compiled to an object in a
 build folder next to this file and linked into ``libet.so`` in the package
-directory, where the Python binding loads it. The random-access ceiling
-probe (``probe/ceiling.hip``, a standalone measurement program that does
-not use the library) is built next to its source.
+directory, where the Python binding loads it.
+
+The random-access ceiling probe (``probe/ceiling.hip``) is a standalone
+measurement program that does not use the library; the library build does
+not touch it. ``python paper_2103_15217_amd/build.py probe`` (or
+:func:`build_probe`) builds it next to its source.
 """
 import os
 import subprocess
@@ -62,13 +65,21 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError("link failed\n" + r.stderr)
     os.replace(tmp, LIB)
+    return LIB
+
+
+def build_probe():
+    """Build the random-access ceiling probe (measurement only)."""
     tmp = PROBE + ".tmp"
     r = subprocess.run([HIPCC, *FLAGS, PROBE_SRC, "-o", tmp], capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("probe build failed\n" + r.stderr)
     os.replace(tmp, PROBE)
-    return LIB
+    return PROBE
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    if len(sys.argv) > 1 and sys.argv[1] == "probe":
+        print(build_probe())
+    else:
+        print(build(verbose=True))

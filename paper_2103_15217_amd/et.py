@@ -98,6 +98,20 @@ def _dev(t, dtype, name):
     return t
 
 
+INT32_MAX = (1 << 31) - 1
+NODE_MAX = (1 << 30) - 1          # nodes of a tree, vertices of a graph (et.h)
+LIST_MAX = INT32_MAX - (1 << 20)  # elements of one et_list_rank / et_list_scan call
+
+
+def _i32(value, name, limit=INT32_MAX):
+    """A size that goes to an int32 argument of the C ABI: ctypes would
+    truncate a larger one silently (2^32 + 5 becomes 5), so refuse it here."""
+    value = int(value)
+    if value < 0 or value > limit:
+        raise ValueError(f"{name} = {value} is outside the library's range [0, {limit}]")
+    return value
+
+
 def version():
     return _lib.et_version()
 
@@ -181,9 +195,11 @@ def et_list_rank(succ, heads, rank=None, ctx=None):
     ctx = ctx or default_context()
     succ = _dev(succ, torch.int32, "succ")
     heads = _dev(heads, torch.int32, "heads")
+    L = _i32(succ.numel(), "list length", LIST_MAX)
+    H = _i32(heads.numel(), "number of list heads")
     if rank is None:
         rank = torch.empty_like(succ)
-    _check(_lib.et_list_rank(ctx.handle, _ptr(succ), succ.numel(), _ptr(heads), heads.numel(),
+    _check(_lib.et_list_rank(ctx.handle, _ptr(succ), L, _ptr(heads), H,
                              _ptr(rank), _stream()), "et_list_rank")
     return rank
 
@@ -301,9 +317,11 @@ def et_list_scan(succ, weight, heads, rank=False, ctx=None):
     heads = _dev(heads, torch.int32, "heads")
     if weight.numel() != succ.numel():
         raise ValueError("succ and weight differ in length")
+    L = _i32(succ.numel(), "list length", LIST_MAX)
+    H = _i32(heads.numel(), "number of list heads")
     out = torch.empty_like(succ)
     r = torch.empty_like(succ) if rank else None
-    _check(_lib.et_list_scan(ctx.handle, _ptr(succ), _ptr(weight), succ.numel(), _ptr(heads), heads.numel(),
+    _check(_lib.et_list_scan(ctx.handle, _ptr(succ), _ptr(weight), L, _ptr(heads), H,
                              _ptr(r), _ptr(out), _stream()), "et_list_scan")
     return (out, r) if rank else out
 
@@ -311,10 +329,11 @@ def et_list_scan(succ, weight, heads, rank=False, ctx=None):
 def et_tree_build(parent, ctx=None):
     ctx = ctx or default_context()
     parent = _dev(parent, torch.int32, "parent")
+    n = _i32(parent.numel(), "tree size", NODE_MAX)
     h = _P()
-    _check(_lib.et_tree_build(ctx.handle, _ptr(parent), parent.numel(), _stream(), ctypes.byref(h)),
+    _check(_lib.et_tree_build(ctx.handle, _ptr(parent), n, _stream(), ctypes.byref(h)),
            "et_tree_build")
-    return Tree(h, parent.numel(), ctx)
+    return Tree(h, n, ctx)
 
 
 def et_tree_build_edges(u, v, n, root, ctx=None, parent_out=None):
@@ -324,6 +343,7 @@ def et_tree_build_edges(u, v, n, root, ctx=None, parent_out=None):
     ctx = ctx or default_context()
     u = _dev(u, torch.int32, "u")
     v = _dev(v, torch.int32, "v")
+    n = _i32(n, "tree size", NODE_MAX)
     if u.numel() != n - 1 or v.numel() != n - 1:
         raise ValueError("a tree on n nodes has n - 1 edges")
     if parent_out is not None:
@@ -347,7 +367,8 @@ def et_tree_build_batch(parent, offsets, ctx=None):
     ctx = ctx or default_context()
     parent = _dev(parent, torch.int32, "parent")
     offsets = _dev(offsets, torch.int64, "offsets")
-    T = offsets.numel() - 1
+    T = _i32(offsets.numel() - 1, "number of trees")
+    _i32(parent.numel(), "batch size", NODE_MAX - 1)
     h = _P()
     _check(_lib.et_tree_build_batch(ctx.handle, _ptr(parent), _ptr(offsets), T, parent.numel(), _stream(),
                                     ctypes.byref(h)), "et_tree_build_batch")
@@ -366,8 +387,8 @@ def et_bridges(row_ptr, col, mask=None, ctx=None, count=True):
     ctx = ctx or default_context()
     row_ptr = _dev(row_ptr, torch.int32, "row_ptr")
     col = _dev(col, torch.int32, "col")
-    n = row_ptr.numel() - 1
-    nnz = col.numel()
+    n = _i32(row_ptr.numel() - 1, "vertex count", NODE_MAX)
+    nnz = _i32(col.numel(), "CSR slot count")
     if mask is None:
         mask = torch.empty(max((nnz + 31) // 32, 1), dtype=torch.int32, device=col.device)
     c = _i64(0)
@@ -408,9 +429,9 @@ def et_bridges_batch(graphs=None, *, row_ptr=None, col=None, voff=None, soff=Non
         if soff.numel() != voff.numel():
             raise ValueError("voff and soff must have the same length")
         ss = list(slots) if slots is not None else torch.diff(soff).cpu().tolist()
-    T = len(ss)
-    n_total = row_ptr.numel() - T
-    nnz = col.numel()
+    T = _i32(len(ss), "number of graphs")
+    n_total = _i32(row_ptr.numel() - T, "total vertex count", NODE_MAX)
+    nnz = _i32(col.numel(), "total CSR slot count")
     if T < 1 or n_total < 0 or sum(ss) != nnz:
         raise ValueError("offsets do not match the concatenated arrays")
     words = [(x + 31) // 32 for x in ss]
@@ -434,8 +455,8 @@ def et_bridges_ck(row_ptr, col, spanning="bfs", mask=None, ctx=None, count=True)
     ctx = ctx or default_context()
     row_ptr = _dev(row_ptr, torch.int32, "row_ptr")
     col = _dev(col, torch.int32, "col")
-    n = row_ptr.numel() - 1
-    nnz = col.numel()
+    n = _i32(row_ptr.numel() - 1, "vertex count", NODE_MAX)
+    nnz = _i32(col.numel(), "CSR slot count")
     if mask is None:
         mask = torch.empty(max((nnz + 31) // 32, 1), dtype=torch.int32, device=col.device)
     c = _i64(0)
@@ -449,9 +470,10 @@ def et_levels(parent, out=None, ctx=None):
     """Node levels by pointer jumping (the naive algorithm's preprocessing)."""
     ctx = ctx or default_context()
     parent = _dev(parent, torch.int32, "parent")
+    n = _i32(parent.numel(), "tree size", NODE_MAX)
     if out is None:
         out = torch.empty_like(parent)
-    _check(_lib.et_levels(ctx.handle, _ptr(parent), parent.numel(), _ptr(out), _stream()), "et_levels")
+    _check(_lib.et_levels(ctx.handle, _ptr(parent), n, _ptr(out), _stream()), "et_levels")
     return out
 
 
@@ -464,9 +486,10 @@ def et_lca_naive(parent, level, qx, qy, out=None, ctx=None):
     qy = _dev(qy, torch.int32, "qy")
     if qx.numel() != qy.numel() or level.numel() != parent.numel():
         raise ValueError("array lengths differ")
+    n = _i32(parent.numel(), "tree size", NODE_MAX)
     if out is None:
         out = torch.empty_like(qx)
-    _check(_lib.et_lca_naive(ctx.handle, _ptr(parent), _ptr(level), parent.numel(), _ptr(qx), _ptr(qy),
+    _check(_lib.et_lca_naive(ctx.handle, _ptr(parent), _ptr(level), n, _ptr(qx), _ptr(qy),
                              qx.numel(), _ptr(out), _stream()), "et_lca_naive")
     return out
 
