@@ -15,9 +15,21 @@
  *    an entry point says so.
  *  - Every call is asynchronous and ordered on the HIP stream it is given.
  *    Outputs are valid once that stream has reached the call's end.
- *  - An et_ctx owns scratch memory, a device status word and the device it
- *    was created on. Calls that share a context must be ordered with
- *    respect to each other (one stream at a time per context).
+ *  - An et_ctx owns scratch memory (a caching pool), a device status word
+ *    and the device it was created on. Calls that share a context must be
+ *    ordered with respect to each other (one stream at a time per context),
+ *    with two exceptions:
+ *      . the query calls et_lca, et_lca_batch and et_lca_rmq take nothing
+ *        from the pool and write nothing of the context but its status bits
+ *        (an atomic OR), so they may run on any stream, concurrently with
+ *        each other and with other calls of the context, as long as the
+ *        tree they read is neither freed nor rebuilt meanwhile;
+ *      . pool blocks are reused in stream order: blocks released on stream A
+ *        (at the end of a call, or by et_tree_free on A) and taken by a call
+ *        on stream B make B wait for an event recorded on A at that moment,
+ *        so work still running on A is not overwritten. (While B is being
+ *        captured into a graph the wait is skipped: capture starts from a
+ *        synchronised device.)
  *  - Ids are 0-based int32. Half-edge ids of a tree with n nodes: 2c is the
  *    half-edge (parent(c) -> c) going down into c, 2c+1 is (c -> parent(c))
  *    going up out of c; the root r's ids 2r and 2r+1 are unused.
@@ -252,8 +264,43 @@ int et_tree_export(const et_tree* tree, int32_t* d_succ, int32_t* d_rank, int32_
                    int32_t* d_pre, int32_t* d_size, uint32_t* d_inlabel, uint32_t* d_asc,
                    hipStream_t s);
 
-/* Release a tree's device tables (stream-ordered on s). */
+/* Release a tree's device tables to its context's pool, ordered on stream
+ * s: work enqueued on s before this call may still read them, and a later
+ * call on another stream that reuses the blocks first waits for s. */
 void et_tree_free(et_tree* tree, hipStream_t s);
+
+/*
+ * Device-memory footprints, for admission control by callers that share a
+ * GPU between jobs (host-only functions: no device call, no GPU needed).
+ * Launch shapes are taken from ctx, or the library defaults when ctx is
+ * NULL.
+ *
+ * et_tree_footprint: for et_tree_build on one tree of n_total nodes
+ * (n_trees = 0) or et_tree_build_batch on n_trees trees of n_total nodes in
+ * all: *h_table_bytes = the bytes of the tables the tree keeps until
+ * et_tree_free (exact), *h_scratch_bytes = an upper bound on the scratch
+ * the build takes from the context's pool (the sum of all its scratch
+ * blocks, so a pool that caches nothing grows by at most table + scratch).
+ * Either output may be NULL. ET_EINVAL for sizes the build rejects.
+ */
+int et_tree_footprint(const et_ctx* ctx, int64_t n_total, int32_t n_trees, int64_t* h_table_bytes,
+                      int64_t* h_scratch_bytes);
+
+/* The same bound for et_bridges on one graph (n_graphs = 0) or
+ * et_bridges_batch on n_graphs graphs with n_total vertices and nnz_total
+ * CSR slots in all. */
+int et_bridges_footprint(const et_ctx* ctx, int32_t n_total, int32_t nnz_total, int32_t n_graphs,
+                         int64_t* h_scratch_bytes);
+
+/* Device bytes a built tree holds now (its pool blocks, RMQ tables included). */
+int et_tree_bytes(const et_tree* tree, int64_t* h_bytes);
+
+/* The context's pool: *h_held = bytes allocated from the device (cached
+ * blocks included), *h_live = bytes handed out now (trees' tables, scratch
+ * of calls in progress), *h_peak_live = the most live bytes since the last
+ * reset; reset_peak != 0 then restarts the peak at the live bytes. Outputs
+ * may be NULL. Host bookkeeping only: no device call. */
+int et_ctx_pool_stats(et_ctx* ctx, int64_t* h_held, int64_t* h_live, int64_t* h_peak_live, int reset_peak);
 
 /*
  * Batched LCA queries on a built tree (Section 3: for each pair (x_i, y_i)

@@ -2,6 +2,7 @@
 // the per-context scratch pool and the device status word.
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <new>
 #include <string>
@@ -24,22 +25,41 @@ namespace {
 constexpr size_t kAlign = 256;
 }
 
-void* pool_get(Ctx* c, size_t bytes) {
+void* pool_get(Ctx* c, size_t bytes, hipStream_t s) {
   bytes = (bytes + kAlign - 1) & ~(kAlign - 1);
   // smallest cached block that fits without wasting more than half of it
   auto it = c->free_blocks.lower_bound(bytes);
   if (it != c->free_blocks.end() && it->first <= 2 * bytes + (1u << 20)) {
-    void* p = it->second;
+    void* p = it->second.p;
+    const hipStream_t from = it->second.s;
+    if (from != s) {
+      hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing(s, &cap) != hipSuccess) {
+        (void)hipGetLastError();
+        cap = hipStreamCaptureStatusNone;
+      }
+      if (cap == hipStreamCaptureStatusNone) {
+        // every use of the block was enqueued on `from` before it came back
+        hipEvent_t e = sync_event(c);
+        if (!e || hipEventRecord(e, from) != hipSuccess || hipStreamWaitEvent(s, e, 0) != hipSuccess) {
+          (void)hipGetLastError();
+          if (hipStreamSynchronize(from) != hipSuccess) return nullptr;
+        }
+        if (e) c->spare_sync.push_back(e);
+      }
+    }
     c->live_blocks[p] = it->first;
+    c->pool_live += it->first;
+    c->pool_peak_live = std::max(c->pool_peak_live, c->pool_live);
     c->free_blocks.erase(it);
     return p;
   }
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
-    // release cached blocks and retry once
+    // release cached blocks and retry once (hipFree waits for the device)
     for (auto& kv : c->free_blocks) {
-      (void)hipFree(kv.second);
+      (void)hipFree(kv.second.p);
       c->pool_bytes -= kv.first;
     }
     c->free_blocks.clear();
@@ -50,7 +70,23 @@ void* pool_get(Ctx* c, size_t bytes) {
   }
   c->pool_bytes += bytes;
   c->live_blocks[p] = bytes;
+  c->pool_live += bytes;
+  c->pool_peak_live = std::max(c->pool_peak_live, c->pool_live);
   return p;
+}
+
+hipEvent_t sync_event(Ctx* c) {
+  if (!c->spare_sync.empty()) {
+    hipEvent_t e = c->spare_sync.back();
+    c->spare_sync.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
 }
 
 hipEvent_t prof_event(Ctx* c) {
@@ -67,11 +103,37 @@ hipEvent_t prof_event(Ctx* c) {
   return e;
 }
 
-void pool_put(Ctx* c, void* p) {
+void pool_put(Ctx* c, void* p, hipStream_t s) {
   auto it = c->live_blocks.find(p);
   if (it == c->live_blocks.end()) return;
-  c->free_blocks.emplace(it->second, p);
+  c->free_blocks.emplace(it->second, Ctx::FreeBlock{p, s});
+  c->pool_live -= it->second;
   c->live_blocks.erase(it);
+}
+
+// The tables of a tree with n node slots (a batch: its nodes + the virtual
+// root), in allocation order: succ, rank, pre, size, node records, head
+// table, the root scalar, and for a batch the offsets and per-tree roots.
+int tree_table_sizes(int32_t n, int32_t batch, size_t sz[9]) {
+  const size_t N = (size_t)n;
+  sz[0] = 2 * N * sizeof(int32_t);
+  sz[1] = 2 * N * sizeof(int32_t);
+  sz[2] = N * sizeof(int32_t);
+  sz[3] = N * sizeof(int32_t);
+  sz[4] = N * sizeof(int4);
+  sz[5] = (N + 2) * sizeof(int2);
+  sz[6] = 64;
+  if (!batch) return 7;
+  sz[7] = ((size_t)batch + 1) * sizeof(int64_t);
+  sz[8] = (size_t)batch * sizeof(int32_t);
+  return 9;
+}
+
+size_t tree_table_bytes(int32_t n, int32_t batch) {
+  size_t sz[9], b = 0;
+  const int k = tree_table_sizes(n, batch, sz);
+  for (int i = 0; i < k; ++i) b += (sz[i] + kAlign - 1) & ~(kAlign - 1);  // pool blocks are multiples of 256 B
+  return b;
 }
 
 }  // namespace et
@@ -124,8 +186,9 @@ void et_ctx_destroy(et_ctx* ctx) {
   if (!ctx) return;
   Ctx* c = &ctx->impl;
   (void)hipDeviceSynchronize();
-  for (auto& kv : c->free_blocks) (void)hipFree(kv.second);
+  for (auto& kv : c->free_blocks) (void)hipFree(kv.second.p);
   for (auto& kv : c->live_blocks) (void)hipFree(kv.first);
+  for (auto e : c->spare_sync) (void)hipEventDestroy(e);
   (void)hipFree(c->d_status);
   for (auto& r : c->prof) {
     (void)hipEventDestroy(r.a);
@@ -241,39 +304,87 @@ int et_list_scan(et_ctx* ctx, const int32_t* d_succ, const int32_t* d_weight, in
   return et::list_scan_generic(&ctx->impl, d_succ, d_weight, len, d_heads, n_heads, d_rank, d_sum, s);
 }
 
-static et_tree* tree_alloc(et_ctx* ctx, int32_t n, int32_t batch) {
+static et_tree* tree_alloc(et_ctx* ctx, int32_t n, int32_t batch, hipStream_t s) {
   Ctx* c = &ctx->impl;
   et_tree* t = new (std::nothrow) et_tree();
   if (!t) return nullptr;
   t->ctx = ctx;
   t->n = n;
   t->batch = batch;
-  const size_t N = (size_t)n;
-  t->d_succ = static_cast<int32_t*>(et::pool_get(c, 2 * N * sizeof(int32_t)));
-  t->d_rank = static_cast<int32_t*>(et::pool_get(c, 2 * N * sizeof(int32_t)));
-  t->d_pre = static_cast<int32_t*>(et::pool_get(c, N * sizeof(int32_t)));
-  t->d_size = static_cast<int32_t*>(et::pool_get(c, N * sizeof(int32_t)));
-  t->d_rec = static_cast<int4*>(et::pool_get(c, N * sizeof(int4)));
-  t->d_head = static_cast<int2*>(et::pool_get(c, (N + 2) * sizeof(int2)));
-  t->d_root = static_cast<int32_t*>(et::pool_get(c, 64));
-  bool ok = t->d_succ && t->d_rank && t->d_pre && t->d_size && t->d_rec && t->d_head && t->d_root;
+  size_t sz[9];
+  const int k = et::tree_table_sizes(n, batch, sz);
+  void* p[9] = {};
+  bool ok = true;
+  for (int i = 0; i < k; ++i) ok = ((p[i] = et::pool_get(c, sz[i], s)) != nullptr) && ok;
+  t->d_succ = static_cast<int32_t*>(p[0]);
+  t->d_rank = static_cast<int32_t*>(p[1]);
+  t->d_pre = static_cast<int32_t*>(p[2]);
+  t->d_size = static_cast<int32_t*>(p[3]);
+  t->d_rec = static_cast<int4*>(p[4]);
+  t->d_head = static_cast<int2*>(p[5]);
+  t->d_root = static_cast<int32_t*>(p[6]);
   if (batch) {
-    t->d_off = static_cast<int64_t*>(et::pool_get(c, ((size_t)batch + 1) * sizeof(int64_t)));
-    t->d_root_of = static_cast<int32_t*>(et::pool_get(c, (size_t)batch * sizeof(int32_t)));
-    ok = ok && t->d_off && t->d_root_of;
+    t->d_off = static_cast<int64_t*>(p[7]);
+    t->d_root_of = static_cast<int32_t*>(p[8]);
   }
   if (!ok) {
-    et_tree_free(t, nullptr);
+    et_tree_free(t, s);
     return nullptr;
   }
   return t;
+}
+
+int et_tree_footprint(const et_ctx* ctx, int64_t n_total, int32_t n_trees, int64_t* h_table_bytes,
+                      int64_t* h_scratch_bytes) {
+  if (n_trees < 0 || n_total < 1 || (n_trees == 0 && n_total >= (1 << 30)) ||
+      (n_trees > 0 && (n_total < n_trees || n_total + 1 >= (1 << 30))))
+    return ET_EINVAL;
+  const int32_t n = (int32_t)(n_trees ? n_total + 1 : n_total);  // a batch adds its virtual root
+  const Ctx* c = ctx ? &ctx->impl : nullptr;
+  if (h_table_bytes) *h_table_bytes = (int64_t)et::tree_table_bytes(n, n_trees);
+  if (h_scratch_bytes) *h_scratch_bytes = (int64_t)et::tree_build_scratch_bytes(c, n, n_trees);
+  return ET_OK;
+}
+
+int et_bridges_footprint(const et_ctx* ctx, int32_t n_total, int32_t nnz_total, int32_t n_graphs,
+                         int64_t* h_scratch_bytes) {
+  if (n_graphs < 0 || n_total < 0 || n_total >= (1 << 30) || nnz_total < 0 || !h_scratch_bytes) return ET_EINVAL;
+  const Ctx* c = ctx ? &ctx->impl : nullptr;
+  *h_scratch_bytes = (int64_t)(n_graphs ? et::bridges_batch_scratch_bytes(c, n_graphs, n_total, nnz_total)
+                                        : et::bridges_scratch_bytes(c, n_total, nnz_total));
+  return ET_OK;
+}
+
+int et_tree_bytes(const et_tree* tree, int64_t* h_bytes) {
+  if (!tree || !h_bytes) return ET_EINVAL;
+  const Ctx* c = &tree->ctx->impl;
+  const void* blocks[] = {tree->d_succ, tree->d_rank, tree->d_pre,   tree->d_size,  tree->d_rec,     tree->d_head,
+                          tree->d_root, tree->d_off,  tree->d_root_of, tree->d_rmq_e, tree->d_rmq_mask, tree->d_rmq_st};
+  int64_t b = 0;
+  for (const void* p : blocks) {
+    if (!p) continue;
+    auto it = c->live_blocks.find(const_cast<void*>(p));
+    if (it != c->live_blocks.end()) b += (int64_t)it->second;
+  }
+  *h_bytes = b;
+  return ET_OK;
+}
+
+int et_ctx_pool_stats(et_ctx* ctx, int64_t* h_held, int64_t* h_live, int64_t* h_peak_live, int reset_peak) {
+  if (!ctx) return ET_EINVAL;
+  Ctx* c = &ctx->impl;
+  if (h_held) *h_held = (int64_t)c->pool_bytes;
+  if (h_live) *h_live = (int64_t)c->pool_live;
+  if (h_peak_live) *h_peak_live = (int64_t)c->pool_peak_live;
+  if (reset_peak) c->pool_peak_live = c->pool_live;
+  return ET_OK;
 }
 
 int et_tree_build(et_ctx* ctx, const int32_t* d_parent, int32_t n, hipStream_t s, et_tree** out) {
   if (!out) return ET_EINVAL;
   *out = nullptr;
   if (!ctx || !d_parent || n < 1 || n >= (1 << 30)) return ET_EINVAL;
-  et_tree* t = tree_alloc(ctx, n, 0);
+  et_tree* t = tree_alloc(ctx, n, 0, s);
   if (!t) return ET_ENOMEM;
   int rc = et::tree_build(&ctx->impl, t, d_parent, s);
   if (rc) {
@@ -290,7 +401,7 @@ int et_tree_build_edges(et_ctx* ctx, const int32_t* d_u, const int32_t* d_v, int
   *out = nullptr;
   if (!ctx || n < 1 || n >= (1 << 30) || root < 0 || root >= n) return ET_EINVAL;
   if (n > 1 && (!d_u || !d_v)) return ET_EINVAL;
-  et_tree* t = tree_alloc(ctx, n, 0);
+  et_tree* t = tree_alloc(ctx, n, 0, s);
   if (!t) return ET_ENOMEM;
   t->from_edges = 1;
   int rc = et::tree_build_edges(&ctx->impl, t, d_u, d_v, root, d_parent_out, s);
@@ -308,7 +419,7 @@ int et_tree_rmq_build(et_tree* tree, const int32_t* d_parent, hipStream_t s) {
   for (void** p : {reinterpret_cast<void**>(&tree->d_rmq_e), reinterpret_cast<void**>(&tree->d_rmq_mask),
                    reinterpret_cast<void**>(&tree->d_rmq_st)})
     if (*p) {
-      et::pool_put(c, *p);
+      et::pool_put(c, *p, s);
       *p = nullptr;
     }
   return et::tree_rmq_build(c, tree, d_parent, s);
@@ -328,7 +439,7 @@ int et_tree_build_batch(et_ctx* ctx, const int32_t* d_parent, const int64_t* d_o
   *out = nullptr;
   if (!ctx || !d_parent || !d_offsets || n_trees < 1 || n_total < n_trees || n_total + 1 >= (1 << 30))
     return ET_EINVAL;
-  et_tree* t = tree_alloc(ctx, (int32_t)(n_total + 1), n_trees);
+  et_tree* t = tree_alloc(ctx, (int32_t)(n_total + 1), n_trees, s);
   if (!t) return ET_ENOMEM;
   if (hipMemcpyAsync(t->d_off, d_offsets, ((size_t)n_trees + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s) !=
       hipSuccess) {
@@ -370,13 +481,12 @@ int et_tree_export(const et_tree* tree, int32_t* d_succ, int32_t* d_rank, int32_
 }
 
 void et_tree_free(et_tree* tree, hipStream_t s) {
-  (void)s;
   if (!tree) return;
   Ctx* c = &tree->ctx->impl;
   void* blocks[] = {tree->d_succ, tree->d_rank, tree->d_pre,   tree->d_size,    tree->d_rec,     tree->d_head,
                     tree->d_root, tree->d_off,  tree->d_root_of, tree->d_rmq_e, tree->d_rmq_mask, tree->d_rmq_st};
   for (void* p : blocks)
-    if (p) et::pool_put(c, p);
+    if (p) et::pool_put(c, p, s);
   delete tree;
 }
 

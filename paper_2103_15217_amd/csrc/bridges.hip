@@ -693,6 +693,23 @@ int spanning_forest(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t 
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }
 
+// Scratch of the Tarjan-Vishkin path of bridges_run: every array below, the
+// ranking's buffers (same scope) and the partials of its three scans.
+size_t bridges_scratch_bytes(const Ctx* c, int32_t n, int32_t nnz) {
+  if (n <= 1 || nnz == 0) return 0;
+  const size_t N = (size_t)n, L = 2 * (size_t)(n - 1), words = ((size_t)nnz + 31) >> 5;
+  const int rlog = c ? c->qs.rmq_log : QueryShape{}.rmq_log;
+  const size_t nb = (N + (1u << rlog) - 1) >> rlog;
+  size_t levels = 1;
+  while (((size_t)1 << levels) <= nb) ++levels;
+  size_t b = scratch_block<int32_t>(N) + scratch_block<uint32_t>(words) + 2 * scratch_block<uint32_t>(N + 1) +
+             7 * scratch_block<int32_t>(L) + 3 * scratch_block<uint32_t>(N) + 2 * scratch_block<int4>(N) +
+             3 * scratch_block<int32_t>(N) + 2 * scratch_block<uint32_t>(N << (rlog - 5)) +
+             2 * scratch_block<int32_t>(levels * nb) + scratch_block<int32_t>(8);
+  b += list_rank_plan_bytes(c, (int32_t)L, 1, 0);
+  return b + scan_scratch_bytes((int64_t)N + 1) + scan_scratch_bytes((int64_t)N) + scan_scratch_bytes((int64_t)L);
+}
+
 int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t nnz, uint32_t* mask,
                 hipStream_t s, int algo) {
   if (algo == kAlgoCK) return bridges_ck_bfs(c, row_ptr, col, n, nnz, mask, s);
@@ -704,7 +721,7 @@ int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, i
   if (n <= 1 || nnz == 0) return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 
   const int32_t Lcap = 2 * (n - 1);  // forest half-edges are at most 2(n-1)
-  Scratch sc(c);
+  Scratch sc(c, s);
   int32_t* cc = sc.get<int32_t>(n);
   uint32_t* tbits = sc.get<uint32_t>(words);
   uint32_t* tdeg = sc.get<uint32_t>((size_t)n + 1);

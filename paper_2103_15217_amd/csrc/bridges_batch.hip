@@ -162,11 +162,18 @@ __global__ void k_gb_halve(int64_t* __restrict__ counts, int32_t T) {
 
 }  // namespace
 
+size_t bridges_batch_scratch_bytes(const Ctx* c, int32_t T, int32_t V, int32_t nnz) {
+  const size_t uwords = ((size_t)nnz + 31) >> 5;
+  const size_t b = scratch_block<int32_t>((size_t)V + 1) + scratch_block<int32_t>((size_t)std::max(nnz, 1)) +
+                   scratch_block<uint32_t>(std::max<size_t>(uwords, 1)) + 2 * scratch_block<uint32_t>((size_t)T + 1);
+  return b + scan_scratch_bytes((int64_t)T + 1) + bridges_scratch_bytes(c, V, nnz);
+}
+
 int bridges_batch_run(Ctx* c, const int32_t* rows, const int32_t* col, const int64_t* voff, const int64_t* soff,
                       int32_t T, int32_t V, int32_t nnz, uint32_t* mask, int64_t mask_words, int64_t* counts,
                       hipStream_t s) {
   const int32_t uwords = (int32_t)(((int64_t)nnz + 31) >> 5);
-  Scratch sc(c);
+  Scratch sc(c, s);
   int32_t* row_g = sc.get<int32_t>((size_t)V + 1);
   int32_t* col_g = sc.get<int32_t>((size_t)std::max(nnz, 1));
   uint32_t* umask = sc.get<uint32_t>((size_t)std::max(uwords, 1));

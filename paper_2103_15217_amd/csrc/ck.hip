@@ -231,7 +231,7 @@ __global__ void k_ck_out(const int32_t* __restrict__ par, const int32_t* __restr
 int ck_mark(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t nnz, const uint32_t* tbits,
             const int32_t* par, const int32_t* lvl, const int32_t* pslot, const int32_t* uslot, uint32_t* mask,
             hipStream_t s) {
-  Scratch sc(c);
+  Scratch sc(c, s);
   uint8_t* mark = sc.get<uint8_t>((size_t)n);
   if (sc.failed) return ET_ENOMEM;
   hipLaunchKernelGGL(k_fill32, dim3(std::min(ceil_div(n, 4 * kB), 4096)), dim3(kB), 0, s,
@@ -251,7 +251,7 @@ int ck_mark(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32
 
 int ck_bfs_forest(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32_t nnz, const int32_t* cc,
                   int32_t* par, int32_t* lvl, int32_t* pslot, int32_t* uslot, uint32_t* tbits, hipStream_t s) {
-  Scratch sc(c);
+  Scratch sc(c, s);
   int32_t* q0 = sc.get<int32_t>((size_t)n);
   int32_t* q1 = sc.get<int32_t>((size_t)n);
   int32_t* cnt = sc.get<int32_t>(4);
@@ -310,7 +310,7 @@ int bridges_ck_bfs(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n
     hipLaunchKernelGGL(k_fill32, dim3(std::min(ceil_div(words, kB), 4096)), dim3(kB), 0, s,
                        reinterpret_cast<int32_t*>(mask), (int64_t)words, 0);
   if (n <= 1 || nnz == 0) return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
-  Scratch sc(c);
+  Scratch sc(c, s);
   int32_t* cc = sc.get<int32_t>((size_t)n);
   uint32_t* tbits = sc.get<uint32_t>((size_t)words);
   int32_t* big = sc.get<int32_t>(4);

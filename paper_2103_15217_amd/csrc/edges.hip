@@ -182,7 +182,7 @@ int tree_build_edges(Ctx* c, et_tree* t, const int32_t* eu, const int32_t* ev, i
   const int32_t L = 2 * m;
   int bits = 1;
   while (bits < 31 && (1ll << bits) < n) ++bits;
-  Scratch scr(c);
+  Scratch scr(c, s);
   int32_t* srcA = scr.get<int32_t>((size_t)L);
   uint32_t* key = scr.get<uint32_t>((size_t)L);
   int32_t* ids = scr.get<int32_t>((size_t)L);

@@ -63,21 +63,32 @@ struct Ctx {
   std::string prof_only;  // time only this kernel when non-empty
   std::vector<ProfRec> prof;
   std::vector<hipEvent_t> spare_events;
+  std::vector<hipEvent_t> spare_sync;  // timing-free events for cross-stream pool reuse
   uint32_t* d_status = nullptr;      // accumulated status bits
   int32_t* d_scalars = nullptr;      // small per-call device scalars (root, head, counters)
   int64_t* d_bcount = nullptr;       // bridge count of the last et_bridges
-  // caching pool: free blocks by size
-  std::multimap<size_t, void*> free_blocks;
+  // caching pool: free blocks by size, each with the stream that released it
+  struct FreeBlock {
+    void* p;
+    hipStream_t s;
+  };
+  std::multimap<size_t, FreeBlock> free_blocks;
   std::map<void*, size_t> live_blocks;
-  size_t pool_bytes = 0;
+  size_t pool_bytes = 0;       // device bytes the pool holds (live + cached)
+  size_t pool_live = 0;        // of which handed out
+  size_t pool_peak_live = 0;   // largest pool_live since the last reset
 };
 
-// scratch allocation from the context pool (stream-ordered reuse: a block
-// handed back is only reused by later work of the same context)
-void* pool_get(Ctx* c, size_t bytes);
-void pool_put(Ctx* c, void* p);
+// Scratch allocation from the context pool. Reuse is stream-ordered: a
+// block released on stream A and taken for work on stream B makes B wait
+// for an event recorded on A at that moment (which follows every use of the
+// block enqueued on A); on the same stream no wait is needed. During stream
+// capture the wait is skipped (capture starts from a synchronised device).
+void* pool_get(Ctx* c, size_t bytes, hipStream_t s);
+void pool_put(Ctx* c, void* p, hipStream_t s);
 
 hipEvent_t prof_event(Ctx* c);
+hipEvent_t sync_event(Ctx* c);
 
 // Brackets the launches issued during its lifetime with events (if enabled).
 struct ProfScope {
@@ -105,22 +116,52 @@ struct ProfScope {
 #define ET_CAT(a, b) ET_CAT2(a, b)
 #define ET_PROF(ctx, stream, name) ::et::ProfScope ET_CAT(et_prof_, __LINE__)(ctx, stream, name)
 
-struct Scratch {  // RAII helper: returns every block on scope exit
+// Scratch of one call. Pool mode (the default): blocks come from the
+// context's pool and go back to it, on the call's stream, at scope exit.
+// Arena mode: blocks are carved in order from a caller-provided region
+// (nothing is allocated; running past its end sets `failed`). Counting mode
+// (arena with a null base): nothing is handed out that may be used, only
+// `used` is summed, to size an arena before any launch.
+struct Scratch {
   Ctx* c;
+  hipStream_t s;
   std::vector<void*> blocks;
   bool failed = false;
-  explicit Scratch(Ctx* ctx) : c(ctx) {}
+  char* arena = nullptr;
+  size_t cap = 0, used = 0;
+  bool arena_mode = false, counting = false;
+  Scratch(Ctx* ctx, hipStream_t st) : c(ctx), s(st) {}
+  Scratch(Ctx* ctx, hipStream_t st, void* base, size_t bytes)
+      : c(ctx), s(st), arena(static_cast<char*>(base)), cap(bytes), arena_mode(true), counting(base == nullptr) {}
   template <typename T>
   T* get(size_t count) {
-    void* p = pool_get(c, count * sizeof(T) + 16);
+    const size_t bytes = count * sizeof(T) + 16;
+    if (arena_mode) {
+      const size_t at = (used + 255) & ~(size_t)255;
+      used = at + bytes;
+      if (counting) return reinterpret_cast<T*>((uintptr_t)(at + 256));  // an address never dereferenced
+      if (used > cap) {
+        failed = true;
+        return nullptr;
+      }
+      return reinterpret_cast<T*>(arena + at);
+    }
+    void* p = pool_get(c, bytes, s);
     if (!p) failed = true;
     else blocks.push_back(p);
     return static_cast<T*>(p);
   }
   ~Scratch() {
-    for (void* p : blocks) pool_put(c, p);
+    for (void* p : blocks) pool_put(c, p, s);
   }
 };
+
+// Bytes one Scratch::get(count) of T takes from the pool (pool blocks are
+// whole multiples of 256 bytes), for the footprint functions below.
+template <typename T>
+constexpr size_t scratch_block(size_t count) {
+  return (count * sizeof(T) + 16 + 255) & ~(size_t)255;
+}
 
 // ---------------------------------------------------------------- device helpers
 __device__ __forceinline__ uint64_t lanemask_lt() {
@@ -252,6 +293,24 @@ int lca_naive_run(Ctx* c, const int32_t* parent, const int32_t* level, int32_t n
                   const int32_t* qy, int64_t q, int32_t* out, hipStream_t s);
 int list_rank_generic(Ctx* c, const int32_t* succ, int32_t len, const int32_t* heads,
                       int32_t nheads, int32_t* rank, hipStream_t s);
+// Footprints: an upper bound on the scratch each call takes from a context's
+// pool, from the same sizes its allocations use: the sum of all of them, so
+// a pool with nothing cached grows by at most this much. (A pool that
+// already caches blocks grows by less, but may hand out a block up to twice
+// the size asked for.)
+size_t scan_scratch_bytes(int64_t n);
+size_t group_by_parent_scratch_bytes(int32_t n);
+size_t list_rank_plan_bytes(const Ctx* c, int32_t len, int32_t nheads, int weighted);
+size_t tree_build_scratch_bytes(const Ctx* c, int32_t n, int32_t batch);
+size_t bridges_scratch_bytes(const Ctx* c, int32_t n, int32_t nnz);
+size_t bridges_batch_scratch_bytes(const Ctx* c, int32_t n_graphs, int32_t n_total, int32_t nnz_total);
+// the device bytes a built tree's own tables take (et_tree_build / _batch)
+size_t tree_table_bytes(int32_t n, int32_t batch);
+// the same ranking with its scratch carved from a caller-provided device
+// region (nothing allocated); list_rank_scratch_bytes gives the bytes it needs
+size_t list_rank_scratch_bytes(Ctx* c, int32_t len, int32_t nheads);
+int list_rank_arena(Ctx* c, void* arena, size_t bytes, const int32_t* succ, int32_t len, const int32_t* heads,
+                    int32_t nheads, int32_t* rank, hipStream_t s);
 int list_scan_generic(Ctx* c, const int32_t* succ, const int32_t* weights, int32_t len, const int32_t* heads,
                       int32_t nheads, int32_t* rank, int32_t* sum, hipStream_t s);
 

@@ -503,131 +503,188 @@ int walk_grid(int32_t total, int32_t per_wave) {
 
 }  // namespace
 
-int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const int32_t* heads,
-                   int32_t nheads, bool tree_weights, const int32_t* expected_reach, LRResult* out,
-                   hipStream_t s, bool empty_head_ok, int weighted) {
-  const int32_t L = len, H = nheads;
+// Every buffer of a ranking is taken from the scratch before the first
+// launch (the level sizes follow from the list length, the number of heads
+// and the launch shape alone), so a fixed-size arena can be checked, or a
+// pool request fail, before anything is enqueued.
+struct LrLevel {
+  int4* rec;        // this level's records (level 1: the sublist records)
+  int32_t T, hb;    // records and the index of the first head record
+  int4* el;         // per record: {sublist, exclusive local len, down} of the level above
+  int2* off;        // per record: exclusive prefix {len, down} from its head
+  int ks;           // splitter spacing of the level above (2^ks)
+  int32_t S_up;     // chunk splitters of the level above
+  int32_t per_wave; // sublists per wavefront of the level above's walk
+};
+
+struct LrPlan {
+  int ks1 = 0;
+  int32_t S1 = 0, cont_max = 0, T1 = 0, per_wave1 = 0;
+  uint64_t* packed = nullptr;
+  int4* rec1 = nullptr;
+  int32_t* ctr = nullptr;
+  std::vector<LrLevel> lv;
+};
+
+static void list_rank_plan(Ctx* c, Scratch& sc, int32_t L, int32_t H, int weighted, LrPlan* pl) {
   // Level-1 splitter spacing K = 2^ks1 (a sublist averages K elements).
   // Shorter lists keep more, shorter sublists: below about 2^25 elements the
   // walk is bound by its dependent steps rather than by line fetches, so the
   // spacing drops by half per factor 4 of length (2^24 -> 16, 2^22 -> 8,
   // 2^20 -> 4), down to 4; the context's value is the largest spacing used.
-  const int ks1 = std::min(c->lr.k1_log2, std::max(2, (floor_log2(L) - 15) / 2));
-  const int32_t S1 = (int32_t)(((int64_t)L + (1 << ks1) - 1) >> ks1);
-  const int32_t cont_max = L / kCap + H + 64;
-  const int32_t T1 = S1 + H + cont_max;
-  uint64_t* packed = sc.get<uint64_t>((size_t)L * (weighted == 2 ? 2 : 1));
-  int4* rec1 = sc.get<int4>((size_t)T1);
-  int32_t* ctr = sc.get<int32_t>(4);
-  if (sc.failed) return ET_ENOMEM;
-  hipLaunchKernelGGL(k_lr_init, dim3(ceil_div(cont_max, 256)), dim3(256), 0, s, ctr, rec1, S1 + H, T1);
+  pl->ks1 = std::min(c->lr.k1_log2, std::max(2, (floor_log2(L) - 15) / 2));
+  pl->S1 = (int32_t)(((int64_t)L + (1 << pl->ks1) - 1) >> pl->ks1);
+  pl->cont_max = L / kCap + H + 64;
+  pl->T1 = pl->S1 + H + pl->cont_max;
+  pl->packed = sc.get<uint64_t>((size_t)L * (weighted == 2 ? 2 : 1));
+  pl->rec1 = sc.get<int4>((size_t)pl->T1);
+  pl->ctr = sc.get<int32_t>(4);
   // sublists per wavefront: the context's value, fewer when that would leave
   // under 4096 wavefronts (at least 64, one per lane)
-  const int32_t per_wave1 = std::min(c->lr.per_wave1, std::max(64, (S1 + H) >> 12));
-  if (tree_weights) {
-    ET_PROF(c, s, "k_walk1<true>");
-    hipLaunchKernelGGL(k_walk1<true>, dim3(walk_grid(S1 + H, per_wave1)), dim3(kWalkThreads), 0, s, succ, L,
-                       heads, H, ks1, kSalt, S1, per_wave1, packed, rec1, ctr, S1 + H, cont_max,
-                       empty_head_ok, c->d_status);
-  } else if (weighted) {
-    ET_PROF(c, s, weighted == 2 ? "k_walk1w<true>" : "k_walk1w<false>");
-    const auto kern = weighted == 2 ? k_walk1w<true> : k_walk1w<false>;
-    hipLaunchKernelGGL(kern, dim3(walk_grid(S1 + H, per_wave1)), dim3(kWalkThreads), 0, s, succ, L, heads, H,
-                       ks1, kSalt, S1, per_wave1, packed, rec1, ctr, S1 + H, cont_max, empty_head_ok, c->d_status);
-  } else {
-    ET_PROF(c, s, "k_walk1<false>");
-    hipLaunchKernelGGL(k_walk1<false>, dim3(walk_grid(S1 + H, per_wave1)), dim3(kWalkThreads), 0, s, succ,
-                       L, heads, H, ks1, kSalt, S1, per_wave1, packed, rec1, ctr, S1 + H, cont_max,
-                       empty_head_ok, c->d_status);
-  }
-
-  // upper levels: (records, element outputs) per level
-  struct Lvl {
-    const int4* rec;
-    int32_t T, hb;
-    int4* el;
-    int2* off;
-  };
-  std::vector<Lvl> lv;
-  lv.push_back({rec1, T1, S1, nullptr, nullptr});
+  pl->per_wave1 = std::min(c->lr.per_wave1, std::max(64, (pl->S1 + H) >> 12));
+  pl->lv.clear();
+  pl->lv.push_back({pl->rec1, pl->T1, pl->S1, nullptr, nullptr, 0, 0, 0});
   for (;;) {
-    Lvl& cur = lv.back();
+    LrLevel& cur = pl->lv.back();
     if (cur.T <= kLdsMax) break;
     const int ks = c->lr.kn_log2;
     const int32_t S = (int32_t)(((int64_t)cur.T + (1 << ks) - 1) >> ks);
     const int32_t Tn = S + H;
     if ((int64_t)Tn * 2 > cur.T) break;  // many heads: shrinking stalls
-    int4* el = sc.get<int4>((size_t)cur.T);
+    cur.el = sc.get<int4>((size_t)cur.T);
     int4* rec = sc.get<int4>((size_t)Tn);
-    if (sc.failed) return ET_ENOMEM;
-    const int32_t per_wave = std::min(c->lr.per_waven, std::max(64, Tn >> 12));
-    {
-      ET_PROF(c, s, "k_walkN");
-      hipLaunchKernelGGL(k_walkN, dim3(walk_grid(Tn, per_wave)), dim3(kWalkThreads), 0, s, cur.rec, cur.T,
-                         cur.hb, H, ks, kSalt ^ (uint32_t)lv.size(), S, per_wave, el, rec, c->d_status);
-    }
-    cur.el = el;
-    lv.push_back({rec, Tn, S, nullptr, nullptr});
+    cur.ks = ks;
+    cur.S_up = S;
+    cur.per_wave = std::min(c->lr.per_waven, std::max(64, Tn >> 12));
+    pl->lv.push_back({rec, Tn, S, nullptr, nullptr, 0, 0, 0});
   }
-  for (auto& l : lv) {
-    l.off = sc.get<int2>((size_t)l.T);
+  for (auto& l : pl->lv) l.off = sc.get<int2>((size_t)l.T);
+}
+
+static int list_rank_launch(Ctx* c, const LrPlan& pl, const int32_t* succ, int32_t L, const int32_t* heads,
+                            int32_t H, bool tree_weights, const int32_t* expected_reach, hipStream_t s,
+                            bool empty_head_ok, int weighted) {
+  const int32_t S1 = pl.S1, T1 = pl.T1, cont_max = pl.cont_max;
+  hipLaunchKernelGGL(k_lr_init, dim3(ceil_div(cont_max, 256)), dim3(256), 0, s, pl.ctr, pl.rec1, S1 + H, T1);
+  const dim3 g1(walk_grid(S1 + H, pl.per_wave1));
+  if (tree_weights) {
+    ET_PROF(c, s, "k_walk1<true>");
+    hipLaunchKernelGGL(k_walk1<true>, g1, dim3(kWalkThreads), 0, s, succ, L, heads, H, pl.ks1, kSalt, S1,
+                       pl.per_wave1, pl.packed, pl.rec1, pl.ctr, S1 + H, cont_max, empty_head_ok, c->d_status);
+  } else if (weighted) {
+    ET_PROF(c, s, weighted == 2 ? "k_walk1w<true>" : "k_walk1w<false>");
+    const auto kern = weighted == 2 ? k_walk1w<true> : k_walk1w<false>;
+    hipLaunchKernelGGL(kern, g1, dim3(kWalkThreads), 0, s, succ, L, heads, H, pl.ks1, kSalt, S1, pl.per_wave1,
+                       pl.packed, pl.rec1, pl.ctr, S1 + H, cont_max, empty_head_ok, c->d_status);
+  } else {
+    ET_PROF(c, s, "k_walk1<false>");
+    hipLaunchKernelGGL(k_walk1<false>, g1, dim3(kWalkThreads), 0, s, succ, L, heads, H, pl.ks1, kSalt, S1,
+                       pl.per_wave1, pl.packed, pl.rec1, pl.ctr, S1 + H, cont_max, empty_head_ok, c->d_status);
   }
-  if (sc.failed) return ET_ENOMEM;
-  Lvl& top = lv.back();
+  // upper levels: level k's records are walked into level k+1's
+  const auto& lv = pl.lv;
+  for (size_t k = 0; k + 1 < lv.size(); ++k) {
+    const LrLevel& cur = lv[k];
+    const int32_t Tn = lv[k + 1].T;
+    ET_PROF(c, s, "k_walkN");
+    hipLaunchKernelGGL(k_walkN, dim3(walk_grid(Tn, cur.per_wave)), dim3(kWalkThreads), 0, s, cur.rec, cur.T,
+                       cur.hb, H, cur.ks, kSalt ^ (uint32_t)(k + 1), cur.S_up, cur.per_wave, cur.el, lv[k + 1].rec,
+                       c->d_status);
+  }
+  const LrLevel& top = lv.back();
   if (top.T <= kLdsMax) {
-    {
-      ET_PROF(c, s, "k_final_lds");
-      hipLaunchKernelGGL(k_final_lds, dim3(1), dim3(kFinalThreads), 0, s, top.rec, top.T, top.hb, H, top.off,
-                         ctr + 1, expected_reach, c->d_status);
-    }
+    ET_PROF(c, s, "k_final_lds");
+    hipLaunchKernelGGL(k_final_lds, dim3(1), dim3(kFinalThreads), 0, s, top.rec, top.T, top.hb, H, top.off,
+                       pl.ctr + 1, expected_reach, c->d_status);
   } else {
     {
       ET_PROF(c, s, "k_final_walk");
       hipLaunchKernelGGL(k_final_walk, dim3(ceil_div(H, 256)), dim3(256), 0, s, top.rec, top.T, top.hb, H,
-                         top.off, ctr + 1, c->d_status);
+                         top.off, pl.ctr + 1, c->d_status);
     }
-    hipLaunchKernelGGL(k_check_reached, dim3(1), dim3(1), 0, s, ctr + 1, expected_reach, c->d_status);
+    hipLaunchKernelGGL(k_check_reached, dim3(1), dim3(1), 0, s, pl.ctr + 1, expected_reach, c->d_status);
   }
   for (int k = (int)lv.size() - 2; k >= 0; --k) {
-    {
-      ET_PROF(c, s, "k_push_down");
-      hipLaunchKernelGGL(k_push_down, dim3(ceil_div(lv[k].T, 256)), dim3(256), 0, s, lv[k].rec, lv[k].el,
-                         lv[k].T, lv[k + 1].off, lv[k + 1].T, lv[k].off, c->d_status);
-    }
+    ET_PROF(c, s, "k_push_down");
+    hipLaunchKernelGGL(k_push_down, dim3(ceil_div(lv[k].T, 256)), dim3(256), 0, s, lv[k].rec, lv[k].el, lv[k].T,
+                       lv[k + 1].off, lv[k + 1].T, lv[k].off, c->d_status);
   }
-  out->packed = packed;
-  out->off = lv[0].off;
-  out->nsub = T1;
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }
 
-int list_rank_generic(Ctx* c, const int32_t* succ, int32_t len, const int32_t* heads, int32_t nheads,
-                      int32_t* rank, hipStream_t s) {
-  if (len == 0) return ET_OK;
-  Scratch sc(c);
-  int32_t* expected = sc.get<int32_t>(1);
+int list_rank_core(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const int32_t* heads,
+                   int32_t nheads, bool tree_weights, const int32_t* expected_reach, LRResult* out,
+                   hipStream_t s, bool empty_head_ok, int weighted) {
+  LrPlan pl;
+  list_rank_plan(c, sc, len, nheads, weighted, &pl);
   if (sc.failed) return ET_ENOMEM;
+  const int rc = list_rank_launch(c, pl, succ, len, heads, nheads, tree_weights, expected_reach, s, empty_head_ok,
+                                  weighted);
+  out->packed = pl.packed;
+  out->off = pl.lv[0].off;
+  out->nsub = pl.T1;
+  return rc;
+}
+
+// Plain ranking with the scratch taken from `sc` (the pool, or an arena):
+// every buffer is reserved before the first launch.
+static int list_rank_with(Ctx* c, Scratch& sc, const int32_t* succ, int32_t len, const int32_t* heads,
+                          int32_t nheads, int32_t* rank, hipStream_t s) {
+  int32_t* expected = sc.get<int32_t>(1);
+  LrPlan pl;
+  list_rank_plan(c, sc, len, nheads, 0, &pl);
+  if (sc.failed || sc.counting) return sc.failed ? ET_ENOMEM : ET_OK;
   hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, expected, 0);
   {
     ET_PROF(c, s, "k_count_used");
     hipLaunchKernelGGL(k_count_used, dim3(std::min(ceil_div(len, 256), 2048)), dim3(256), 0, s, succ, len,
                        expected);
   }
-  LRResult r;
-  int rc = list_rank_core(c, sc, succ, len, heads, nheads, false, expected, &r, s);
+  int rc = list_rank_launch(c, pl, succ, len, heads, nheads, false, expected, s, false, 0);
   if (rc) return rc;
   {
     ET_PROF(c, s, "k_rank_fix");
-    hipLaunchKernelGGL(k_rank_fix, dim3(ceil_div(len, 256)), dim3(256), 0, s, succ, r.packed, len, r.off,
-                       r.nsub, rank, c->d_status);
+    hipLaunchKernelGGL(k_rank_fix, dim3(ceil_div(len, 256)), dim3(256), 0, s, succ, pl.packed, len, pl.lv[0].off,
+                       pl.T1, rank, c->d_status);
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+}
+
+int list_rank_generic(Ctx* c, const int32_t* succ, int32_t len, const int32_t* heads, int32_t nheads,
+                      int32_t* rank, hipStream_t s) {
+  if (len == 0) return ET_OK;
+  Scratch sc(c, s);
+  return list_rank_with(c, sc, succ, len, heads, nheads, rank, s);
+}
+
+size_t list_rank_plan_bytes(const Ctx* c, int32_t len, int32_t nheads, int weighted) {
+  if (len == 0) return 0;
+  Ctx shape;  // the plan reads only the launch shape
+  shape.lr = c ? c->lr : LrShape{};
+  Scratch count(&shape, nullptr, nullptr, 0);
+  LrPlan pl;
+  list_rank_plan(&shape, count, len, nheads, weighted, &pl);
+  return count.used;
+}
+
+size_t list_rank_scratch_bytes(Ctx* c, int32_t len, int32_t nheads) {
+  if (len == 0) return 0;
+  Scratch count(c, nullptr, nullptr, 0);
+  (void)list_rank_with(c, count, nullptr, len, nullptr, nheads, nullptr, nullptr);
+  return count.used;
+}
+
+int list_rank_arena(Ctx* c, void* arena, size_t bytes, const int32_t* succ, int32_t len, const int32_t* heads,
+                    int32_t nheads, int32_t* rank, hipStream_t s) {
+  if (len == 0) return ET_OK;
+  Scratch sc(c, s, arena, bytes);
+  return list_rank_with(c, sc, succ, len, heads, nheads, rank, s);
 }
 
 int list_scan_generic(Ctx* c, const int32_t* succ, const int32_t* weights, int32_t len, const int32_t* heads,
                       int32_t nheads, int32_t* rank, int32_t* sum, hipStream_t s) {
   if (len == 0) return ET_OK;
-  Scratch sc(c);
+  Scratch sc(c, s);
   int32_t* expected = sc.get<int32_t>(1);
   int2* sw = sc.get<int2>((size_t)len);
   if (sc.failed) return ET_ENOMEM;

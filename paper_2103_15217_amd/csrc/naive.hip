@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kB) void k_lca_naive(const int32_t* __restrict__ pa
 
 int levels_run(Ctx* c, const int32_t* parent, int32_t n, int32_t* level, hipStream_t s) {
   if (n == 0) return ET_OK;
-  Scratch sc(c);
+  Scratch sc(c, s);
   uint64_t* jump = sc.get<uint64_t>((size_t)n);
   int32_t* roots = sc.get<int32_t>(1);
   if (sc.failed) return ET_ENOMEM;

@@ -228,6 +228,14 @@ int plan_passes(int bits, int64_t n, int* width) {
 
 }  // namespace
 
+// histograms of every tile and the ping-pong keys and values, plus the
+// largest histogram scan's partials
+size_t group_by_parent_scratch_bytes(int32_t n) {
+  const int32_t ntiles = ceil_div(n, kTile);
+  return scratch_block<uint32_t>((size_t)kMaxDigits * ntiles) + scratch_block<uint32_t>((size_t)n) +
+         scratch_block<int32_t>((size_t)n) + scan_scratch_bytes((int64_t)kMaxDigits * ntiles);
+}
+
 // keys_out / vals_out receive the stable order; scalars[0] = root, scalars[1]
 // = number of roots; succ[2c] of every non-root c is set to 2c+1 and
 // succ[2c+1] to -2 (the successor step writes it), both root ids to -2.
@@ -238,7 +246,7 @@ int group_by_parent_impl(Ctx* c, const int32_t* parent, int32_t n, uint32_t* key
   int width[8];
   const int passes = plan_passes(bits, n, width);
   const int32_t ntiles = ceil_div(n, kTile);
-  Scratch sc(c);
+  Scratch sc(c, s);
   uint32_t* hist = sc.get<uint32_t>((size_t)kMaxDigits * ntiles);
   uint32_t* tk = sc.get<uint32_t>((size_t)n);
   int32_t* tv = sc.get<int32_t>((size_t)n);
@@ -291,7 +299,7 @@ int sort_pairs_u32(Ctx* c, const uint32_t* keys, const int32_t* vals, int32_t n,
   int width[8];
   const int passes = plan_passes(bits, n, width);
   const int32_t ntiles = ceil_div(n, kTile);
-  Scratch sc(c);
+  Scratch sc(c, s);
   uint32_t* hist = sc.get<uint32_t>((size_t)kMaxDigits * ntiles);
   uint32_t* tk = sc.get<uint32_t>((size_t)n);
   int32_t* tv = sc.get<int32_t>((size_t)n);

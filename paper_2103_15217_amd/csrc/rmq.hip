@@ -147,9 +147,9 @@ int tree_rmq_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
   const int32_t nb = (int32_t)(((int64_t)L + (1 << lg) - 1) >> lg);
   int levels = 1;
   while ((1 << levels) <= nb) ++levels;
-  t->d_rmq_e = static_cast<uint64_t*>(pool_get(c, (size_t)L * sizeof(uint64_t)));
-  t->d_rmq_mask = pool_get(c, ((size_t)L << (lg - 5)) * sizeof(uint32_t));
-  t->d_rmq_st = static_cast<uint64_t*>(pool_get(c, (size_t)levels * nb * sizeof(uint64_t)));
+  t->d_rmq_e = static_cast<uint64_t*>(pool_get(c, (size_t)L * sizeof(uint64_t), s));
+  t->d_rmq_mask = pool_get(c, ((size_t)L << (lg - 5)) * sizeof(uint32_t), s);
+  t->d_rmq_st = static_cast<uint64_t*>(pool_get(c, (size_t)levels * nb * sizeof(uint64_t), s));
   if (!t->d_rmq_e || !t->d_rmq_mask || !t->d_rmq_st) return ET_ENOMEM;
   t->rmq_nb = nb;
   t->rmq_log = lg;

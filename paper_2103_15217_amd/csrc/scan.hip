@@ -192,7 +192,7 @@ int scan_impl(Ctx* c, const uint32_t* in, uint32_t* out, int64_t n, bool exclusi
   }
   int64_t per = (chunks + kMaxRanges - 1) / kMaxRanges;
   int nranges = (int)((chunks + per - 1) / per);
-  Scratch sc(c);
+  Scratch sc(c, s);
   uint32_t* partial = sc.get<uint32_t>(nranges);
   if (sc.failed) return ET_ENOMEM;
   {
@@ -218,6 +218,13 @@ int scan_impl(Ctx* c, const uint32_t* in, uint32_t* out, int64_t n, bool exclusi
 }
 
 }  // namespace
+
+size_t scan_scratch_bytes(int64_t n) {
+  const int64_t chunks = (n + kChunk - 1) / kChunk;
+  if (chunks <= kSmallChunks) return 0;
+  const int64_t per = (chunks + kMaxRanges - 1) / kMaxRanges;
+  return scratch_block<uint32_t>((size_t)((chunks + per - 1) / per));
+}
 
 int scan_u32(Ctx* c, const uint32_t* in, uint32_t* out, int64_t n, ScanOp op, bool exclusive,
              hipStream_t s) {

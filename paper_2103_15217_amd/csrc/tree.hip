@@ -396,6 +396,21 @@ __global__ void k_export_batch(const int4* __restrict__ rec, const int32_t* __re
 
 }  // namespace
 
+// Scratch of tree_build: the grouping buffer and the compact inlabels, the
+// grouping's own scratch (released before the ranking starts, but counted
+// as if held: the pool may hand a released block to a smaller request) and
+// the ranking's buffers; a batch adds its combined parent array and root
+// counts.
+size_t tree_build_scratch_bytes(const Ctx* c, int32_t n, int32_t batch) {
+  size_t b = 0;
+  if (batch) {
+    b += scratch_block<int32_t>((size_t)n) + scratch_block<int32_t>((size_t)batch);  // n counts the virtual root
+  }
+  if (n <= 1) return b;
+  b += scratch_block<uint32_t>(2 * (size_t)n) + scratch_block<uint32_t>((size_t)n);
+  return b + group_by_parent_scratch_bytes(n) + list_rank_plan_bytes(c, 2 * n, 1, 0);
+}
+
 int tree_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
   const int32_t n = t->n;
   int32_t* sc = t->d_root;
@@ -405,7 +420,7 @@ int tree_build(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
     return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
   }
   const int32_t L2 = 2 * n;          // half-edge id space (the tour uses 2(n-1) of them)
-  Scratch scr(c);
+  Scratch scr(c, s);
   uint32_t* kv = scr.get<uint32_t>((size_t)L2);  // sorted parents | children, later the path-label table
   if (scr.failed) return ET_ENOMEM;
   uint32_t* keys = kv;
@@ -530,7 +545,7 @@ int tree_lca_batch(Ctx* c, const et_tree* t, const int32_t* qt, const int32_t* q
 
 int tree_build_batch(Ctx* c, et_tree* t, const int32_t* parent, hipStream_t s) {
   const int32_t N = t->n - 1, T = t->batch;
-  Scratch scr(c);
+  Scratch scr(c, s);
   int32_t* gp = scr.get<int32_t>((size_t)N + 1);
   int32_t* nroots = scr.get<int32_t>((size_t)T);
   if (scr.failed) return ET_ENOMEM;

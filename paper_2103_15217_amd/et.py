@@ -53,6 +53,11 @@ _SIG = {
     "et_tree_rmq_build": ([_P, _P, _P], ctypes.c_int),
     "et_lca_rmq": ([_P, _P, _P, _i64, _P, _P], ctypes.c_int),
     "et_lca_naive": ([_P, _P, _P, _i32, _P, _P, _i64, _P, _P], ctypes.c_int),
+    "et_tree_footprint": ([_P, _i64, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)], ctypes.c_int),
+    "et_bridges_footprint": ([_P, _i32, _i32, _i32, ctypes.POINTER(_i64)], ctypes.c_int),
+    "et_tree_bytes": ([_P, ctypes.POINTER(_i64)], ctypes.c_int),
+    "et_ctx_pool_stats": ([_P, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.c_int],
+                          ctypes.c_int),
 }
 for _name, (_args, _res) in _SIG.items():
     _fn = getattr(_lib, _name)
@@ -165,6 +170,16 @@ class Context:
             _check(rc, "et_ctx_profile_read")
             return {k: tuple(v) for k, v in json.loads(buf.value.decode()).items()}
 
+    def pool_stats(self, reset_peak=False):
+        """Device bytes of this context's scratch pool: ``held`` (allocated
+        from the device, cached blocks included), ``live`` (handed out now:
+        resident trees' tables and running calls' scratch) and ``peak_live``
+        (the most live since the last reset)."""
+        held, live, peak = _i64(0), _i64(0), _i64(0)
+        _check(_lib.et_ctx_pool_stats(self._h, ctypes.byref(held), ctypes.byref(live), ctypes.byref(peak),
+                                      1 if reset_peak else 0), "et_ctx_pool_stats")
+        return {"held": held.value, "live": live.value, "peak_live": peak.value}
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.et_ctx_destroy(self._h)
@@ -185,6 +200,31 @@ def default_context():
     if _default is None:
         _default = Context()
     return _default
+
+
+# ------------------------------------------------------------------ footprints (host only)
+
+def tree_footprint(n_total, n_trees=0, ctx=None):
+    """(table bytes, scratch bytes) of et_tree_build on one tree of ``n_total``
+    nodes (``n_trees`` = 0) or of et_tree_build_batch on ``n_trees`` trees with
+    ``n_total`` nodes in all: the tables the tree keeps (exact) and an upper
+    bound on the scratch the build takes. Launch shapes from ``ctx`` (library
+    defaults when None). No device call: this works without a GPU."""
+    tb, sb = _i64(0), _i64(0)
+    _check(_lib.et_tree_footprint(ctx.handle if ctx else None, int(n_total), _i32(n_trees, "number of trees"),
+                                  ctypes.byref(tb), ctypes.byref(sb)), "et_tree_footprint")
+    return tb.value, sb.value
+
+
+def bridges_footprint(n_total, nnz_total, n_graphs=0, ctx=None):
+    """Upper bound on the scratch bytes of et_bridges on one graph
+    (``n_graphs`` = 0) or of et_bridges_batch on ``n_graphs`` graphs, from
+    their vertex and CSR-slot totals. No device call."""
+    sb = _i64(0)
+    _check(_lib.et_bridges_footprint(ctx.handle if ctx else None, _i32(n_total, "vertex count", NODE_MAX),
+                                     _i32(nnz_total, "CSR slot count"), _i32(n_graphs, "number of graphs"),
+                                     ctypes.byref(sb)), "et_bridges_footprint")
+    return sb.value
 
 
 # ------------------------------------------------------------------ list ranking
@@ -295,7 +335,15 @@ class Tree:
         _check(_lib.et_lca_rmq(self._h, _ptr(qx), _ptr(qy), qx.numel(), _ptr(out), _stream()), "et_lca_rmq")
         return out
 
+    def nbytes(self):
+        """Device bytes of this tree's tables (exact: the pool blocks it holds)."""
+        b = _i64(0)
+        _check(_lib.et_tree_bytes(self._h, ctypes.byref(b)), "et_tree_bytes")
+        return b.value
+
     def free(self):
+        """Return the tables to the context's pool, ordered on the current
+        stream: later work on another stream that reuses them waits for it."""
         if self._h:
             _lib.et_tree_free(self._h, _stream())
             self._h = None
