@@ -1,35 +1,181 @@
-"""Serving loop: every job's result is the same alone (plain executor) and in
-the mix (continuous batching with resident trees, batched builds and
-overlapping streams), and LCA results match the oracle."""
+"""Serving on the GPU.
+
+* Every job's result is the same alone (plain executor) and in the mix
+  (continuous batching under a memory budget small enough to evict, rebuild
+  and defer), and LCA and bridge results match the oracle.
+* The library's footprint figures bound what the calls really take: on a
+  fresh context the pool grows by at most the estimate (trees, batches,
+  bridges, bridge batches), and a tree holds exactly its table bytes.
+* LCA queries take nothing from the pool (they may run on any stream).
+* et_tree_free is stream-ordered: blocks freed on one stream and reused by
+  a build on another are not overwritten before the first stream's queries
+  have read them.
+"""
 import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
 
 
+def _d(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
+
+
 def test_served_results_equal_alone(oracle_mod):
     import torch
     from paper_2103_15217_amd import serve
     dev = torch.device("cuda", 0)
-    pool = serve.make_pool(seed=3, trees=12, graphs=4, tree_log2=(4, 15), graph_log2=(8, 13))
-    dpool = serve.upload_pool(pool, dev)
-    jobs = serve.make_trace(pool, rate=20000, duration=0.03, seed=3, qlog2=(0, 9))
+    bases = serve.make_bases(seed=3, count=10, tree_log2=(4, 15))
+    graphs = serve.make_graphs(seed=3, count=4, graph_log2=(8, 13))
+    jobs, specs = serve.make_trace(bases, graphs, rate=20000, duration=0.03, seed=3, qlog2=(0, 9))
     assert len(jobs) > 200
-    serve.upload_trace(jobs, dev)
-    plain = serve.PlainExecutor(dpool, keep_results=True)
+    dinp = serve.DeviceInputs(bases, graphs, dev)
+    dinp.prepare(jobs, specs)
+    plain = serve.PlainExecutor(dinp, keep_results=True)
     plain.run(jobs)
-    # a small memory budget forces evictions and re-builds in the mix
-    served = serve.ServedExecutor(dpool, streams=3, budget_bytes=1 << 24, keep_results=True, max_batch=5)
+    # a budget of a few trees forces evictions, rebuilds and deferrals in the mix
+    budget = 3 * sum(serve.et.tree_footprint(1 << 15)) + (4 << 20)
+    served = serve.ServedExecutor(dinp, streams=3, budget_bytes=budget, keep_results=True, max_batch=5)
     stats = served.run(jobs)
     served.close()
-    assert stats["jobs"] == len(jobs)
+    assert stats["completed"] == len(jobs)
+    assert stats["evictions"] > 0 and stats["over_budget"] == 0
+    assert stats["cold_fraction"] >= serve.cold_fraction(jobs) - 1e-9
     for j in jobs:
         a, b = plain.results[j.jid].numpy(), served.results[j.jid].numpy()
         assert np.array_equal(a, b), (j.jid, j.kind)
-    for j in [j for j in jobs if j.kind == "lca"][:20]:
-        want = oracle_mod.lca_offline(pool["trees"][j.item], j.qx.cpu().numpy(), j.qy.cpu().numpy())
+    for j in [j for j in jobs if j.kind == "lca"][:25]:
+        s = specs[j.key]
+        parent = serve.relabel(bases[s.base], s.a, s.c)
+        assert np.array_equal(dinp.trees[j.key].cpu().numpy(), parent)
+        want = oracle_mod.lca_offline(parent, j.qx.cpu().numpy(), j.qy.cpu().numpy())
         assert np.array_equal(served.results[j.jid].numpy(), want)
     for j in [j for j in jobs if j.kind == "bridges"][:5]:
-        rp, col = pool["graphs"][j.item]
+        rp, col = graphs[j.key]
         ref, _ = oracle_mod.bridges(rp, col)
         assert np.array_equal(served.results[j.jid].numpy().view(np.uint32)[: len(ref)], ref)
+
+
+@pytest.mark.parametrize("n", [1, 2, 1000, 1 << 16, (1 << 20) + 7, 1 << 22])
+def test_tree_footprint_bounds_the_pool(n, bench_ctx):
+    import torch
+    import gen
+    import paper_2103_15217_amd as et
+    ctx = bench_ctx("single")
+    parent = _d(gen.random_tree(n, None, seed=n))
+    table, scratch = et.tree_footprint(n, 0, ctx=ctx)
+    t = et.et_tree_build(parent, ctx=ctx)
+    torch.cuda.synchronize()
+    st = ctx.pool_stats()
+    assert t.nbytes() == table
+    assert table <= st["held"] <= table + scratch, (st, table, scratch)
+    assert st["peak_live"] <= st["held"]
+    t.free()
+    ctx.check()
+
+
+@pytest.mark.parametrize("trees,lo,hi", [(3, 4, 8), (64, 6, 14), (300, 8, 16)])
+def test_batch_footprint_bounds_the_pool(trees, lo, hi, bench_ctx):
+    import torch
+    import gen
+    import paper_2103_15217_amd as et
+    ctx = bench_ctx("batch")
+    b = gen.forest_batch(trees, seed=trees, log2_min=lo, log2_max=hi)
+    parent = _d(b["parent"])
+    offs = torch.from_numpy(b["offsets"].astype(np.int64)).cuda()
+    table, scratch = et.tree_footprint(parent.numel(), trees, ctx=ctx)
+    t = et.et_tree_build_batch(parent, offs, ctx=ctx)
+    torch.cuda.synchronize()
+    st = ctx.pool_stats()
+    assert t.nbytes() == table
+    assert table <= st["held"] <= table + scratch, (st, table, scratch)
+    t.free()
+    ctx.check()
+
+
+@pytest.mark.parametrize("n,m", [(1000, 4000), (1 << 16, 1 << 19), (1 << 20, 1 << 23)])
+def test_bridges_footprint_bounds_the_pool(n, m, bench_ctx):
+    import torch
+    import gen
+    import paper_2103_15217_amd as et
+    ctx = bench_ctx("single")
+    rp, col, _ = gen.planted_bridge_graph(n=n, m=m, chains=max(1, n >> 10), max_chain=16, seed=n)
+    est = et.bridges_footprint(n, len(col), 0, ctx=ctx)
+    et.et_bridges(_d(rp), _d(col), ctx=ctx, count=False)
+    torch.cuda.synchronize()
+    st = ctx.pool_stats()
+    assert 0 < st["held"] <= est, (st, est)
+    ctx.check()
+    # a batch of graphs on a fresh context
+    ctx2 = bench_ctx("batch")
+    gl = [gen.planted_bridge_graph(n=k, m=4 * k, chains=max(1, k >> 9), max_chain=8, seed=k)[:2]
+          for k in (300, 5000, 70000)]
+    est = et.bridges_footprint(sum(len(g[0]) - 1 for g in gl), sum(len(g[1]) for g in gl), len(gl), ctx=ctx2)
+    et.et_bridges_batch([(_d(r), _d(c)) for r, c in gl], ctx=ctx2, counts=False)
+    torch.cuda.synchronize()
+    st = ctx2.pool_stats()
+    assert 0 < st["held"] <= est, (st, est)
+    ctx2.check()
+
+
+def test_queries_take_no_scratch(bench_ctx):
+    import torch
+    import gen
+    import paper_2103_15217_amd as et
+    ctx = bench_ctx("single")
+    n = 1 << 18
+    parent = _d(gen.random_tree(n, 64, seed=5))
+    qx, qy = [_d(a) for a in gen.random_queries(n, 1 << 18, seed=5)]
+    t = et.et_tree_build(parent, ctx=ctx)
+    b = gen.forest_batch(20, seed=5)
+    bt = et.et_tree_build_batch(_d(b["parent"]), torch.from_numpy(b["offsets"].astype(np.int64)).cuda(), ctx=ctx)
+    bq = [_d(b[k]) for k in ("qtree", "qx", "qy")]
+    out, bout = torch.empty_like(qx), torch.empty_like(bq[1])
+    torch.cuda.synchronize()
+    before = ctx.pool_stats(reset_peak=True)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):   # queries may run on another stream than the builds
+        for _ in range(3):
+            t.lca(qx, qy, out=out)
+            bt.lca_batch(*bq, out=bout)
+    torch.cuda.synchronize()
+    after = ctx.pool_stats()
+    assert after == dict(before, peak_live=before["live"]), (before, after)
+    assert np.array_equal(out.cpu().numpy(), t.lca(qx, qy).cpu().numpy())
+    t.free()
+    bt.free()
+    ctx.check()
+
+
+def test_free_is_stream_ordered(oracle_mod):
+    """Tree 1 is built and queried on stream A and freed there without a
+    sync; tree 2 is then built on stream B with the same context, reusing
+    tree 1's blocks. B must wait for A's queries to read them first."""
+    import torch
+    import gen
+    import paper_2103_15217_amd as et
+    ctx = et.Context()
+    n = 1 << 21
+    p1, p2 = gen.random_tree(n, None, seed=21), gen.random_tree(n, 1000, seed=22)
+    qx, qy = gen.random_queries(n, 1 << 22, seed=21)
+    d1, d2, dqx, dqy = _d(p1), _d(p2), _d(qx), _d(qy)
+    a, b = torch.cuda.Stream(), torch.cuda.Stream()
+    warm = et.et_tree_build(d1, ctx=ctx)   # fill the pool with blocks of this size
+    warm.free()
+    torch.cuda.synchronize()
+    held = ctx.pool_stats()["held"]
+    with torch.cuda.stream(a):
+        t1 = et.et_tree_build(d1, ctx=ctx)
+        out1 = t1.lca(dqx, dqy)
+        t1.free()
+    with torch.cuda.stream(b):
+        t2 = et.et_tree_build(d2, ctx=ctx)
+        out2 = t2.lca(dqx, dqy)
+    torch.cuda.synchronize()
+    assert ctx.pool_stats()["held"] <= held + (1 << 20)   # tree 2 reused tree 1's blocks
+    assert np.array_equal(out1.cpu().numpy(), oracle_mod.lca_offline(p1, qx, qy))
+    assert np.array_equal(out2.cpu().numpy(), oracle_mod.lca_offline(p2, qx, qy))
+    t2.free()
+    ctx.check()
+    ctx.close()
