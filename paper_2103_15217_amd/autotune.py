@@ -3,9 +3,11 @@
 Times a workload for a grid of context parameters (``et_ctx_set_param``),
 one parameter at a time around the current best (coordinate descent), and
 stores the winner in ``tuned.json`` next to this file, keyed by GPU
-architecture and workload. ``apply(ctx, workload)`` loads it into a
-context. Results of the library never depend on these parameters; only
-speed does.
+architecture, workload and log2-size bucket (the size the workload was
+tuned at: nodes of a tree, nodes of a whole batch). ``apply(ctx, workload,
+size)`` loads the entry of the stored bucket nearest to ``size`` (in log2)
+into a context. Results of the library never depend on these parameters;
+only speed does.
 
 Parameters: list-ranking splitter spacing and sublists per wavefront
 (level 1 and upper levels), the range-minimum block size of the bridge and
@@ -15,13 +17,18 @@ Workloads:
   single  three trees of 2^log2n nodes (grasp n, 1000, 1), each built and
           queried with 2^log2n uniform pairs, plus bridges on a planted
           sparse graph of 2^graph_log2n vertices and 8x as many edges
-  batch   a forest of many trees of log-uniform size (batched build and
-          batched queries) plus one batched bridge call over many graphs
+  batch   a forest of trees of log-uniform size (batched build and batched
+          queries) plus one batched bridge call over many graphs: at
+          log2n >= 26 the 4096-tree forest of 2^6..2^18-node trees and 1024
+          graphs of 2^6..2^14 vertices; below, 16 trees of
+          2^(log2n-6)..2^(log2n-3) nodes (about 2^log2n in all) and 16
+          graphs of a quarter of that size
 
-    python -m paper_2103_15217_amd.autotune --workload single [--write]
+    python -m paper_2103_15217_amd.autotune --workload single --log2n 20 [--write]
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -46,24 +53,70 @@ def arch():
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
 
 
-def key(workload):
-    return f"{arch()}/{workload}"
+def key(workload, bucket=None):
+    k = f"{arch()}/{workload}"
+    return k if bucket is None else f"{k}/2^{int(bucket)}"
 
 
-def load(workload):
-    """The stored parameters of this GPU and workload, or None."""
-    if not os.path.exists(CACHE):
+_cache = {"path": None, "mtime": None, "data": {}}
+
+
+def _read(path=None):
+    path = path or CACHE
+    if not os.path.exists(path):
+        return {}
+    m = os.path.getmtime(path)
+    if _cache["path"] != path or _cache["mtime"] != m:
+        _cache.update(path=path, mtime=m, data=json.load(open(path)))
+    return _cache["data"]
+
+
+def stored_buckets(cache, arch_name, workload):
+    """{log2 size: params} of one workload; an entry without a bucket in its
+    key counts at the size it was tuned at (its log2n)."""
+    out = {}
+    prefix = f"{arch_name}/{workload}"
+    for k, entry in cache.items():
+        if k == prefix:
+            out.setdefault(int(entry.get("log2n", 24)), dict(entry["params"]))
+        elif k.startswith(prefix + "/2^"):
+            out[int(k[len(prefix) + 3:])] = dict(entry["params"])
+    return out
+
+
+def bucket_for(size, buckets):
+    """The stored bucket nearest to ``size`` in log2 (ties go to the larger)."""
+    if not buckets:
         return None
-    entry = json.load(open(CACHE)).get(key(workload))
-    return dict(entry["params"]) if entry else None
+    lg = math.log2(max(int(size), 1))
+    return min(buckets, key=lambda b: (abs(b - lg), -b))
 
 
-def apply(ctx, workload="single"):
-    """Load the tuned parameters of this GPU and workload into ``ctx``;
-    returns them (None when nothing is stored)."""
-    params = load(workload)
-    for k, v in (params or {}).items():
-        ctx.set_param(k, v)
+def load(workload, size=None):
+    """The stored parameters of this GPU and workload for ``size`` (the
+    largest stored bucket when None), or None."""
+    cache = _read()
+    if not cache:
+        return None
+    buckets = stored_buckets(cache, arch(), workload)
+    if not buckets:
+        return None
+    b = max(buckets) if size is None else bucket_for(size, list(buckets))
+    return dict(buckets[b])
+
+
+def apply(ctx, workload="single", size=None):
+    """Load the tuned parameters of this GPU, workload and size into ``ctx``
+    (skipped when the context already holds them); returns them (None when
+    nothing is stored)."""
+    params = load(workload, size)
+    if params and getattr(ctx, "_tuned_params", None) != params:
+        for k, v in params.items():
+            ctx.set_param(k, v)
+        try:
+            ctx._tuned_params = dict(params)
+        except AttributeError:
+            pass
     return params
 
 
@@ -113,19 +166,24 @@ def single_workload(et, ctx, log2n, graph_log2n):
     return [trees_and_queries, bridges, rmq_engine]
 
 
-def batch_workload(et, ctx, trees, graphs):
+def batch_workload(et, ctx, log2n):
     import numpy as np
     import torch
     sys.path.insert(0, os.path.dirname(HERE))
     import gen
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
-    b = gen.forest_batch(trees, seed=12)
+    if log2n >= 26:
+        trees, tlo, thi, graphs, glo, ghi = 4096, 6, 18, 1024, 6, 14
+    else:
+        trees, tlo, thi = 16, max(log2n - 6, 4), max(log2n - 3, 5)
+        graphs, glo, ghi = 16, max(log2n - 8, 6), max(log2n - 5, 7)
+    b = gen.forest_batch(trees, seed=12, log2_min=tlo, log2_max=thi)
     parent, offs = d(b["parent"]), torch.from_numpy(b["offsets"].astype(np.int64)).cuda()
     qt, qx, qy = d(b["qtree"]), d(b["qx"]), d(b["qy"])
     rng = np.random.default_rng(12)
     gl = []
     for t in range(graphs):
-        n = int(2 ** rng.uniform(6, 14))
+        n = int(2 ** rng.uniform(glo, ghi))
         chains = max(1, n // 512)
         rp, col, _ = gen.planted_bridge_graph(n=n, m=4 * n, chains=chains, max_chain=max(2, n // (8 * chains)),
                                               seed=1000 + t)
@@ -180,14 +238,13 @@ def coordinate_search(cost, grid=None, start=None, rounds=2, log=print):
     return best, final, default, table
 
 
-def tune(workload="single", log2n=24, graph_log2n=22, batch_trees=4096, batch_graphs=1024, reps=3, rounds=2,
-         log=print):
+def tune(workload="single", log2n=24, graph_log2n=22, reps=3, rounds=2, log=print):
     import paper_2103_15217_amd as et
     ctx = et.Context()
     if workload == "single":
         parts = single_workload(et, ctx, log2n, graph_log2n)
     else:
-        parts = batch_workload(et, ctx, batch_trees, batch_graphs)
+        parts = batch_workload(et, ctx, log2n)
 
     def cost(params):
         for k, v in params.items():
@@ -204,15 +261,17 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=["single", "batch"], default="single")
     ap.add_argument("--log2n", type=int, default=24)
-    ap.add_argument("--graph-log2n", type=int, default=22)
+    ap.add_argument("--graph-log2n", type=int, default=None, help="default: log2n - 2")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--write", action="store_true", help=f"store the winner in {CACHE}")
     ap.add_argument("--out", default=CACHE, help="the file --write updates")
     a = ap.parse_args()
     t0 = time.time()
+    if a.graph_log2n is None:
+        a.graph_log2n = max(a.log2n - 2, 8)
     best, ms, default, table = tune(a.workload, a.log2n, a.graph_log2n, reps=a.reps,
                                    log=lambda m: print(m, flush=True))
-    out = {"key": key(a.workload), "params": best, "ms": ms, "default_ms": default, "trials": len(table),
+    out = {"key": key(a.workload, a.log2n), "params": best, "ms": ms, "default_ms": default, "trials": len(table),
            "seconds": time.time() - t0}
     print(json.dumps(out), flush=True)
     if a.write:

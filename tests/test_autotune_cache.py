@@ -77,3 +77,38 @@ def test_coordinate_search_drops_a_pick_that_does_not_hold_up():
         return 50.0 if (p["a"] == 2 and seen[2] == 1) else 100.0
     best, ms, default, _ = autotune.coordinate_search(cost, grid, {"a": 1}, log=lambda m: None)
     assert best == {"a": 1} and ms == default == 100.0
+
+
+def test_bucket_choice():
+    assert autotune.bucket_for(1, [12, 16, 20, 24]) == 12
+    assert autotune.bucket_for(1 << 12, [12, 16, 20, 24]) == 12
+    assert autotune.bucket_for(1 << 14, [12, 16, 20, 24]) == 16      # tie: the larger bucket
+    assert autotune.bucket_for((1 << 14) - 100, [12, 16, 20, 24]) == 12
+    assert autotune.bucket_for(3 << 20, [12, 16, 20, 24]) == 20
+    assert autotune.bucket_for(1 << 30, [12, 16, 20, 24]) == 24
+    assert autotune.bucket_for(1 << 10, [27]) == 27
+    assert autotune.bucket_for(5, []) is None
+
+
+def test_apply_by_size_picks_the_nearest_bucket(tmp_path, monkeypatch):
+    cache = {"gfx950/single/2^12": {"params": {"lr_k1_log2": 3}},
+             "gfx950/single/2^24": {"params": {"lr_k1_log2": 5}},
+             "gfx950/batch": {"params": {"lr_per_wave1": 64}, "log2n": 27}}
+    path = tmp_path / "tuned.json"
+    path.write_text(json.dumps(cache))
+    monkeypatch.setattr(autotune, "CACHE", str(path))
+    monkeypatch.setattr(autotune, "arch", lambda: "gfx950")
+    assert autotune.stored_buckets(cache, "gfx950", "single") == {12: {"lr_k1_log2": 3}, 24: {"lr_k1_log2": 5}}
+    assert autotune.stored_buckets(cache, "gfx950", "batch") == {27: {"lr_per_wave1": 64}}
+    ctx = _FakeCtx()
+    assert autotune.apply(ctx, "single", size=3000) == {"lr_k1_log2": 3}
+    assert autotune.apply(ctx, "single", size=1 << 23) == {"lr_k1_log2": 5}
+    assert autotune.apply(ctx, "single") == {"lr_k1_log2": 5}        # no size: the largest bucket
+    assert autotune.apply(ctx, "batch", size=100) == {"lr_per_wave1": 64}
+    # the same parameters again are not sent to the context a second time
+    calls = []
+    ctx2 = _FakeCtx()
+    ctx2.set_param = lambda k, v: calls.append((k, v))
+    autotune.apply(ctx2, "single", size=1 << 24)
+    autotune.apply(ctx2, "single", size=1 << 25)
+    assert calls == [("lr_k1_log2", 5)]
