@@ -86,9 +86,14 @@ def parse():
                     help="skip the plain vs weighted list ranking of the tours and of a random list")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=4.0)
-    ap.add_argument("--serve-sweep", default="1000,4000,8000,16000",
+    ap.add_argument("--serve-budget-gib", type=float, default=2.0,
+                    help="device-memory budget of the continuous-batching server (GiB)")
+    ap.add_argument("--serve-sweep", default="1000,4000,8000",
                     help="extra arrival rates (jobs/s) replayed for 2 s each to show where each path saturates; "
                          "empty to skip")
+    ap.add_argument("--protocol-seeds", type=int, default=5,
+                    help="instances of the paper's measurement protocol (0 to skip)")
+    ap.add_argument("--protocol-runs", type=int, default=5, help="timed runs per instance (after one warm-up)")
     ap.add_argument("--default-params", action="store_true",
                     help="run with the library's default launch shapes instead of the autotuned ones")
     ap.add_argument("--no-kernel-times", action="store_true",
@@ -318,6 +323,10 @@ def main():
     if not args.no_serve:
         log("serving: generating the job pool")
         result["components"]["serving"] = serving(args, dev)
+    if args.protocol_seeds > 0:
+        log(f"protocol: {args.protocol_seeds} instances x {args.protocol_runs} runs")
+        result["components"]["protocol"] = protocol(args, et, ctx, d, grasps,
+                                                    (d_parent, d_qx, d_qy, d_rp, d_col))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on the sample")
         result["cpu_baseline"], result["parity"] = cpu_baseline(trees[0], qx, qy, rp, col, ginfo, et, d, ctx,
@@ -694,31 +703,49 @@ def bridges_batched_vs_plain(args, et, ctx, d):
 
 
 def serving(args, dev):
-    """Open-loop Poisson trace (70 % LCA jobs on trees of 2^10..2^22 nodes,
-    half of them on a tree seen before; 30 % bridge jobs on graphs of
-    2^12..2^20 vertices, average degree 8..32) replayed in real time through
-    the plain FCFS per-job path and through the continuous-batching server."""
+    """Open-loop Poisson trace (70 % LCA jobs on trees of 2^10..2^22 nodes:
+    with probability 1/2 one of the 32 most recently used trees, else a tree
+    never seen before; 30 % bridge jobs on graphs of 2^12..2^20 vertices,
+    average degree 8..32) replayed in real time through the plain FCFS
+    per-job path and through the continuous-batching server, which admits
+    jobs by the library's footprint figures within a device-memory budget."""
     from paper_2103_15217_amd import serve
     t0 = time.time()
-    pool = serve.make_pool(seed=args.seed)
-    dpool = serve.upload_pool(pool, dev)
-    jobs = serve.make_trace(pool, args.serve_rate, args.serve_seconds, seed=args.seed)
-    serve.upload_trace(jobs, dev)
-    log(f"serving: pool and {len(jobs)}-job trace ready in {time.time() - t0:.1f}s")
-    res = serve.compare(dpool, jobs, tuned=not args.default_params)
+    bases = serve.make_bases(seed=args.seed)
+    graphs = serve.make_graphs(seed=args.seed)
+    dinp = serve.DeviceInputs(bases, graphs, dev)
+    budget = int(args.serve_budget_gib * (1 << 30))
+
+    def replay(rate, seconds, seed):
+        jobs, specs = serve.make_trace(bases, graphs, rate, seconds, seed=seed)
+        dinp.prepare(jobs, specs)
+        r = serve.compare(dinp, jobs, budget_bytes=budget, tuned=not args.default_params)
+        r["trace_cold_fraction"] = serve.cold_fraction(jobs)
+        r["distinct_trees"] = len(specs)
+        dinp.release_trees()
+        return r
+
+    jobs_probe, _ = serve.make_trace(bases, graphs, args.serve_rate, args.serve_seconds, seed=args.seed)
+    log(f"serving: {len(bases)} base trees, {len(graphs)} graphs, {len(jobs_probe)}-job trace "
+        f"ready in {time.time() - t0:.1f}s")
+    res = replay(args.serve_rate, args.serve_seconds, args.seed)
     res["rate_jobs_per_s"] = args.serve_rate
     res["trace_seconds"] = args.serve_seconds
+    res["budget_bytes"] = budget
     res["p99_ratio_served_over_plain"] = res["served"]["p99_ms"] / res["plain"]["p99_ms"]
+    s = res["served"]
+    log(f"serving {args.serve_rate:.0f} jobs/s: plain p50/p99 {res['plain']['p50_ms']:.2f}/"
+        f"{res['plain']['p99_ms']:.2f} ms, served {s['p50_ms']:.2f}/{s['p99_ms']:.2f} ms; cold "
+        f"{s['cold_fraction']:.2f}, evictions {s['evictions']}, deferrals {s['deferrals']}")
     sweep = []
     for rate in [float(r) for r in args.serve_sweep.split(",") if r.strip()]:
-        jobs = serve.make_trace(pool, rate, 2.0, seed=args.seed + 1)
-        serve.upload_trace(jobs, dev)
-        r = serve.compare(dpool, jobs, tuned=not args.default_params)
+        r = replay(rate, 2.0, args.seed + 1)
         log(f"serving sweep {rate:.0f} jobs/s: plain p99 {r['plain']['p99_ms']:.2f} ms, "
             f"served p99 {r['served']['p99_ms']:.2f} ms")
-        sweep.append({"rate_jobs_per_s": rate, "jobs": len(jobs),
+        sweep.append({"rate_jobs_per_s": rate, "jobs": r["served"]["jobs"],
                       **{f"{k}_{m}": r[k][m] for k in ("plain", "served")
-                         for m in ("p50_ms", "p99_ms", "jobs_per_s", "wall_s")}})
+                         for m in ("p50_ms", "p99_ms", "jobs_per_s", "wall_s")},
+                      **{f"served_{m}": r["served"][m] for m in ("cold_fraction", "evictions", "deferrals")}})
     res["sweep"] = sweep
     return res
 
@@ -816,7 +843,7 @@ def cpu_baseline(parent, qx, qy, rp, col, ginfo, et, d, ctx, d_parent, d_qx, d_q
         "bridges_count": int(cnt), "bridges_count_oracle": int(cnt_ref),
     }
     base = {"value": elements / secs, "unit": "elements/s (tree nodes + LCA queries + graph edges)",
-            "cores": 1, "kind": "oracle",
+            "cores": 1, "kind": "oracle", **host_cpu(),
             "sample": (f"grasp-n tree of {n} nodes (Euler tour, depth/preorder/size, Inlabel tables) + {q} "
                        f"offline LCA queries ({t1 - t0:.1f}s), and Tarjan bridges on the {len(rp) - 1}-vertex "
                        f"{ginfo['m']}-edge graph ({t2 - t1:.1f}s)"),
@@ -824,5 +851,111 @@ def cpu_baseline(parent, qx, qy, rp, col, ginfo, et, d, ctx, d_parent, d_qx, d_q
     return base, parity
 
 
+def host_cpu():
+    """The host's CPU model and logical CPU count (the oracle runs on one
+    thread of it)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"host_cpu_model": model, "host_logical_cpus": os.cpu_count(), "host_cpus_usable": usable}
+
+
+def protocol(args, et, ctx, d, grasps, first):
+    """The paper's protocol (Section 3.3, Section 4.3): 5 instances (seeds)
+    x 5 runs after one warm-up run, per component: the build of each grasp
+    tree, its 2^log2n queries, and the bridges call. ``first`` holds the
+    instance of ``args.seed`` already on the device."""
+    import torch
+    import gen
+    n = 1 << args.log2n
+    gn, gm = 1 << args.graph_log2n, 1 << args.graph_log2m
+    chains = 4096 if args.graph_log2n >= 16 else 16
+    runs = {f"build_{g}": [] for g in ("n", "1000", "1")}
+    runs.update({f"lca_{g}": [] for g in ("n", "1000", "1")})
+    runs["bridges"] = []
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        r = fn()
+        b.record(stream)
+        return r, (a, b)
+
+    for k in range(args.protocol_seeds):
+        seed = args.seed + k
+        t0 = time.time()
+        if k == 0:
+            d_parent, d_qx, d_qy, d_rp, d_col = first
+            m = None
+        else:
+            d_parent = [d(gen.random_tree(n, g, seed=seed + i)) for i, g in enumerate(grasps)]
+            qx, qy = gen.random_queries(n, n, seed=seed)
+            d_qx, d_qy = d(qx), d(qy)
+            rp, col, _ = gen.planted_bridge_graph(n=gn, m=gm, chains=chains, max_chain=min(512, max(2, gn >> 13)),
+                                                  seed=seed)
+            d_rp, d_col = d(rp), d(col)
+        out = torch.empty_like(d_qx)
+        mask = torch.empty(max((d_col.numel() + 31) // 32, 1), dtype=torch.int32, device=d_col.device)
+        pairs = {key: [] for key in runs}
+        for r in range(1 + args.protocol_runs):
+            for i, g in enumerate(("n", "1000", "1")):
+                t, e = timed(lambda: et.et_tree_build(d_parent[i], ctx=ctx))
+                _, e2 = timed(lambda: t.lca(d_qx, d_qy, out=out))
+                t.free()
+                if r:
+                    pairs[f"build_{g}"].append(e)
+                    pairs[f"lca_{g}"].append(e2)
+            _, e = timed(lambda: et.et_bridges(d_rp, d_col, mask=mask, ctx=ctx, count=False))
+            if r:
+                pairs["bridges"].append(e)
+        torch.cuda.synchronize()
+        ctx.check()
+        for key, evs in pairs.items():
+            runs[key].extend(a.elapsed_time(b) for a, b in evs)
+        log(f"protocol: instance {k} (seed {seed}) in {time.time() - t0:.1f}s")
+    units = {"build": ("nodes/s", n), "lca": ("queries/s", n), "bridges": ("edges/s", None)}
+    out = {"instances": args.protocol_seeds, "runs_per_instance": args.protocol_runs, "warmup_runs": 1}
+    for key, ms in runs.items():
+        ms = np.asarray(ms)
+        unit, count = units[key.split("_")[0]]
+        count = count if count is not None else gm
+        rate = count / (ms * 1e-3)
+        out[key] = {"ms_mean": float(ms.mean()), "ms_min": float(ms.min()), "ms_max": float(ms.max()),
+                    "ms_rel_std": float(ms.std() / ms.mean()), "rate_mean": float(rate.mean()),
+                    "rate_max": float(rate.max()), "unit": unit}
+    return out
+
+
+def end_children():
+    """List and end any child process this run left (none is expected);
+    names them on stderr so a leftover can be traced to its source."""
+    try:
+        import psutil
+    except ImportError:
+        return []
+    kids = psutil.Process().children(recursive=True)
+    for k in kids:
+        try:
+            log(f"ending leftover child process {k.pid}: {' '.join(k.cmdline())[:200]}")
+            k.terminate()
+        except psutil.Error:
+            pass
+    if kids:
+        psutil.wait_procs(kids, timeout=5)
+    return [k.pid for k in kids]
+
+
 if __name__ == "__main__":
     main()
+    end_children()
