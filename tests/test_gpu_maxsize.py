@@ -272,7 +272,15 @@ def test_bridges_at_the_slot_limit(lib, ctx):
 
 
 def test_vertex_limit_rejected(lib, ctx):
+    import ctypes
     row_ptr = torch.zeros((1 << 30) + 1, dtype=torch.int32, device="cuda")
-    col = torch.zeros(0, dtype=torch.int32, device="cuda")
-    with pytest.raises(lib.EtError):
+    col = torch.zeros(1, dtype=torch.int32, device="cuda")
+    mask = torch.zeros(1, dtype=torch.int32, device="cuda")
+    # the binding refuses the size before the call ...
+    with pytest.raises(ValueError):
         lib.et_bridges(row_ptr, col, ctx=ctx)
+    # ... and the C ABI itself returns ET_EINVAL for n = 2^30 vertices
+    P = ctypes.c_void_p
+    rc = lib.et._lib.et_bridges(ctx.handle, P(row_ptr.data_ptr()), P(col.data_ptr()), 1 << 30, 0,
+                                P(mask.data_ptr()), None, P(torch.cuda.current_stream().cuda_stream))
+    assert rc == lib.et.ET_EINVAL
