@@ -9,6 +9,9 @@
 // Over an int32 array of 2^log2n elements it times, best of 5 launches:
 //   copy        streaming copy of 8 B per element (reference bandwidth)
 //   gather      out[i] = a[idx[i]], idx a random permutation (independent random reads)
+//   gather8     the same with 8-byte elements (an array of 8 B x 2^log2n)
+//   gather16    the same with 16-byte elements (the query kernel's record loads)
+//   scatter4    out[idx[i]] = i, 4-byte stores (the successor kernel's stores)
 //   scatter8    rec[idx[i]] = i, 8-byte records (independent random writes)
 //   chase       2^19 lanes each follow a[] through a disjoint piece of one random
 //               cycle (dependent random reads, one chain per lane)
@@ -47,6 +50,21 @@ __global__ void k_gather(const int32_t* __restrict__ a, const int32_t* __restric
                          int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = a[idx[i]];
+}
+
+template <typename T>
+__global__ void k_gather_w(const T* __restrict__ a, const int32_t* __restrict__ idx, int32_t* __restrict__ out,
+                           int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const T v = a[idx[i]];
+    out[i] = (int32_t)(reinterpret_cast<const uint32_t*>(&v)[0] ^ reinterpret_cast<const uint32_t*>(&v)[sizeof(T) / 4 - 1]);
+  }
+}
+
+__global__ void k_scatter4(const int32_t* __restrict__ idx, int32_t* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[idx[i]] = (int32_t)i;
 }
 
 __global__ void k_scatter8(const int32_t* __restrict__ idx, uint64_t* __restrict__ rec, int64_t n) {
@@ -92,19 +110,21 @@ int main(int argc, char** argv) {
 
   int32_t *d_a, *d_idx, *d_out, *d_start, *d_lane;
   uint64_t* d_rec;
-  int4 *d_c0, *d_c1;
+  int4 *d_c0, *d_c1, *d_g16;
   CHECK(hipMalloc(&d_a, n * 4));
   CHECK(hipMalloc(&d_idx, n * 4));
   CHECK(hipMalloc(&d_out, n * 4));
   CHECK(hipMalloc(&d_rec, n * 8));
   CHECK(hipMalloc(&d_c0, n * 8));
   CHECK(hipMalloc(&d_c1, n * 8));
+  CHECK(hipMalloc(&d_g16, n * 16));
   CHECK(hipMalloc(&d_start, lanes * 4));
   CHECK(hipMalloc(&d_lane, lanes * 4));
   CHECK(hipMemcpy(d_idx, perm.data(), n * 4, hipMemcpyHostToDevice));
   CHECK(hipMemcpy(d_a, cyc.data(), n * 4, hipMemcpyHostToDevice));
   CHECK(hipMemcpy(d_start, start.data(), lanes * 4, hipMemcpyHostToDevice));
   CHECK(hipMemset(d_c0, 1, n * 8));
+  CHECK(hipMemset(d_g16, 3, n * 16));
   hipEvent_t e0, e1;
   CHECK(hipEventCreate(&e0));
   CHECK(hipEventCreate(&e1));
@@ -130,6 +150,14 @@ int main(int argc, char** argv) {
   const unsigned gl = (unsigned)((lanes + kB - 1) / kB);
   measure("copy", 16.0, [&] { hipLaunchKernelGGL(k_copy, dim3((unsigned)((n / 2 + kB - 1) / kB)), dim3(kB), 0, 0, d_c0, d_c1, n / 2); });
   measure("gather", 12.0, [&] { hipLaunchKernelGGL(k_gather, dim3(g), dim3(kB), 0, 0, d_a, d_idx, d_out, n); });
+  measure("gather8", 16.0, [&] {
+    hipLaunchKernelGGL(k_gather_w<uint64_t>, dim3(g), dim3(kB), 0, 0, reinterpret_cast<const uint64_t*>(d_c0), d_idx,
+                       d_out, n);
+  });
+  measure("gather16", 24.0, [&] {
+    hipLaunchKernelGGL(k_gather_w<int4>, dim3(g), dim3(kB), 0, 0, d_g16, d_idx, d_out, n);
+  });
+  measure("scatter4", 8.0, [&] { hipLaunchKernelGGL(k_scatter4, dim3(g), dim3(kB), 0, 0, d_idx, d_out, n); });
   measure("scatter8", 12.0, [&] { hipLaunchKernelGGL(k_scatter8, dim3(g), dim3(kB), 0, 0, d_idx, d_rec, n); });
   measure("chase", 4.0, [&] {
     hipLaunchKernelGGL(k_chase<false>, dim3(gl), dim3(kB), 0, 0, d_a, d_start, lanes, steps, d_rec, d_lane);
@@ -138,7 +166,7 @@ int main(int argc, char** argv) {
     hipLaunchKernelGGL(k_chase<true>, dim3(gl), dim3(kB), 0, 0, d_a, d_start, lanes, steps, d_rec, d_lane);
   });
   CHECK(hipGetLastError());
-  for (void* p : {(void*)d_a, (void*)d_idx, (void*)d_out, (void*)d_rec, (void*)d_c0, (void*)d_c1, (void*)d_start,
+  for (void* p : {(void*)d_a, (void*)d_idx, (void*)d_out, (void*)d_rec, (void*)d_c0, (void*)d_c1, (void*)d_g16, (void*)d_start,
                   (void*)d_lane})
     CHECK(hipFree(p));
   return 0;
