@@ -664,7 +664,8 @@ size_t list_rank_plan_bytes(const Ctx* c, int32_t len, int32_t nheads, int weigh
   Scratch count(&shape, nullptr, nullptr, 0);
   LrPlan pl;
   list_rank_plan(&shape, count, len, nheads, weighted, &pl);
-  return count.used;
+  // as pool blocks: every block, the last one too, takes whole 256-byte units
+  return (count.used + 255) & ~(size_t)255;
 }
 
 size_t list_rank_scratch_bytes(Ctx* c, int32_t len, int32_t nheads) {
