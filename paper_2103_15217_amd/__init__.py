@@ -9,9 +9,9 @@ The work runs in the hand-written HIP kernels of ``libet.so``; the C ABI is
 from .et import (BatchGraph, BridgesBatchGraph, Context, EtError, Tree, default_context, et_bridges,
                  et_bridges_batch, et_bridges_ck, et_lca, et_lca_batch, et_lca_naive, et_levels,
                  et_list_rank, et_list_scan, et_tree_build, et_tree_build_batch, et_tree_build_edges,
-                 version, LIB_PATH)
+                 tree_footprint, bridges_footprint, version, LIB_PATH)
 
 __all__ = ["BatchGraph", "BridgesBatchGraph", "Context", "EtError", "Tree", "default_context", "et_bridges",
            "et_bridges_batch", "et_bridges_ck", "et_lca", "et_lca_batch", "et_lca_naive", "et_levels",
            "et_list_rank", "et_list_scan", "et_tree_build", "et_tree_build_batch", "et_tree_build_edges",
-           "version", "LIB_PATH"]
+           "tree_footprint", "bridges_footprint", "version", "LIB_PATH"]
