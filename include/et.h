@@ -61,6 +61,7 @@ extern "C" {
 #define ET_ENOMEM (-2)  /* device memory exhausted */
 #define ET_EHIP (-3)    /* a HIP runtime call failed */
 #define ET_EINPUT (-4)  /* malformed input detected on the device */
+#define ET_ESIZE (-5)   /* input beyond a fixed-size limit of the entry point (its scratch or LDS) */
 
 typedef struct et_ctx et_ctx;
 typedef struct et_tree et_tree;
@@ -137,6 +138,31 @@ int et_ctx_profile_read(et_ctx* ctx, hipStream_t s, char* h_buf, int32_t buflen)
  */
 int et_list_rank(et_ctx* ctx, const int32_t* d_succ, int32_t len, const int32_t* d_heads,
                  int32_t n_heads, int32_t* d_rank, hipStream_t s);
+
+/*
+ * List ranking without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same operation, arguments and results as
+ * et_list_rank, with the scratch taken from one fixed array of
+ * ET_NOALLOC_SCRATCH_BYTES in the library's device memory instead of the
+ * context's pool. Nothing is allocated or freed by this call (and no memset
+ * is enqueued: counters are cleared by kernels).
+ *   Limits: len <= ET_NOALLOC_MAX_LEN, n_heads <= ET_NOALLOC_MAX_HEADS;
+ *   larger inputs return ET_ESIZE and enqueue nothing. Within these limits
+ *   the scratch fits every launch shape et_ctx_set_param allows (the plan is
+ *   still checked on every call, ET_ESIZE if it would not fit).
+ *   The array is per GPU, created with the library's code on that GPU and
+ *   held until the process ends; its device address is resolved when a
+ *   context is created on the device. Every call on one GPU uses the same
+ *   array and leaves the last call's contents in it (each call clears what
+ *   it needs), so calls that overlap on one GPU -- concurrent streams, or
+ *   several contexts -- race and give wrong ranks: order them.
+ */
+#define ET_NOALLOC_MAX_LEN (1 << 20)
+#define ET_NOALLOC_MAX_HEADS (1 << 16)
+#define ET_NOALLOC_SCRATCH_BYTES (40u << 20)
+int et_list_rank_noalloc(et_ctx* ctx, const int32_t* d_succ, int32_t len, const int32_t* d_heads,
+                         int32_t n_heads, int32_t* d_rank, hipStream_t s);
 
 /*
  * Weighted list ranking: prefix sums along lists (Section 2.2: list ranking

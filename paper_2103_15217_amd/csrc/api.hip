@@ -4,6 +4,7 @@
 #include <cstring>
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -140,6 +141,35 @@ size_t tree_table_bytes(int32_t n, int32_t batch) {
 
 using et::Ctx;
 
+// Fixed scratch of et_list_rank_noalloc. Each GPU that loads the library's
+// code holds its own copy of this array (until the process ends), at its own
+// address. On the host the name is only a stand-in for the symbol, never a
+// device address: kernels and copies get the address resolved per device by
+// hipGetSymbolAddress below.
+static __device__ __align__(256) char scratch[ET_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+void* g_fixed[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (which must be current),
+// resolved once per device. nullptr if it cannot be resolved.
+void* fixed_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_fixed_mu);
+  if (!g_fixed[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_fixed[dev] = p;
+  }
+  return g_fixed[dev];
+}
+}  // namespace
+
 extern "C" {
 
 int et_version(void) { return 100; }
@@ -151,6 +181,7 @@ const char* et_strerror(int code) {
     case ET_ENOMEM: return "out of device memory";
     case ET_EHIP: return "HIP runtime error";
     case ET_EINPUT: return "malformed input detected on the device";
+    case ET_ESIZE: return "input beyond a fixed-size limit of this call";
     default: return "unknown error";
   }
 }
@@ -178,6 +209,9 @@ int et_ctx_create(et_ctx** out) {
   c->d_status = static_cast<uint32_t*>(p);
   c->d_scalars = reinterpret_cast<int32_t*>(static_cast<char*>(p) + 64);
   c->d_bcount = reinterpret_cast<int64_t*>(static_cast<char*>(p) + 128);
+  // the fixed scratch of et_list_rank_noalloc on this device (resolved here,
+  // so that the non-allocating call itself makes no runtime set-up call)
+  c->d_fixed = fixed_scratch(c->device);
   *out = ctx;
   return ET_OK;
 }
@@ -293,6 +327,19 @@ int et_list_rank(et_ctx* ctx, const int32_t* d_succ, int32_t len, const int32_t*
   if (n_heads > 0 && !d_heads) return ET_EINVAL;
   if (len > 0 && n_heads == 0) return ET_EINVAL;
   return et::list_rank_generic(&ctx->impl, d_succ, len, d_heads, n_heads, d_rank, s);
+}
+
+int et_list_rank_noalloc(et_ctx* ctx, const int32_t* d_succ, int32_t len, const int32_t* d_heads,
+                         int32_t n_heads, int32_t* d_rank, hipStream_t s) {
+  if (!ctx || len < 0 || n_heads < 0) return ET_EINVAL;
+  if (len > 0 && (!d_succ || !d_rank)) return ET_EINVAL;
+  if (n_heads > 0 && !d_heads) return ET_EINVAL;
+  if (len > 0 && n_heads == 0) return ET_EINVAL;
+  if (len > ET_NOALLOC_MAX_LEN || n_heads > ET_NOALLOC_MAX_HEADS) return ET_ESIZE;
+  Ctx* c = &ctx->impl;
+  if (!c->d_fixed) return ET_EHIP;
+  if (et::list_rank_scratch_bytes(c, len, n_heads) > ET_NOALLOC_SCRATCH_BYTES) return ET_ESIZE;
+  return et::list_rank_arena(c, c->d_fixed, ET_NOALLOC_SCRATCH_BYTES, d_succ, len, d_heads, n_heads, d_rank, s);
 }
 
 int et_list_scan(et_ctx* ctx, const int32_t* d_succ, const int32_t* d_weight, int32_t len, const int32_t* d_heads,

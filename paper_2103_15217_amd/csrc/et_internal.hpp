@@ -67,6 +67,7 @@ struct Ctx {
   uint32_t* d_status = nullptr;      // accumulated status bits
   int32_t* d_scalars = nullptr;      // small per-call device scalars (root, head, counters)
   int64_t* d_bcount = nullptr;       // bridge count of the last et_bridges
+  void* d_fixed = nullptr;           // this device's fixed scratch (et_list_rank_noalloc)
   // caching pool: free blocks by size, each with the stream that released it
   struct FreeBlock {
     void* p;
@@ -313,7 +314,6 @@ int list_rank_arena(Ctx* c, void* arena, size_t bytes, const int32_t* succ, int3
                     int32_t nheads, int32_t* rank, hipStream_t s);
 int list_scan_generic(Ctx* c, const int32_t* succ, const int32_t* weights, int32_t len, const int32_t* heads,
                       int32_t nheads, int32_t* rank, int32_t* sum, hipStream_t s);
-
 }  // namespace et
 
 // the public opaque types

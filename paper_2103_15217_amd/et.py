@@ -35,6 +35,7 @@ _SIG = {
     "et_ctx_profile_read": ([_P, _P, ctypes.c_char_p, _i32], ctypes.c_int),
     "et_list_rank": ([_P, _P, _i32, _P, _i32, _P, _P], ctypes.c_int),
     "et_list_scan": ([_P, _P, _P, _i32, _P, _i32, _P, _P, _P], ctypes.c_int),
+    "et_list_rank_noalloc": ([_P, _P, _i32, _P, _i32, _P, _P], ctypes.c_int),
     "et_tree_build": ([_P, _P, _i32, _P, ctypes.POINTER(_P)], ctypes.c_int),
     "et_tree_size": ([_P], _i32),
     "et_tree_batch_size": ([_P], _i32),
@@ -64,7 +65,10 @@ for _name, (_args, _res) in _SIG.items():
     _fn.argtypes = _args
     _fn.restype = _res
 
-ET_OK, ET_EINVAL, ET_ENOMEM, ET_EHIP, ET_EINPUT = 0, -1, -2, -3, -4
+ET_OK, ET_EINVAL, ET_ENOMEM, ET_EHIP, ET_EINPUT, ET_ESIZE = 0, -1, -2, -3, -4, -5
+# limits of et_list_rank_noalloc (et.h)
+NOALLOC_MAX_LEN = 1 << 20
+NOALLOC_MAX_HEADS = 1 << 16
 
 STATUS_BITS = {
     1 << 0: "bad parent", 1 << 1: "root count", 1 << 2: "unreached element",
@@ -241,6 +245,24 @@ def et_list_rank(succ, heads, rank=None, ctx=None):
         rank = torch.empty_like(succ)
     _check(_lib.et_list_rank(ctx.handle, _ptr(succ), L, _ptr(heads), H,
                              _ptr(rank), _stream()), "et_list_rank")
+    return rank
+
+
+def et_list_rank_noalloc(succ, heads, rank, ctx=None):
+    """``et_list_rank`` with its scratch in the library's fixed per-GPU array:
+    the call allocates nothing, so ``rank`` must be given. Lists of at most
+    ``NOALLOC_MAX_LEN`` elements and ``NOALLOC_MAX_HEADS`` heads; calls that
+    overlap on one GPU race (they share the array)."""
+    ctx = ctx or default_context()
+    succ = _dev(succ, torch.int32, "succ")
+    heads = _dev(heads, torch.int32, "heads")
+    rank = _dev(rank, torch.int32, "rank")
+    L = _i32(succ.numel(), "list length", LIST_MAX)
+    H = _i32(heads.numel(), "number of list heads")
+    if rank.numel() < L:
+        raise ValueError("rank is shorter than succ")
+    _check(_lib.et_list_rank_noalloc(ctx.handle, _ptr(succ), L, _ptr(heads), H,
+                                     _ptr(rank), _stream()), "et_list_rank_noalloc")
     return rank
 
 

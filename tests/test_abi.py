@@ -55,3 +55,4 @@ def test_host_argument_checks():
     I32, I64 = ctypes.c_int32, ctypes.c_int64
     lib.et_bridges_batch.argtypes = [P, P, P, P, P, I32, I32, I32, P, I64, P, P]
     assert lib.et_bridges_batch(None, None, None, None, None, 1, 4, 8, None, 1, None, None) == -1
+    assert lib.et_strerror(-5) == b"input beyond a fixed-size limit of this call"
