@@ -303,6 +303,9 @@ def main():
         log("batched forest: generating")
         result["components"]["batched"] = batched_vs_plain(args, et, bctx, d, dev)
     if not args.no_batch:
+        log("small-tree batches: one fused launch vs the multi-kernel batch")
+        result["components"]["small_batches"] = small_batches(args, et, bctx, d, dev)
+    if not args.no_batch:
         log("batched graphs: generating")
         result["components"]["bridges_batched"] = bridges_batched_vs_plain(args, et, bctx, d)
     if not args.no_engines:
@@ -645,6 +648,79 @@ def batched_vs_plain(args, et, ctx, d, dev):
             "batched_queries_per_s": q / (res["batched"]["gpu_ms"] * 1e-3),
             "speedup": res["plain"]["gpu_ms"] / res["batched"]["gpu_ms"],
             "graph_ms": res["graph"]["gpu_ms"], "graph_matches_eager": graph_ok, **res["breakdown"]}
+
+
+def small_batches(args, et, ctx, d, dev):
+    """Batches of small trees (log-uniform sizes in [2^6, 2^12], grasp 1, 64
+    or n, 2^10..2^14 queries per tree) with total size from 2^10 to 2^22
+    nodes: the one-launch fused path (eager and replayed from a HIP graph)
+    against the multi-kernel batched path (eager and from its HIP graph).
+    The crossover is the smallest total at which the multi-kernel graph is
+    faster; every fused answer is checked against the multi-kernel one."""
+    import torch
+    import gen
+    rows = []
+    stream = torch.cuda.current_stream()
+
+    def time_fn(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for lg in range(10, 23, 2):
+        target = 1 << lg
+        # enough trees for the target total (mean size of log-uniform [2^6, 2^12] is about 950)
+        T = max(1, int(target / 950 * 1.3) + 2)
+        b = gen.forest_batch(T, seed=args.seed + lg, log2_min=6, log2_max=min(12, lg))
+        keep = int(np.searchsorted(b["offsets"], target, side="right")) - 1
+        keep = max(1, min(keep, T))
+        qn = int(np.searchsorted(b["qtree"], keep))
+        off = b["offsets"][:keep + 1]
+        parent = b["parent"][:int(off[-1])]
+        qt, qx, qy = b["qtree"][:qn], b["qx"][:qn], b["qy"][:qn]
+        qoff = np.searchsorted(qt, np.arange(keep + 1)).astype(np.int64)
+        d_parent, d_qt, d_qx, d_qy = d(parent), d(qt), d(qx), d(qy)
+        d_off = torch.from_numpy(off.astype(np.int64)).to(dev)
+        d_qoff = torch.from_numpy(qoff).to(dev)
+        max_nodes = int(np.diff(off).max())
+        d_out = torch.empty_like(d_qx)
+        reps = 20 if lg <= 16 else 5
+
+        def fused():
+            et.et_lca_batch_fused(d_parent, d_off, d_qoff, d_qx, d_qy, max_nodes, out=d_out, ctx=ctx)
+
+        def multi():
+            tr = et.et_tree_build_batch(d_parent, d_off, ctx=ctx)
+            tr.lca_batch(d_qt, d_qx, d_qy)
+            tr.free()
+
+        fused_ms = time_fn(fused, reps)
+        multi_ms = time_fn(multi, reps)
+        fg = et.FusedBatchGraph(d_parent, d_off, d_qoff, d_qx, d_qy, max_nodes, ctx=ctx)
+        fused_graph_ms = time_fn(fg.replay, reps)
+        mctx = et.Context()
+        mg = et.BatchGraph(d_parent, d_off, d_qt, d_qx, d_qy, ctx=mctx)
+        multi_graph_ms = time_fn(mg.replay, reps)
+        same = bool(torch.equal(fg.out, mg.out))
+        fg.close()
+        mg.close()
+        mctx.close()
+        ctx.check()
+        nodes = int(off[-1])
+        rows.append({"log2_target": lg, "trees": keep, "nodes": nodes, "queries": qn, "max_tree_nodes": max_nodes,
+                     "fused_ms": fused_ms, "fused_graph_ms": fused_graph_ms, "multi_ms": multi_ms,
+                     "multi_graph_ms": multi_graph_ms,
+                     "fused_nodes_per_s": nodes / (fused_graph_ms * 1e-3),
+                     "multi_nodes_per_s": nodes / (multi_graph_ms * 1e-3),
+                     "fused_over_multi_graph": multi_graph_ms / fused_graph_ms, "answers_equal": same})
+    cross = next((r["nodes"] for r in rows if r["multi_graph_ms"] < r["fused_graph_ms"]), None)
+    return {"sweep": rows, "crossover_nodes": cross}
 
 
 def bridges_batched_vs_plain(args, et, ctx, d):

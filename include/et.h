@@ -262,6 +262,47 @@ int et_lca_batch(const et_tree* tree, const int32_t* d_qtree, const int32_t* d_q
                  const int32_t* d_qy, int64_t q, int32_t* d_out, hipStream_t s);
 
 /*
+ * Many small trees built and queried in one kernel launch (Section 3.3,
+ * batched queries on preprocessed trees; Sections 2 and 3.1 for each
+ * tree's path). Each tree is built entirely in one workgroup's LDS (stable
+ * child grouping, successors, sublist list ranking of the tour, depth /
+ * preorder / size, Inlabel tables) and its queries are answered from those
+ * tables, so HBM sees only the parent arrays, the queries and the answers.
+ * Workgroups take trees from a counter until none are left (a persistent
+ * grid sized to the GPU). Nothing is kept: the call returns no et_tree.
+ *   d_parent[n_total]        concatenated parent arrays, local ids, -1 at
+ *                            each tree's root (as for et_tree_build_batch)
+ *   d_offsets[n_trees + 1]   device int64 node offsets: tree t is
+ *                            [offsets[t], offsets[t+1]); offsets[0] = 0,
+ *                            offsets[n_trees] = n_total
+ *   max_tree_nodes           an upper bound on every tree's size, 1 ..
+ *                            ET_FUSED_MAX_NODES; it sets the LDS each
+ *                            workgroup takes (a smaller bound lets more
+ *                            workgroups share a compute unit)
+ *   d_qoffsets[n_trees + 1]  device int64 query offsets: the queries of tree
+ *                            t are [qoffsets[t], qoffsets[t+1]) (queries come
+ *                            grouped by tree); qoffsets[n_trees] = q_total
+ *   d_qx, d_qy[q_total]      local node ids of each query
+ *   d_out[q_total]           output: the LCA as a local id; -1 for a query
+ *                            with an id out of range or on a malformed tree
+ *   d_depth, d_pre, d_size   optional outputs (NULL allowed), n_total
+ *                            entries each: depth, 0-based preorder and
+ *                            subtree size of every node within its tree
+ * Same results as et_tree_build_batch + et_lca_batch (and per tree as
+ * et_tree_build + et_lca). ET_ESIZE if max_tree_nodes exceeds
+ * ET_FUSED_MAX_NODES or the LDS it needs exceeds what one workgroup may
+ * take on this GPU. A tree larger than max_tree_nodes, a parent array that
+ * is not one tree, or inconsistent offsets set ET_EINPUT in ctx's status.
+ * Uses a counter pair of ctx: calls sharing a context must be ordered on
+ * one stream.
+ */
+#define ET_FUSED_MAX_NODES 4096
+int et_lca_batch_fused(et_ctx* ctx, const int32_t* d_parent, const int64_t* d_offsets, int32_t n_trees,
+                       int64_t n_total, int32_t max_tree_nodes, const int64_t* d_qoffsets, const int32_t* d_qx,
+                       const int32_t* d_qy, int64_t q_total, int32_t* d_out, int32_t* d_depth, int32_t* d_pre,
+                       int32_t* d_size, hipStream_t s);
+
+/*
  * The tour itself as an array (Section 2: the Euler tour as the sequence of
  * its half-edges, the inverse of the rank): d_tour[r] = the half-edge id at
  * tour position r, for r in [0, 2(n-1)). Half-edge ids as for d_rank of

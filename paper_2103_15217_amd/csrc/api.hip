@@ -209,6 +209,7 @@ int et_ctx_create(et_ctx** out) {
   c->d_status = static_cast<uint32_t*>(p);
   c->d_scalars = reinterpret_cast<int32_t*>(static_cast<char*>(p) + 64);
   c->d_bcount = reinterpret_cast<int64_t*>(static_cast<char*>(p) + 128);
+  c->d_fused = reinterpret_cast<uint32_t*>(static_cast<char*>(p) + 192);  // zero; kept zero between launches
   // the fixed scratch of et_list_rank_noalloc on this device (resolved here,
   // so that the non-allocating call itself makes no runtime set-up call)
   c->d_fixed = fixed_scratch(c->device);
@@ -507,6 +508,20 @@ int et_lca_batch(const et_tree* tree, const int32_t* d_qtree, const int32_t* d_q
   if (!tree || !tree->batch || q < 0 || q > (int64_t)0x7fffffff * 64) return ET_EINVAL;
   if (q > 0 && (!d_qtree || !d_qx || !d_qy || !d_out)) return ET_EINVAL;
   return et::tree_lca_batch(&tree->ctx->impl, tree, d_qtree, d_qx, d_qy, q, d_out, s);
+}
+
+int et_lca_batch_fused(et_ctx* ctx, const int32_t* d_parent, const int64_t* d_offsets, int32_t n_trees,
+                       int64_t n_total, int32_t max_tree_nodes, const int64_t* d_qoffsets, const int32_t* d_qx,
+                       const int32_t* d_qy, int64_t q_total, int32_t* d_out, int32_t* d_depth, int32_t* d_pre,
+                       int32_t* d_size, hipStream_t s) {
+  if (!ctx || n_trees < 0 || n_total < n_trees || q_total < 0) return ET_EINVAL;
+  if (n_trees == 0) return n_total == 0 && q_total == 0 ? ET_OK : ET_EINVAL;
+  if (!d_parent || !d_offsets || !d_qoffsets || max_tree_nodes < 1) return ET_EINVAL;
+  if (q_total > 0 && (!d_qx || !d_qy || !d_out)) return ET_EINVAL;
+  if (n_total > (int64_t)n_trees * max_tree_nodes) return ET_EINVAL;  // some tree would exceed the bound
+  if (max_tree_nodes > ET_FUSED_MAX_NODES) return ET_ESIZE;
+  return et::small_batch_run(&ctx->impl, d_parent, d_offsets, n_trees, n_total, max_tree_nodes, d_qoffsets, d_qx,
+                             d_qy, q_total, d_out, d_depth, d_pre, d_size, s);
 }
 
 int32_t et_tree_batch_size(const et_tree* tree) { return tree ? tree->batch : -1; }

@@ -68,6 +68,7 @@ struct Ctx {
   int32_t* d_scalars = nullptr;      // small per-call device scalars (root, head, counters)
   int64_t* d_bcount = nullptr;       // bridge count of the last et_bridges
   void* d_fixed = nullptr;           // this device's fixed scratch (et_list_rank_noalloc)
+  uint32_t* d_fused = nullptr;       // work counter pair of the one-launch small-tree batch
   // caching pool: free blocks by size, each with the stream that released it
   struct FreeBlock {
     void* p;
@@ -314,6 +315,12 @@ int list_rank_arena(Ctx* c, void* arena, size_t bytes, const int32_t* succ, int3
                     int32_t nheads, int32_t* rank, hipStream_t s);
 int list_scan_generic(Ctx* c, const int32_t* succ, const int32_t* weights, int32_t len, const int32_t* heads,
                       int32_t nheads, int32_t* rank, int32_t* sum, hipStream_t s);
+// small.hip: build and query many trees of at most 4096 nodes in one launch
+size_t small_batch_lds_bytes(int32_t max_nodes);
+int small_batch_run(Ctx* c, const int32_t* parent, const int64_t* off, int32_t T, int64_t n_total,
+                    int32_t max_nodes, const int64_t* qoff, const int32_t* qx, const int32_t* qy, int64_t q_total,
+                    int32_t* out, int32_t* depth, int32_t* pre, int32_t* size, hipStream_t s);
+
 }  // namespace et
 
 // the public opaque types

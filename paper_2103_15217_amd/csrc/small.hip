@@ -1,0 +1,512 @@
+// Many small trees built and queried in one launch (Section 3.3: a batch of
+// LCA queries answered on trees that are preprocessed once; Section 2 and
+// 3.1 for what each tree goes through).
+//
+// A workgroup of 1024 lanes takes one tree at a time from an atomic counter
+// (the grid is sized to what stays resident, so the launch is persistent)
+// and runs the tree's whole path in LDS, reading only its parent array and
+// its queries from HBM and writing only the answers (and, on request, the
+// node statistics):
+//   1. parents into LDS, checked (one root, ids in range, no self parent);
+//   2. children grouped by parent in ascending id order: a stable LSD radix
+//      sort of the child ids by parent id (7-bit digits, the root's key n
+//      sorts last), ranks within a wavefront by ballots and per-wavefront
+//      digit counters scanned digit-major;
+//   3. successors over the grouped order (next sibling, else back up to the
+//      parent; the first child under its parent's down half-edge), the same
+//      rule as the multi-kernel build;
+//   4. list ranking of the tour: both half-edges of every 2^k-th node (and
+//      the head) start a sublist that one lane walks, recording its length and down
+//      count; pointer jumping over the sublists gives suffix sums, hence each
+//      sublist's offset; a second walk writes every half-edge's rank and
+//      inclusive down count. The tour must reach all 2(n-1) half-edges;
+//   5. depth, preorder, size and inlabel per node from the two ranks of its
+//      half-edges, the head table and parent path labels per inlabel path,
+//      the ascendants one path level at a time from the highest;
+//   6. the tree's queries by the Schieber-Vishkin rule on the LDS tables.
+// Ids are below 2^16 here (a tree has at most 4096 nodes, 8192 half-edges),
+// so the LDS tables hold 16-bit entries.
+#include "et_internal.hpp"
+
+namespace et {
+namespace {
+
+constexpr int kFT = 1024;           // lanes per workgroup
+constexpr int kFW = kFT / 64;       // wavefronts per workgroup
+constexpr int kFMax = 4096;         // nodes per tree at most
+constexpr int kRoundsMax = kFMax / kFT;
+constexpr uint16_t kEnd = 0xffff;   // list end, no node, unused label
+constexpr uint16_t kNoSucc = 0xfffe;  // a half-edge id of the root (not on the tour)
+constexpr int kDigitBits = 7;
+constexpr int kDigits = 1 << kDigitBits;
+constexpr int kSubMax = 1025;       // sublists: at most 1024 regular ones and the head's
+
+__host__ __device__ inline uint32_t al64(uint32_t x) { return (x + 63u) & ~63u; }
+
+// Byte offsets of the LDS regions for trees of at most N nodes (N a
+// multiple of 64). Regions are reused as the phases go:
+//   p   parent u16[N]                                  (whole tree)
+//   rb  successor u16[2N], later head u32[N+1]
+//   rc  radix counters u32[kDigits][kFW], later rank / down u16[2N] each,
+//       later parent path labels u16[N+1]
+//   rd  sort buffers u16[2][N], later inlabel, ascendant, depth u16[N] each
+//   rf  sublists: next, length, down u16[2][kSubMax] each
+//   sc  scalars and wavefront sums
+struct SmallLayout {
+  uint32_t p, rb, rc, rd, rf, sc, total;
+};
+
+__host__ __device__ inline SmallLayout small_layout(uint32_t N) {
+  SmallLayout L;
+  uint32_t at = 0;
+  L.p = at;
+  at += al64(2 * N);
+  L.rb = at;
+  at += al64(4 * N + 4);
+  L.rc = at;
+  at += al64(8 * N > (uint32_t)(kDigits * kFW * 4) ? 8 * N : (uint32_t)(kDigits * kFW * 4));
+  L.rd = at;
+  at += al64(6 * N);
+  L.rf = at;
+  at += al64(12 * kSubMax);
+  L.sc = at;
+  at += 256;
+  L.total = at;
+  return L;
+}
+
+enum { S_ROOT = 0, S_NROOTS, S_BAD, S_HEAD, S_TREE, S_FAIL, S_WSUM = 16 };  // int32 scalar slots
+
+__device__ __forceinline__ int clog2(uint32_t x) { return x <= 1 ? 0 : 32 - __clz((int)(x - 1)); }
+
+// Exclusive scan of a[0..m) in place (m <= 8 * kFT); wsum: kFW + 1 slots.
+__device__ void block_scan_excl(uint32_t* a, int m, int32_t* wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int per = (m + kFT - 1) / kFT;
+  const int lo = min(tid * per, m), hi = min(lo + per, m);
+  uint32_t sum = 0;
+  for (int i = lo; i < hi; ++i) sum += a[i];
+  uint32_t incl = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t v = __shfl_up(incl, d);
+    if (lane >= d) incl += v;
+  }
+  if (lane == 63) wsum[w] = (int32_t)incl;
+  __syncthreads();
+  if (tid < 64) {
+    const uint32_t v = tid < kFW ? (uint32_t)wsum[tid] : 0u;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < kFW; d <<= 1) {
+      const uint32_t y = __shfl_up(x, d);
+      if (lane >= d) x += y;
+    }
+    if (tid < kFW) wsum[tid] = (int32_t)(x - v);
+  }
+  __syncthreads();
+  uint32_t run = (uint32_t)wsum[w] + incl - sum;
+  for (int i = lo; i < hi; ++i) {
+    const uint32_t x = a[i];
+    a[i] = run;
+    run += x;
+  }
+  __syncthreads();
+}
+
+// lanes of the wavefront whose digit equals this lane's (among valid lanes)
+__device__ __forceinline__ uint64_t match_digit(bool valid, uint32_t d) {
+  uint64_t peers = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < kDigitBits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+__device__ __forceinline__ uint16_t root_key(uint16_t p, uint32_t n) { return p == kEnd ? (uint16_t)n : p; }
+
+__global__ __launch_bounds__(kFT) void k_small_batch(
+    const int32_t* __restrict__ parent, const int64_t* __restrict__ off, int32_t T, int64_t n_total, uint32_t N,
+    int32_t nmax, const int64_t* __restrict__ qoff, int64_t q_total, const int32_t* __restrict__ qx,
+    const int32_t* __restrict__ qy, int32_t* __restrict__ out, int32_t* __restrict__ depth_out,
+    int32_t* __restrict__ pre_out, int32_t* __restrict__ size_out, uint32_t* __restrict__ counters,
+    uint32_t* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const SmallLayout L = small_layout(N);
+  uint16_t* P = reinterpret_cast<uint16_t*>(lds + L.p);
+  uint16_t* SUCC = reinterpret_cast<uint16_t*>(lds + L.rb);
+  uint32_t* HEAD = reinterpret_cast<uint32_t*>(lds + L.rb);
+  uint32_t* CNT = reinterpret_cast<uint32_t*>(lds + L.rc);
+  uint16_t* RK = reinterpret_cast<uint16_t*>(lds + L.rc);
+  uint16_t* DN = RK + 2 * N;
+  uint16_t* PLAB = reinterpret_cast<uint16_t*>(lds + L.rc);
+  uint16_t* ORD0 = reinterpret_cast<uint16_t*>(lds + L.rd);
+  uint16_t* ORD1 = ORD0 + N;
+  uint16_t* INL = reinterpret_cast<uint16_t*>(lds + L.rd);
+  uint16_t* ASC = INL + N;
+  uint16_t* DEP = ASC + N;
+  // sublist next / length / down count, two buffers each (pointer jumping)
+  uint16_t* SUB = reinterpret_cast<uint16_t*>(lds + L.rf);
+#define NX(b) (SUB + (b) * kSubMax)
+#define LN(b) (SUB + (2 + (b)) * kSubMax)
+#define DS(b) (SUB + (4 + (b)) * kSubMax)
+  int32_t* SC = reinterpret_cast<int32_t*>(lds + L.sc);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+
+  if (blockIdx.x == 0 && tid == 0) {
+    if (off[0] != 0 || off[T] != n_total) flag(status, ST_BAD_PARENT);
+    if (qoff[0] != 0 || qoff[T] != q_total) flag(status, ST_BAD_QUERY);
+  }
+  for (;;) {
+    if (tid == 0) SC[S_TREE] = (int32_t)atomicAdd(&counters[0], 1u);
+    __syncthreads();
+    const int32_t t = SC[S_TREE];
+    if (t >= T) break;
+    const int64_t base = off[t], nt = off[t + 1] - base;
+    const int64_t qb = qoff[t], nq = qoff[t + 1] - qb;
+    const bool q_ok = qb >= 0 && nq >= 0 && qb + nq <= q_total;
+    if (!q_ok && tid == 0) flag(status, ST_BAD_QUERY);
+    const bool tree_ok = base >= 0 && nt >= 1 && nt <= (int64_t)nmax && base + nt <= n_total;
+    if (!tree_ok && tid == 0) flag(status, ST_BAD_PARENT);
+    const uint32_t n = tree_ok ? (uint32_t)nt : 0u;
+
+    // 1. parents
+    if (tid == 0) {
+      SC[S_NROOTS] = 0;
+      SC[S_BAD] = 0;
+      SC[S_FAIL] = tree_ok ? 0 : 1;
+      SC[S_HEAD] = -1;
+    }
+    __syncthreads();
+    for (uint32_t c = tid; c < n; c += kFT) {
+      const int32_t p = parent[base + c];
+      if (p == -1) {
+        P[c] = kEnd;
+        atomicAdd(&SC[S_NROOTS], 1);
+        SC[S_ROOT] = (int32_t)c;
+      } else if (p >= 0 && (uint32_t)p < n && (uint32_t)p != c) {
+        P[c] = (uint16_t)p;
+      } else {
+        P[c] = 0;
+        SC[S_BAD] = 1;
+      }
+    }
+    __syncthreads();
+    if (tree_ok && (SC[S_NROOTS] != 1 || SC[S_BAD])) {
+      if (tid == 0) {
+        flag(status, SC[S_BAD] ? ST_BAD_PARENT : ST_ROOTS);
+        SC[S_FAIL] = 1;
+      }
+    }
+    __syncthreads();
+    const uint32_t root = (uint32_t)SC[S_ROOT];
+    const uint32_t E = 2 * n;
+
+    if (!SC[S_FAIL] && n > 1) {
+      // 2. stable radix sort of child ids by parent id
+      for (uint32_t i = tid; i < n; i += kFT) ORD0[i] = (uint16_t)i;
+      uint16_t* src = ORD0;
+      uint16_t* dst = ORD1;
+      const int kbits = 32 - __clz((int)n);   // bits of the largest key (n, the root's)
+      const uint32_t seg = ((n + kFT - 1) / kFT) * 64;  // elements per wavefront, whole rounds
+      const int rounds = (int)(seg / 64);
+      const uint64_t below = lanemask_lt();
+      for (int sh = 0; sh < kbits; sh += kDigitBits) {
+        for (int i = tid; i < kDigits * kFW; i += kFT) CNT[i] = 0;
+        __syncthreads();
+        uint32_t lr[kRoundsMax], dg[kRoundsMax];
+        uint16_t vv[kRoundsMax];
+#pragma unroll
+        for (int r = 0; r < kRoundsMax; ++r) {
+          if (r >= rounds) break;
+          const uint32_t idx = w * seg + r * 64 + lane;
+          const bool valid = idx < n;
+          const uint16_t v = valid ? src[idx] : (uint16_t)0;
+          const uint32_t d = valid ? ((uint32_t)root_key(P[v], n) >> sh) & (kDigits - 1) : 0u;
+          const uint64_t peers = match_digit(valid, d);
+          uint32_t old = 0;
+          if (valid) old = CNT[d * kFW + w];
+          if (valid && lane == __ffsll((unsigned long long)peers) - 1)
+            CNT[d * kFW + w] = old + (uint32_t)__popcll(peers);
+          lr[r] = old + (uint32_t)__popcll(peers & below);
+          dg[r] = d;
+          vv[r] = v;
+        }
+        __syncthreads();
+        block_scan_excl(CNT, kDigits * kFW, SC + S_WSUM);
+#pragma unroll
+        for (int r = 0; r < kRoundsMax; ++r) {
+          if (r >= rounds) break;
+          const uint32_t idx = w * seg + r * 64 + lane;
+          if (idx < n) dst[CNT[dg[r] * kFW + w] + lr[r]] = vv[r];
+        }
+        __syncthreads();
+        uint16_t* tmp = src;
+        src = dst;
+        dst = tmp;
+      }
+      const uint16_t* ord = src;
+
+      // 3. successors; the root sorts last (position n-1)
+      for (uint32_t e = tid; e < E; e += kFT)
+        SUCC[e] = ((e >> 1) == root) ? kNoSucc : ((e & 1u) ? kEnd : (uint16_t)(e + 1));
+      __syncthreads();
+      for (uint32_t k = tid; k + 1 < n; k += kFT) {
+        const uint32_t c = ord[k];
+        const uint16_t p = P[c];
+        uint16_t nxt;
+        if (k + 2 < n && P[ord[k + 1]] == p) nxt = (uint16_t)(2 * ord[k + 1]);
+        else nxt = (p == root) ? kEnd : (uint16_t)(2 * p + 1);
+        SUCC[2 * c + 1] = nxt;
+        if (k == 0 || P[ord[k - 1]] != p) {
+          if (p == root) SC[S_HEAD] = (int32_t)(2 * c);
+          else SUCC[2 * p] = (uint16_t)(2 * c);
+        }
+      }
+      __syncthreads();
+      if (SC[S_HEAD] < 0) {  // the root has no child: the other nodes form cycles
+        if (tid == 0) {
+          flag(status, ST_UNREACHED);
+          SC[S_FAIL] = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (!SC[S_FAIL] && n > 1) {
+      // 4. sublists: both half-edges of every 2^m-th node id start one (so
+      // the runs down into and up out of a subtree both meet splitters),
+      // and so does the head; at most 1024 regular ones
+      const int m = max(0, clog2(n) - 9);
+      const uint32_t M = (1u << m) - 1u;
+      const uint32_t Sreg = 2 * ((n + M) >> m);
+      const uint32_t S = Sreg + 1;
+      const uint32_t head = (uint32_t)SC[S_HEAD];
+      const uint32_t hsub = ((head >> 1) & M) ? Sreg : (((head >> 1) >> m) << 1);
+      for (uint32_t s = tid; s < S; s += kFT) {
+        const uint32_t e0 = (s == Sreg) ? head : ((((s >> 1) << m) << 1) | (s & 1u));
+        const bool valid = (s == Sreg) ? ((head >> 1) & M) != 0 : (e0 < E && SUCC[e0] != kNoSucc);
+        uint32_t len = 0, dn = 0, nxs = kEnd;
+        if (valid) {
+          uint32_t e = e0;
+          for (;;) {
+            ++len;
+            dn += !(e & 1u);
+            const uint32_t nx = SUCC[e];
+            if (nx == kEnd) break;
+            if (nx >= E || len >= E) {
+              SC[S_BAD] = 1;
+              break;
+            }
+            if (!((nx >> 1) & M)) {
+              nxs = (((nx >> 1) >> m) << 1) | (nx & 1u);
+              break;
+            }
+            e = nx;
+          }
+        }
+        NX(0)[s] = (uint16_t)nxs;
+        LN(0)[s] = (uint16_t)len;
+        DS(0)[s] = (uint16_t)dn;
+      }
+      __syncthreads();
+      // suffix sums along the sublist list by pointer jumping
+      int cur = 0;
+      const int jumps = clog2(S) + 1;
+      for (int it = 0; it < jumps; ++it) {
+        for (uint32_t s = tid; s < S; s += kFT) {
+          const uint16_t nx = NX(cur)[s];
+          if (nx != kEnd && nx < S) {
+            NX(cur ^ 1)[s] = NX(cur)[nx];
+            LN(cur ^ 1)[s] = (uint16_t)(LN(cur)[s] + LN(cur)[nx]);
+            DS(cur ^ 1)[s] = (uint16_t)(DS(cur)[s] + DS(cur)[nx]);
+          } else {
+            NX(cur ^ 1)[s] = kEnd;
+            LN(cur ^ 1)[s] = LN(cur)[s];
+            DS(cur ^ 1)[s] = DS(cur)[s];
+          }
+        }
+        __syncthreads();
+        cur ^= 1;
+      }
+      const uint32_t total = LN(cur)[hsub], total_dn = DS(cur)[hsub];
+      if (tid == 0 && (SC[S_BAD] || total != E - 2)) {
+        flag(status, ST_UNREACHED);
+        SC[S_FAIL] = 1;
+      }
+      __syncthreads();
+      if (!SC[S_FAIL]) {
+        // second walk: rank and inclusive down count of every half-edge
+        for (uint32_t s = tid; s < S; s += kFT) {
+          const uint32_t e0 = (s == Sreg) ? head : ((((s >> 1) << m) << 1) | (s & 1u));
+          const bool valid = (s == Sreg) ? ((head >> 1) & M) != 0 : (e0 < E && SUCC[e0] != kNoSucc);
+          if (!valid) continue;
+          uint32_t r = total - LN(cur)[s], d = total_dn - DS(cur)[s];
+          uint32_t e = e0;
+          for (uint32_t steps = 0; steps < E; ++steps) {
+            d += !(e & 1u);
+            RK[e] = (uint16_t)r;
+            DN[e] = (uint16_t)d;
+            ++r;
+            const uint32_t nx = SUCC[e];
+            if (nx >= E || !((nx >> 1) & M)) break;
+            e = nx;
+          }
+        }
+      }
+      __syncthreads();
+    }
+
+    if (!SC[S_FAIL]) {
+      // 5. node statistics and inlabels (RD's sort buffers are dead)
+      for (uint32_t c = tid; c < n; c += kFT) {
+        int32_t dep, pre, size;
+        if (c == root) {
+          dep = 0;
+          pre = 0;
+          size = (int32_t)n;
+        } else {
+          const int32_t r0 = RK[2 * c], d0 = DN[2 * c], r1 = RK[2 * c + 1];
+          pre = d0;
+          dep = 2 * d0 - r0 - 1;
+          size = (r1 - r0 + 1) >> 1;
+        }
+        INL[c] = (uint16_t)inlabel_of(pre, size);
+        DEP[c] = (uint16_t)dep;
+        if (depth_out) depth_out[base + c] = dep;
+        if (pre_out) pre_out[base + c] = pre;
+        if (size_out) size_out[base + c] = size;
+      }
+      __syncthreads();  // RK / DN dead from here: PLAB takes RC
+      for (uint32_t I = tid; I <= n; I += kFT) PLAB[I] = kEnd;
+      __syncthreads();
+      // path tops: head[label] = {parent of the top, its depth}, plab = the parent's label
+      for (uint32_t v = tid; v < n; v += kFT) {
+        const uint16_t inl = INL[v];
+        const uint16_t p = P[v];
+        const bool is_root = v == root;
+        const uint16_t pinl = is_root ? (uint16_t)0 : INL[p];
+        if (is_root || pinl != inl) {
+          if (inl >= 1 && inl <= n) {
+            HEAD[inl] = (uint32_t)(is_root ? kEnd : p) | ((uint32_t)(uint16_t)(DEP[v] - 1) << 16);
+            PLAB[inl] = pinl;
+          } else {
+            SC[S_BAD] = 1;
+          }
+        }
+      }
+      __syncthreads();
+      // ascendants by label, highest level first
+      for (int lv = 31 - __clz((int)n); lv >= 0; --lv) {
+        for (uint32_t k = tid; ((2 * k + 1) << lv) <= n; k += kFT) {
+          const uint32_t I = (2 * k + 1) << lv;
+          const uint16_t pl = PLAB[I];
+          if (pl == kEnd) continue;
+          uint32_t up = 0;
+          if (pl != 0) {
+            if (pl <= n && (__ffs((int)pl) - 1) > lv) up = PLAB[pl];
+            else SC[S_BAD] = 1;
+          }
+          PLAB[I] = (uint16_t)(up | (1u << lv));
+        }
+        __syncthreads();
+      }
+      for (uint32_t v = tid; v < n; v += kFT) ASC[v] = PLAB[min((uint32_t)INL[v], n)];
+      __syncthreads();
+      if (tid == 0 && SC[S_BAD]) flag(status, ST_BAD_INDEX);
+    }
+
+    // 6. queries
+    if (q_ok) {
+      const bool fail = SC[S_FAIL] != 0;
+      for (int64_t i = qb + tid; i < qb + nq; i += kFT) {
+        const int32_t x = qx[i], y = qy[i];
+        int32_t r = -1;
+        if ((uint32_t)x >= n || (uint32_t)y >= n) {
+          if (!fail) flag(status, ST_BAD_QUERY);
+        } else if (!fail) {
+          const uint32_t a = INL[x], b = INL[y];
+          const int32_t dx = DEP[x], dy = DEP[y];
+          if (a == b) {
+            r = dx <= dy ? x : y;
+          } else {
+            const int ha = __ffs((int)a) - 1, hb = __ffs((int)b) - 1;
+            const int i0 = max(max(ha, hb), 31 - __clz((int)(a ^ b)));
+            const uint32_t ax = ASC[x], ay = ASC[y];
+            const uint32_t common = ax & ay & (~0u << i0);
+            if (common == 0u) {
+              flag(status, ST_BAD_INDEX);
+            } else {
+              const int j = __ffs((int)common) - 1;
+              const uint32_t low = (1u << j) - 1u;
+              int32_t xv = x, xd = dx, yv = y, yd = dy;
+              if (ha != j) {
+                const int k = 31 - __clz((int)(ax & low));
+                const uint32_t wl = ((a >> (k + 1)) << (k + 1)) | (1u << k);
+                const uint32_t h = HEAD[min(wl, n)];
+                xv = (h & 0xffffu) == kEnd ? -1 : (int32_t)(h & 0xffffu);
+                xd = (int32_t)(int16_t)(h >> 16);
+              }
+              if (hb != j) {
+                const int k = 31 - __clz((int)(ay & low));
+                const uint32_t wl = ((b >> (k + 1)) << (k + 1)) | (1u << k);
+                const uint32_t h = HEAD[min(wl, n)];
+                yv = (h & 0xffffu) == kEnd ? -1 : (int32_t)(h & 0xffffu);
+                yd = (int32_t)(int16_t)(h >> 16);
+              }
+              r = xd <= yd ? xv : yv;
+            }
+          }
+        }
+        out[i] = r;
+      }
+    }
+    __syncthreads();  // the tables and SC[S_TREE] are rewritten by the next tree
+  }
+  // the last workgroup out resets the counters for the next launch
+  if (tid == 0) {
+    __threadfence();
+    if (atomicAdd(&counters[1], 1u) == gridDim.x - 1) {
+      atomicExch(&counters[0], 0u);
+      atomicExch(&counters[1], 0u);
+    }
+  }
+#undef NX
+#undef LN
+#undef DS
+}
+
+}  // namespace
+
+size_t small_batch_lds_bytes(int32_t max_nodes) {
+  const uint32_t N = al64((uint32_t)std::max(max_nodes, 1));
+  return small_layout(N).total;
+}
+
+int small_batch_run(Ctx* c, const int32_t* parent, const int64_t* off, int32_t T, int64_t n_total,
+                    int32_t max_nodes, const int64_t* qoff, const int32_t* qx, const int32_t* qy, int64_t q_total,
+                    int32_t* out, int32_t* depth, int32_t* pre, int32_t* size, hipStream_t s) {
+  if (T == 0) return ET_OK;
+  if (max_nodes < 1 || max_nodes > kFMax) return ET_ESIZE;
+  const uint32_t N = al64((uint32_t)max_nodes);
+  const uint32_t lds = small_layout(N).total;
+  int dev = 0, max_lds = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ET_EHIP;
+  if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return ET_EHIP;
+  if ((int)lds > max_lds) return ET_ESIZE;
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_small_batch), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds) != hipSuccess)
+    return ET_EHIP;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_small_batch, kFT, lds) != hipSuccess) return ET_EHIP;
+  const int grid = (int)std::min<int64_t>(T, (int64_t)std::max(per_cu, 1) * cus);
+  ET_PROF(c, s, "k_small_batch");
+  hipLaunchKernelGGL(k_small_batch, dim3(grid), dim3(kFT), lds, s, parent, off, T, n_total, N, max_nodes, qoff, q_total, qx,
+                     qy, out, depth, pre, size, c->d_fused, c->d_status);
+  return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+}
+
+}  // namespace et

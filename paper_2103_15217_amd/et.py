@@ -36,6 +36,7 @@ _SIG = {
     "et_list_rank": ([_P, _P, _i32, _P, _i32, _P, _P], ctypes.c_int),
     "et_list_scan": ([_P, _P, _P, _i32, _P, _i32, _P, _P, _P], ctypes.c_int),
     "et_list_rank_noalloc": ([_P, _P, _i32, _P, _i32, _P, _P], ctypes.c_int),
+    "et_lca_batch_fused": ([_P, _P, _P, _i32, _i64, _i32, _P, _P, _P, _i64, _P, _P, _P, _P, _P], ctypes.c_int),
     "et_tree_build": ([_P, _P, _i32, _P, ctypes.POINTER(_P)], ctypes.c_int),
     "et_tree_size": ([_P], _i32),
     "et_tree_batch_size": ([_P], _i32),
@@ -66,6 +67,7 @@ for _name, (_args, _res) in _SIG.items():
     _fn.restype = _res
 
 ET_OK, ET_EINVAL, ET_ENOMEM, ET_EHIP, ET_EINPUT, ET_ESIZE = 0, -1, -2, -3, -4, -5
+FUSED_MAX_NODES = 4096  # trees of et_lca_batch_fused (et.h)
 # limits of et_list_rank_noalloc (et.h)
 NOALLOC_MAX_LEN = 1 << 20
 NOALLOC_MAX_HEADS = 1 << 16
@@ -449,6 +451,43 @@ def et_lca_batch(tree, qtree, qx, qy, out=None):
     return tree.lca_batch(qtree, qx, qy, out)
 
 
+def et_lca_batch_fused(parent, offsets, qoffsets, qx, qy, max_tree_nodes, out=None, stats=False, ctx=None):
+    """Build many small trees (at most ``FUSED_MAX_NODES`` nodes each, at most
+    ``max_tree_nodes``) and answer their queries in one kernel launch.
+    ``parent`` / ``offsets`` as for :func:`et_tree_build_batch`; the queries
+    come grouped by tree: tree t's are ``[qoffsets[t], qoffsets[t+1])`` of
+    ``qx`` / ``qy`` (local ids). Returns the answers (local ids), and with
+    ``stats`` also per-node depth, preorder and subtree size within each tree."""
+    ctx = ctx or default_context()
+    parent = _dev(parent, torch.int32, "parent")
+    offsets = _dev(offsets, torch.int64, "offsets")
+    qoffsets = _dev(qoffsets, torch.int64, "qoffsets")
+    qx = _dev(qx, torch.int32, "qx")
+    qy = _dev(qy, torch.int32, "qy")
+    T = _i32(offsets.numel() - 1, "number of trees")
+    if qoffsets.numel() != offsets.numel():
+        raise ValueError("qoffsets must have one entry per tree plus one")
+    if qx.numel() != qy.numel():
+        raise ValueError("qx and qy differ in length")
+    q = qx.numel()
+    if out is None:
+        out = torch.empty(q, dtype=torch.int32, device=qx.device)
+    else:
+        out = _dev(out, torch.int32, "out")
+        if out.numel() < q:
+            raise ValueError("out is shorter than the queries")
+    depth = pre = size = None
+    if stats:
+        depth, pre, size = (torch.empty(parent.numel(), dtype=torch.int32, device=parent.device) for _ in range(3))
+    _check(_lib.et_lca_batch_fused(ctx.handle, _ptr(parent), _ptr(offsets), T, parent.numel(),
+                                   _i32(max_tree_nodes, "max_tree_nodes"), _ptr(qoffsets), _ptr(qx), _ptr(qy), q,
+                                   _ptr(out), _ptr(depth), _ptr(pre), _ptr(size), _stream()),
+           "et_lca_batch_fused")
+    if stats:
+        return out, {"depth": depth, "pre": pre, "size": size}
+    return out
+
+
 # ------------------------------------------------------------------ bridges
 
 def et_bridges(row_ptr, col, mask=None, ctx=None, count=True):
@@ -601,6 +640,32 @@ class BatchGraph:
         if self.tree is not None:
             self.tree.free()
             self.tree = None
+
+
+class FusedBatchGraph:
+    """The one-launch small-tree batch (et_lca_batch_fused) captured in a HIP
+    graph: each replay is one kernel node. It allocates nothing and writes
+    only ``out``; its work counter resets itself at the end of every launch,
+    so replays need no set-up node. The context must not run another
+    et_lca_batch_fused call while a replay is in flight."""
+
+    def __init__(self, parent, offsets, qoffsets, qx, qy, max_tree_nodes, ctx=None):
+        self.ctx = ctx or Context()
+        self.inputs = (parent, offsets, qoffsets, qx, qy)
+        self.out = torch.empty_like(qx)
+        et_lca_batch_fused(parent, offsets, qoffsets, qx, qy, max_tree_nodes, out=self.out, ctx=self.ctx)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            et_lca_batch_fused(parent, offsets, qoffsets, qx, qy, max_tree_nodes, out=self.out, ctx=self.ctx)
+
+    def replay(self):
+        self.graph.replay()
+        return self.out
+
+    def close(self):
+        torch.cuda.synchronize()
+        self.graph = None
 
 
 class BridgesBatchGraph:
