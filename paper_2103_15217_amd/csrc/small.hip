@@ -40,6 +40,7 @@ constexpr uint16_t kNoSucc = 0xfffe;  // a half-edge id of the root (not on the 
 constexpr int kDigitBits = 7;
 constexpr int kDigits = 1 << kDigitBits;
 constexpr int kSubMax = 1025;       // sublists: at most 1024 regular ones and the head's
+constexpr int kQPer = 4;            // queries a lane loads before answering them
 
 __host__ __device__ inline uint32_t al64(uint32_t x) { return (x + 63u) & ~63u; }
 
@@ -181,8 +182,17 @@ __global__ __launch_bounds__(kFT) void k_small_batch(
       SC[S_HEAD] = -1;
     }
     __syncthreads();
-    for (uint32_t c = tid; c < n; c += kFT) {
-      const int32_t p = parent[base + c];
+    int32_t praw[kRoundsMax];  // all of a lane's parent loads first
+#pragma unroll
+    for (int r = 0; r < kRoundsMax; ++r) {
+      const uint32_t c = tid + r * kFT;
+      praw[r] = c < n ? parent[base + c] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kRoundsMax; ++r) {
+      const uint32_t c = tid + r * kFT;
+      if (c >= n) break;
+      const int32_t p = praw[r];
       if (p == -1) {
         P[c] = kEnd;
         atomicAdd(&SC[S_NROOTS], 1);
@@ -421,46 +431,58 @@ __global__ __launch_bounds__(kFT) void k_small_batch(
     // 6. queries
     if (q_ok) {
       const bool fail = SC[S_FAIL] != 0;
-      for (int64_t i = qb + tid; i < qb + nq; i += kFT) {
-        const int32_t x = qx[i], y = qy[i];
-        int32_t r = -1;
-        if ((uint32_t)x >= n || (uint32_t)y >= n) {
-          if (!fail) flag(status, ST_BAD_QUERY);
-        } else if (!fail) {
-          const uint32_t a = INL[x], b = INL[y];
-          const int32_t dx = DEP[x], dy = DEP[y];
-          if (a == b) {
-            r = dx <= dy ? x : y;
-          } else {
-            const int ha = __ffs((int)a) - 1, hb = __ffs((int)b) - 1;
-            const int i0 = max(max(ha, hb), 31 - __clz((int)(a ^ b)));
-            const uint32_t ax = ASC[x], ay = ASC[y];
-            const uint32_t common = ax & ay & (~0u << i0);
-            if (common == 0u) {
-              flag(status, ST_BAD_INDEX);
+      for (int64_t i0 = qb; i0 < qb + nq; i0 += (int64_t)kQPer * kFT) {
+        int32_t xs[kQPer], ys[kQPer];  // a lane's query loads first, then the lookups
+#pragma unroll
+        for (int j = 0; j < kQPer; ++j) {
+          const int64_t i = i0 + (int64_t)j * kFT + tid;
+          xs[j] = i < qb + nq ? qx[i] : 0;
+          ys[j] = i < qb + nq ? qy[i] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kQPer; ++j) {
+          const int64_t i = i0 + (int64_t)j * kFT + tid;
+          if (i >= qb + nq) break;
+          const int32_t x = xs[j], y = ys[j];
+          int32_t r = -1;
+          if ((uint32_t)x >= n || (uint32_t)y >= n) {
+            if (!fail) flag(status, ST_BAD_QUERY);
+          } else if (!fail) {
+            const uint32_t a = INL[x], b = INL[y];
+            const int32_t dx = DEP[x], dy = DEP[y];
+            if (a == b) {
+              r = dx <= dy ? x : y;
             } else {
-              const int j = __ffs((int)common) - 1;
-              const uint32_t low = (1u << j) - 1u;
-              int32_t xv = x, xd = dx, yv = y, yd = dy;
-              if (ha != j) {
-                const int k = 31 - __clz((int)(ax & low));
-                const uint32_t wl = ((a >> (k + 1)) << (k + 1)) | (1u << k);
-                const uint32_t h = HEAD[min(wl, n)];
-                xv = (h & 0xffffu) == kEnd ? -1 : (int32_t)(h & 0xffffu);
-                xd = (int32_t)(int16_t)(h >> 16);
+              const int ha = __ffs((int)a) - 1, hb = __ffs((int)b) - 1;
+              const int lb = max(max(ha, hb), 31 - __clz((int)(a ^ b)));  // b-level of the labels' LCA
+              const uint32_t ax = ASC[x], ay = ASC[y];
+              const uint32_t common = ax & ay & (~0u << lb);
+              if (common == 0u) {
+                flag(status, ST_BAD_INDEX);
+              } else {
+                const int jl = __ffs((int)common) - 1;
+                const uint32_t low = (1u << jl) - 1u;
+                int32_t xv = x, xd = dx, yv = y, yd = dy;
+                if (ha != jl) {
+                  const int k = 31 - __clz((int)(ax & low));
+                  const uint32_t wl = ((a >> (k + 1)) << (k + 1)) | (1u << k);
+                  const uint32_t h = HEAD[min(wl, n)];
+                  xv = (h & 0xffffu) == kEnd ? -1 : (int32_t)(h & 0xffffu);
+                  xd = (int32_t)(int16_t)(h >> 16);
+                }
+                if (hb != jl) {
+                  const int k = 31 - __clz((int)(ay & low));
+                  const uint32_t wl = ((b >> (k + 1)) << (k + 1)) | (1u << k);
+                  const uint32_t h = HEAD[min(wl, n)];
+                  yv = (h & 0xffffu) == kEnd ? -1 : (int32_t)(h & 0xffffu);
+                  yd = (int32_t)(int16_t)(h >> 16);
+                }
+                r = xd <= yd ? xv : yv;
               }
-              if (hb != j) {
-                const int k = 31 - __clz((int)(ay & low));
-                const uint32_t wl = ((b >> (k + 1)) << (k + 1)) | (1u << k);
-                const uint32_t h = HEAD[min(wl, n)];
-                yv = (h & 0xffffu) == kEnd ? -1 : (int32_t)(h & 0xffffu);
-                yd = (int32_t)(int16_t)(h >> 16);
-              }
-              r = xd <= yd ? xv : yv;
             }
           }
+          out[i] = r;
         }
-        out[i] = r;
       }
     }
     __syncthreads();  // the tables and SC[S_TREE] are rewritten by the next tree
