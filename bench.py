@@ -828,10 +828,11 @@ def serving(args, dev):
 
 def kernel_roofline(kernel, avg_ms, launches, work, params):
     """Roofline figures of one kernel from its average launch time: the
-    algorithmic bytes per launch over that time against 8 TB/s, the
-    counter-measured HBM bytes (when a current summary exists) against 8 TB/s
-    and against the measured copy rate, and its units per second against
-    the measured random-access ceiling of its access pattern."""
+    algorithmic bytes per launch over that time against 8 TB/s; the bytes
+    the L2 actually requested from memory per launch (request-size counters,
+    when a current summary exists) against 8 TB/s and against the measured
+    read-only and copy stream rates; and its units per second against the
+    measured random-access ceiling of its access pattern."""
     r = {"kernel": kernel, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
          "traffic": measured_traffic(kernel, params), "avg_launch_ms": avg_ms, "launches_per_step": launches}
     if kernel not in ALG_BYTES:
@@ -842,14 +843,17 @@ def kernel_roofline(kernel, avg_ms, launches, work, params):
               "units_per_launch": upl})
     r["frac"] = r["achieved"] / HBM_PEAK_GBS
     if r["traffic"]:
-        # what the memory system actually moves: every random access costs a whole line
+        # what the memory side serves: a random read costs a whole 128-byte line,
+        # a random store a 32-byte write (HBM and last-level-cache hits together)
         rate = r["traffic"] / (avg_ms * 1e-3) / 1e9
         r["traffic_GBps"] = rate
         r["traffic_frac"] = rate / HBM_PEAK_GBS
-        copy = probe_ceiling("copy", 27, "GB_per_s")        # measured stream-copy peak
-        if copy:
-            r["copy_GBps"] = copy
-            r["traffic_frac_of_copy"] = rate / copy
+        r["traffic_over_alg"] = r["traffic"] / (bpu * upl)
+        for name in ("read", "copy"):                      # measured stream rates (probe/ceiling.hip)
+            ceil = probe_ceiling(name, 27, "GB_per_s")
+            if ceil:
+                r[f"{name}_stream_GBps"] = ceil
+                r[f"traffic_frac_of_{name}_stream"] = rate / ceil
     # dependent walks against chase + store, the rest against independent gathers
     ceil = probe_ceiling("chase+w8" if kernel.startswith("k_walk1") else "gather")
     if ceil:
@@ -860,9 +864,9 @@ def kernel_roofline(kernel, avg_ms, launches, work, params):
 
 
 def probe_ceiling(name, log2n=25, field="elements_per_s"):
-    """One figure of a probe of probe/ceiling.hip (copy, gather, dependent
-    chase, chase with an 8-byte store) from its committed summary
-    (profiles/random_access_ceiling.txt)."""
+    """One figure of a probe of probe/ceiling.hip (copy, read, gather,
+    scatter, dependent chase, chase with an 8-byte store) from its committed
+    summary (profiles/random_access_ceiling.txt)."""
     path = os.path.join(ROOT, "profiles", "random_access_ceiling.txt")
     if not os.path.exists(path):
         return None
@@ -875,9 +879,11 @@ def probe_ceiling(name, log2n=25, field="elements_per_s"):
 
 
 def measured_traffic(kernel, params=None):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when none was taken, the kernel's source changed since,
-    or it was taken with other launch parameters."""
+    """Bytes per launch of `kernel` that the L2 requested from memory (reads
+    in 32-, 64- and 128-byte requests, writes in 32- and 64-byte requests,
+    from rocprofv3's TCC_EA0 request counters), from the committed summary;
+    None when none was taken, the kernel's source changed since, or it was
+    taken with other launch parameters."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_2e24.json")
     if not os.path.exists(path):
@@ -890,7 +896,7 @@ def measured_traffic(kernel, params=None):
         return None
     if rec.get("launch_params") != params:
         return None
-    return rec["fetch_kib"] * 1024 * rec["fetch_factor"] + rec["write_kib"] * 1024 * rec["write_factor"]
+    return rec["read_bytes"] + rec["write_bytes"]
 
 
 def cpu_baseline(parent, qx, qy, rp, col, ginfo, et, d, ctx, d_parent, d_qx, d_qy, d_rp, d_col):

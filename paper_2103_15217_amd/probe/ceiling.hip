@@ -8,6 +8,8 @@
 //
 // Over an int32 array of 2^log2n elements it times, best of 5 launches:
 //   copy        streaming copy of 8 B per element (reference bandwidth)
+//   read        streaming read of the same 8 B per element: the read-only
+//               bandwidth
 //   gather      out[i] = a[idx[i]], idx a random permutation (independent random reads)
 //   gather8     the same with 8-byte elements (an array of 8 B x 2^log2n)
 //   gather16    the same with 16-byte elements (the query kernel's record loads)
@@ -44,6 +46,15 @@ constexpr int kB = 256;
 __global__ void k_copy(const int4* __restrict__ a, int4* __restrict__ b, int64_t n4) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n4) b[i] = a[i];
+}
+
+__global__ void k_read(const int4* __restrict__ a, int32_t* __restrict__ out, int64_t n4) {
+  // one 16-byte load per lane; the store is taken only for a value the
+  // array never holds, so the kernel reads and (in effect) writes nothing
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n4) return;
+  const int4 v = a[i];
+  if ((v.x ^ v.y ^ v.z ^ v.w) == 0x7fffffff) out[i >> 6] = 1;
 }
 
 __global__ void k_gather(const int32_t* __restrict__ a, const int32_t* __restrict__ idx, int32_t* __restrict__ out,
@@ -149,6 +160,8 @@ int main(int argc, char** argv) {
   const unsigned g = (unsigned)((n + kB - 1) / kB);
   const unsigned gl = (unsigned)((lanes + kB - 1) / kB);
   measure("copy", 16.0, [&] { hipLaunchKernelGGL(k_copy, dim3((unsigned)((n / 2 + kB - 1) / kB)), dim3(kB), 0, 0, d_c0, d_c1, n / 2); });
+  // the copy's source, read only (a store would go to d_out[i / 64] < n)
+  measure("read", 8.0, [&] { hipLaunchKernelGGL(k_read, dim3((unsigned)((n / 2 + kB - 1) / kB)), dim3(kB), 0, 0, d_c0, d_out, n / 2); });
   measure("gather", 12.0, [&] { hipLaunchKernelGGL(k_gather, dim3(g), dim3(kB), 0, 0, d_a, d_idx, d_out, n); });
   measure("gather8", 16.0, [&] {
     hipLaunchKernelGGL(k_gather_w<uint64_t>, dim3(g), dim3(kB), 0, 0, reinterpret_cast<const uint64_t*>(d_c0), d_idx,

@@ -24,8 +24,12 @@ def test_traffic_record_needs_matching_source_and_parameters():
     for kernel, r in rec.items():
         t = bench.measured_traffic(kernel, r["launch_params"])
         current = hashlib.sha256(open(os.path.join(ROOT, r["source"]), "rb").read()).hexdigest() == r["sha256"]
-        want = r["fetch_kib"] * 1024 * r["fetch_factor"] + r["write_kib"] * 1024 * r["write_factor"]
+        want = r["read_bytes"] + r["write_bytes"]
         assert t == (want if current else None), kernel
+        # the bytes are the request counts times the request sizes
+        q = r["requests"]
+        assert r["read_bytes"] == 32 * q["rd32"] + 64 * q["rd64"] + 128 * q["rd128"], kernel
+        assert r["write_bytes"] == 32 * (q["wr"] - q["wr64"]) + 64 * q["wr64"], kernel
         other = dict(r["launch_params"] or {}, lr_per_wave1=12345)
         assert bench.measured_traffic(kernel, other) is None, kernel
     assert bench.measured_traffic("k_not_profiled", None) is None
