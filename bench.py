@@ -720,7 +720,34 @@ def small_batches(args, et, ctx, d, dev):
                      "multi_nodes_per_s": nodes / (multi_graph_ms * 1e-3),
                      "fused_over_multi_graph": multi_graph_ms / fused_graph_ms, "answers_equal": same})
     cross = next((r["nodes"] for r in rows if r["multi_graph_ms"] < r["fused_graph_ms"]), None)
-    return {"sweep": rows, "crossover_nodes": cross}
+    # tiny trees (2^4..2^10 nodes, 2^4..2^10 queries each): the 256-lane shape
+    tiny = []
+    for lg in (14, 18, 22):
+        T = max(1, int((1 << lg) / 180 * 1.3) + 2)
+        b = gen.forest_batch(T, seed=args.seed + 100 + lg, log2_min=4, log2_max=10, qlog2_min=4, qlog2_max=10)
+        keep = max(1, min(int(np.searchsorted(b["offsets"], 1 << lg, side="right")) - 1, T))
+        qn = int(np.searchsorted(b["qtree"], keep))
+        off = b["offsets"][:keep + 1]
+        d_parent, d_qt, d_qx, d_qy = d(b["parent"][:int(off[-1])]), d(b["qtree"][:qn]), d(b["qx"][:qn]), d(b["qy"][:qn])
+        d_off = torch.from_numpy(off.astype(np.int64)).to(dev)
+        d_qoff = torch.from_numpy(np.searchsorted(b["qtree"][:qn], np.arange(keep + 1)).astype(np.int64)).to(dev)
+        max_nodes = int(np.diff(off).max())
+        fg = et.FusedBatchGraph(d_parent, d_off, d_qoff, d_qx, d_qy, max_nodes, ctx=ctx)
+        fused_graph_ms = time_fn(fg.replay, 10)
+        mctx = et.Context()
+        mg = et.BatchGraph(d_parent, d_off, d_qt, d_qx, d_qy, ctx=mctx)
+        multi_graph_ms = time_fn(mg.replay, 10)
+        same = bool(torch.equal(fg.out, mg.out))
+        fg.close()
+        mg.close()
+        mctx.close()
+        ctx.check()
+        nodes = int(off[-1])
+        tiny.append({"log2_target": lg, "trees": keep, "nodes": nodes, "queries": qn, "max_tree_nodes": max_nodes,
+                     "fused_graph_ms": fused_graph_ms, "multi_graph_ms": multi_graph_ms,
+                     "fused_trees_per_s": keep / (fused_graph_ms * 1e-3),
+                     "fused_over_multi_graph": multi_graph_ms / fused_graph_ms, "answers_equal": same})
+    return {"sweep": rows, "crossover_nodes": cross, "tiny_trees": tiny}
 
 
 def bridges_batched_vs_plain(args, et, ctx, d):

@@ -189,6 +189,45 @@ __device__ __forceinline__ int msb32(uint32_t x) { return 31 - __clz((int)x); }
 __device__ __forceinline__ int ctz32(uint32_t x) { return __ffs((int)x) - 1; }
 __device__ __forceinline__ int ctz64(uint64_t x) { return __ffsll((unsigned long long)x) - 1; }
 
+// (used by the one-launch small-instance kernels)
+// Exclusive scan of a[0..m) in place by a workgroup of kFT lanes; wsum:
+// kFT / 64 + 1 slots.
+template <int kFT>
+__device__ inline void wg_scan_excl(uint32_t* a, int m, int32_t* wsum) {
+  constexpr int kFW = kFT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int per = (m + kFT - 1) / kFT;
+  const int lo = min(tid * per, m), hi = min(lo + per, m);
+  uint32_t sum = 0;
+  for (int i = lo; i < hi; ++i) sum += a[i];
+  uint32_t incl = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t v = __shfl_up(incl, d);
+    if (lane >= d) incl += v;
+  }
+  if (lane == 63) wsum[w] = (int32_t)incl;
+  __syncthreads();
+  if (tid < 64) {
+    const uint32_t v = tid < kFW ? (uint32_t)wsum[tid] : 0u;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < kFW; d <<= 1) {
+      const uint32_t y = __shfl_up(x, d);
+      if (lane >= d) x += y;
+    }
+    if (tid < kFW) wsum[tid] = (int32_t)(x - v);
+  }
+  __syncthreads();
+  uint32_t run = (uint32_t)wsum[w] + incl - sum;
+  for (int i = lo; i < hi; ++i) {
+    const uint32_t x = a[i];
+    a[i] = run;
+    run += x;
+  }
+  __syncthreads();
+}
+
 // In-block range-minimum masks: one bit per position of a block of 2^LOG
 // positions (LOG 5: 32-bit words, LOG 6: 64-bit words, one wavefront).
 template <int LOG>

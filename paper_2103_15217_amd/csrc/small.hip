@@ -2,7 +2,9 @@
 // LCA queries answered on trees that are preprocessed once; Section 2 and
 // 3.1 for what each tree goes through).
 //
-// A workgroup of 1024 lanes takes one tree at a time from an atomic counter
+// A workgroup of 1024 lanes (256 when no tree has more than 1024 nodes and
+// the trees outnumber the compute units) takes one tree at a time from an
+// atomic counter
 // (the grid is sized to what stays resident, so the launch is persistent)
 // and runs the tree's whole path in LDS, reading only its parent array and
 // its queries from HBM and writing only the answers (and, on request, the
@@ -31,10 +33,13 @@
 namespace et {
 namespace {
 
-constexpr int kFT = 1024;           // lanes per workgroup
-constexpr int kFW = kFT / 64;       // wavefronts per workgroup
+// Two shapes: 1024 lanes for trees of up to 4096 nodes, 256 lanes (four
+// workgroups in the place of one) when no tree exceeds 1024 nodes. Either
+// way a lane holds at most kRoundsMax nodes of its tree.
 constexpr int kFMax = 4096;         // nodes per tree at most
-constexpr int kRoundsMax = kFMax / kFT;
+constexpr int kFSmall = 1024;       // nodes per tree at most for the 256-lane shape
+constexpr int kRoundsMax = 4;
+constexpr int kWavesMax = 16;       // wavefronts per workgroup at most
 constexpr uint16_t kEnd = 0xffff;   // list end, no node, unused label
 constexpr uint16_t kNoSucc = 0xfffe;  // a half-edge id of the root (not on the tour)
 constexpr int kDigitBits = 7;
@@ -48,7 +53,7 @@ __host__ __device__ inline uint32_t al64(uint32_t x) { return (x + 63u) & ~63u; 
 // multiple of 64). Regions are reused as the phases go:
 //   p   parent u16[N]                                  (whole tree)
 //   rb  successor u16[2N], later head u32[N+1]
-//   rc  radix counters u32[kDigits][kFW], later rank / down u16[2N] each,
+//   rc  radix counters u32[kDigits][waves], later rank / down u16[2N] each,
 //       later parent path labels u16[N+1]
 //   rd  sort buffers u16[2][N], later inlabel, ascendant, depth u16[N] each
 //   rf  sublists: next, length, down u16[2][kSubMax] each
@@ -65,7 +70,7 @@ __host__ __device__ inline SmallLayout small_layout(uint32_t N) {
   L.rb = at;
   at += al64(4 * N + 4);
   L.rc = at;
-  at += al64(8 * N > (uint32_t)(kDigits * kFW * 4) ? 8 * N : (uint32_t)(kDigits * kFW * 4));
+  at += al64(8 * N > (uint32_t)(kDigits * kWavesMax * 4) ? 8 * N : (uint32_t)(kDigits * kWavesMax * 4));
   L.rd = at;
   at += al64(6 * N);
   L.rf = at;
@@ -79,41 +84,6 @@ __host__ __device__ inline SmallLayout small_layout(uint32_t N) {
 enum { S_ROOT = 0, S_NROOTS, S_BAD, S_HEAD, S_TREE, S_FAIL, S_WSUM = 16 };  // int32 scalar slots
 
 __device__ __forceinline__ int clog2(uint32_t x) { return x <= 1 ? 0 : 32 - __clz((int)(x - 1)); }
-
-// Exclusive scan of a[0..m) in place (m <= 8 * kFT); wsum: kFW + 1 slots.
-__device__ void block_scan_excl(uint32_t* a, int m, int32_t* wsum) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int per = (m + kFT - 1) / kFT;
-  const int lo = min(tid * per, m), hi = min(lo + per, m);
-  uint32_t sum = 0;
-  for (int i = lo; i < hi; ++i) sum += a[i];
-  uint32_t incl = sum;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t v = __shfl_up(incl, d);
-    if (lane >= d) incl += v;
-  }
-  if (lane == 63) wsum[w] = (int32_t)incl;
-  __syncthreads();
-  if (tid < 64) {
-    const uint32_t v = tid < kFW ? (uint32_t)wsum[tid] : 0u;
-    uint32_t x = v;
-#pragma unroll
-    for (int d = 1; d < kFW; d <<= 1) {
-      const uint32_t y = __shfl_up(x, d);
-      if (lane >= d) x += y;
-    }
-    if (tid < kFW) wsum[tid] = (int32_t)(x - v);
-  }
-  __syncthreads();
-  uint32_t run = (uint32_t)wsum[w] + incl - sum;
-  for (int i = lo; i < hi; ++i) {
-    const uint32_t x = a[i];
-    a[i] = run;
-    run += x;
-  }
-  __syncthreads();
-}
 
 // lanes of the wavefront whose digit equals this lane's (among valid lanes)
 __device__ __forceinline__ uint64_t match_digit(bool valid, uint32_t d) {
@@ -129,12 +99,15 @@ __device__ __forceinline__ uint64_t match_digit(bool valid, uint32_t d) {
 
 __device__ __forceinline__ uint16_t root_key(uint16_t p, uint32_t n) { return p == kEnd ? (uint16_t)n : p; }
 
+template <int kFT>
 __global__ __launch_bounds__(kFT) void k_small_batch(
     const int32_t* __restrict__ parent, const int64_t* __restrict__ off, int32_t T, int64_t n_total, uint32_t N,
     int32_t nmax, const int64_t* __restrict__ qoff, int64_t q_total, const int32_t* __restrict__ qx,
     const int32_t* __restrict__ qy, int32_t* __restrict__ out, int32_t* __restrict__ depth_out,
     int32_t* __restrict__ pre_out, int32_t* __restrict__ size_out, uint32_t* __restrict__ counters,
     uint32_t* __restrict__ status) {
+  constexpr int kFW = kFT / 64;  // wavefronts per workgroup
+  static_assert(kFT * kRoundsMax >= kFSmall && kFW <= kWavesMax, "a lane holds at most kRoundsMax nodes");
   extern __shared__ __align__(16) unsigned char lds[];
   const SmallLayout L = small_layout(N);
   uint16_t* P = reinterpret_cast<uint16_t*>(lds + L.p);
@@ -246,7 +219,7 @@ __global__ __launch_bounds__(kFT) void k_small_batch(
           vv[r] = v;
         }
         __syncthreads();
-        block_scan_excl(CNT, kDigits * kFW, SC + S_WSUM);
+        wg_scan_excl<kFT>(CNT, kDigits * kFW, SC + S_WSUM);
 #pragma unroll
         for (int r = 0; r < kRoundsMax; ++r) {
           if (r >= rounds) break;
@@ -519,15 +492,23 @@ int small_batch_run(Ctx* c, const int32_t* parent, const int64_t* off, int32_t T
   if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return ET_EHIP;
+  // 256 lanes hold four trees where 1024 lanes hold one; worth it once there
+  // are more trees than compute units (one 1024-lane workgroup fits a unit)
+  const bool narrow = max_nodes <= kFSmall && T > cus;
+  const int threads = narrow ? 256 : 1024;
+  const void* kern = narrow ? reinterpret_cast<const void*>(k_small_batch<256>)
+                            : reinterpret_cast<const void*>(k_small_batch<1024>);
   if ((int)lds > max_lds) return ET_ESIZE;
-  if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_small_batch), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)lds) != hipSuccess)
-    return ET_EHIP;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_small_batch, kFT, lds) != hipSuccess) return ET_EHIP;
+  if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return ET_EHIP;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess) return ET_EHIP;
   const int grid = (int)std::min<int64_t>(T, (int64_t)std::max(per_cu, 1) * cus);
   ET_PROF(c, s, "k_small_batch");
-  hipLaunchKernelGGL(k_small_batch, dim3(grid), dim3(kFT), lds, s, parent, off, T, n_total, N, max_nodes, qoff, q_total, qx,
-                     qy, out, depth, pre, size, c->d_fused, c->d_status);
+  if (narrow)
+    hipLaunchKernelGGL(k_small_batch<256>, dim3(grid), dim3(256), lds, s, parent, off, T, n_total, N, max_nodes,
+                       qoff, q_total, qx, qy, out, depth, pre, size, c->d_fused, c->d_status);
+  else
+    hipLaunchKernelGGL(k_small_batch<1024>, dim3(grid), dim3(1024), lds, s, parent, off, T, n_total, N, max_nodes,
+                       qoff, q_total, qx, qy, out, depth, pre, size, c->d_fused, c->d_status);
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }
 

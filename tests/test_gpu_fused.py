@@ -70,7 +70,7 @@ def check_against_oracle(oracle_mod, batch, out, st):
 
 
 @pytest.mark.parametrize("T,lo,hi,seed", [(1, 6, 6, 0), (37, 6, 12, 1), (500, 6, 12, 2), (300, 2, 8, 3),
-                                          (64, 11, 12, 4)])
+                                          (64, 11, 12, 4), (700, 4, 10, 5)])
 def test_random_batches(lib, oracle_mod, T, lo, hi, seed):
     batch = gen.forest_batch(T, seed=seed, log2_min=lo, log2_max=hi, qlog2_min=0, qlog2_max=10)
     max_nodes = int(batch["sizes"].max())
@@ -122,15 +122,16 @@ def test_equals_multi_kernel_batch(lib):
         assert np.array_equal(st[k], ref[k]), k
 
 
-def test_repeated_calls_and_graph_replays(lib):
+@pytest.mark.parametrize("log2_max,bound", [(12, 4096), (10, 1024)])  # the 1024- and the 256-lane shape
+def test_repeated_calls_and_graph_replays(lib, log2_max, bound):
     """The work counter resets itself at the end of every launch: calls in a
     row with different grids, and replays of a captured graph, all agree."""
     import torch
-    big = gen.forest_batch(600, seed=21, log2_min=6, log2_max=12, qlog2_min=4, qlog2_max=9)
+    big = gen.forest_batch(600, seed=21, log2_min=6, log2_max=log2_max, qlog2_min=4, qlog2_max=9)
     small = gen.forest_batch(3, seed=22, log2_min=6, log2_max=8, qlog2_min=4, qlog2_max=6)
     ctx = lib.Context()
     try:
-        first = [run_fused(lib, b, 4096, ctx=ctx)[0] for b in (big, small, big)]
+        first = [run_fused(lib, b, bound, ctx=ctx)[0] for b in (big, small, big)]
         ctx.check()
         assert np.array_equal(first[0], first[2])
         T = len(big["sizes"])
@@ -140,19 +141,19 @@ def test_repeated_calls_and_graph_replays(lib):
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            lib.et_lca_batch_fused(*args, 4096, out=out, ctx=ctx)  # warm-up outside capture
+            lib.et_lca_batch_fused(*args, bound, out=out, ctx=ctx)  # warm-up outside capture
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            lib.et_lca_batch_fused(*args, 4096, out=out, ctx=ctx)
+            lib.et_lca_batch_fused(*args, bound, out=out, ctx=ctx)
         for _ in range(4):
             out.fill_(-7)
             g.replay()
             torch.cuda.synchronize()
             assert np.array_equal(out.cpu().numpy(), first[0])
             # eager work between replays
-            assert np.array_equal(run_fused(lib, small, 4096, ctx=ctx)[0], first[1])
+            assert np.array_equal(run_fused(lib, small, bound, ctx=ctx)[0], first[1])
         ctx.check()
     finally:
         ctx.close()
