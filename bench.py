@@ -306,6 +306,9 @@ def main():
         log("small-tree batches: one fused launch vs the multi-kernel batch")
         result["components"]["small_batches"] = small_batches(args, et, bctx, d, dev)
     if not args.no_batch:
+        log("small-graph batches: one fused launch vs the multi-kernel batch")
+        result["components"]["small_graph_batches"] = small_graph_batches(args, et, bctx, d)
+    if not args.no_batch:
         log("batched graphs: generating")
         result["components"]["bridges_batched"] = bridges_batched_vs_plain(args, et, bctx, d)
     if not args.no_engines:
@@ -803,6 +806,48 @@ def bridges_batched_vs_plain(args, et, ctx, d):
             "plain_ms": res["plain"], "graph_ms": res["graph"], "batched_edges_per_s": m / (res["batched"] * 1e-3),
             "plain_edges_per_s": m / (res["plain"] * 1e-3), "speedup": res["plain"] / res["batched"],
             "masks_equal": ok, "graph_matches_eager": graph_ok, **res["breakdown"]}
+
+
+def small_graph_batches(args, et, ctx, d):
+    """Batches of small graphs (log-uniform 2^3..2^10 vertices, average
+    degree 4, distinct pairs: sparse, so rich in bridges) with 2^12 to 2^20
+    vertices in all: the one-launch path (et_bridges_batch_fused) against
+    the multi-kernel et_bridges_batch, both replayed from a HIP graph, masks
+    and counts compared."""
+    import torch
+    import gen
+    rows_out = []
+    for lg in (12, 14, 16, 18, 20):
+        rng = np.random.default_rng(args.seed + 31 + lg)
+        graphs, nv = [], 0
+        while nv < (1 << lg):
+            n = int(2 ** rng.uniform(3, 10))
+            rp, col = gen.random_multigraph(n, 2 * n, seed=int(rng.integers(1 << 30)), loops=False, multi=False)
+            graphs.append((d(rp), d(col)))
+            nv += n
+        rows = torch.cat([g[0] for g in graphs])
+        cols = torch.cat([g[1] for g in graphs])
+        vs = [g[0].numel() - 1 for g in graphs]
+        ss = [g[1].numel() for g in graphs]
+        voff = torch.from_numpy(np.concatenate([[0], np.cumsum(vs)]).astype(np.int64)).cuda()
+        soff = torch.from_numpy(np.concatenate([[0], np.cumsum(ss)]).astype(np.int64)).cuda()
+        fg = et.BridgesFusedGraph(rows, cols, voff, soff, ss, vs, ctx=ctx)
+        fused_ms = _gpu_ms(fg.replay, 10)
+        mg = et.BridgesBatchGraph(rows, cols, voff, soff, ss)
+        multi_ms = _gpu_ms(mg.replay, 10)
+        total = sum((x + 31) // 32 for x in ss)
+        same = bool(torch.equal(fg.mask[:total], mg.mask[:total]) and torch.equal(fg.counts, mg.counts))
+        fg.close()
+        mg.ctx.check()
+        mg.close()
+        ctx.check()
+        m = sum(ss) // 2
+        rows_out.append({"log2_target": lg, "graphs": len(graphs), "vertices": nv, "edges": m,
+                         "fused_graph_ms": fused_ms, "multi_graph_ms": multi_ms,
+                         "fused_edges_per_s": m / (fused_ms * 1e-3), "multi_edges_per_s": m / (multi_ms * 1e-3),
+                         "fused_over_multi_graph": multi_ms / fused_ms, "answers_equal": same})
+    cross = next((r["vertices"] for r in rows_out if r["multi_graph_ms"] < r["fused_graph_ms"]), None)
+    return {"sweep": rows_out, "crossover_vertices": cross}
 
 
 def serving(args, dev):

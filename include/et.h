@@ -472,6 +472,41 @@ int et_bridges_batch(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col
                      const int64_t* d_soff, int32_t n_graphs, int32_t n_total, int32_t nnz_total,
                      uint32_t* d_mask, int64_t mask_words, int64_t* d_counts, hipStream_t s);
 
+/*
+ * Bridges of many small graphs in one kernel launch (Section 4.1 for each
+ * graph; batched as the tree batch of Section 3.3). Each graph is solved in
+ * one workgroup's LDS -- spanning forest by union-find, the forest's Euler
+ * tour (succ = next(twin), Section 2.1) ranked by pointer jumping,
+ * preorder and subtree sizes, per-vertex non-forest extremes, low / high by
+ * range minima and maxima, the bridge test -- so HBM sees only the CSR
+ * arrays, the mask words and the counts. Workgroups take graphs from a
+ * counter until none are left.
+ *   d_row_ptr, d_col, d_voff, d_soff   as for et_bridges_batch (each graph's
+ *                  own row pointers back to back, its columns back to back,
+ *                  int64 vertex and slot offsets)
+ *   d_moff[n_graphs + 1]  device int64 offsets of the graphs' mask words:
+ *                  graph t's ceil(nnz_t / 32) words start at moff[t]
+ *                  (moff[0] = 0; the layout et_bridges_batch uses when they
+ *                  are the running sums of ceil(nnz_t / 32))
+ *   max_graph_vertices, max_graph_slots  upper bounds on every graph's
+ *                  vertex and slot counts, at most ET_FUSED_MAX_VERTICES and
+ *                  ET_FUSED_MAX_SLOTS; they set the LDS each workgroup takes
+ *   d_mask[mask_words]  output words (bit k of graph t's words = its slot k)
+ *   d_counts[n_graphs]  optional device output: bridges per graph
+ * Same masks and counts as et_bridges_batch. ET_ESIZE if a bound exceeds
+ * its maximum or the LDS it needs exceeds what one workgroup may take. A
+ * graph larger than the bounds, offsets that do not match, rows that are
+ * not sorted or a slot without its twin set ET_EINPUT in ctx's status (that
+ * graph's words are then zero). Uses a counter pair of ctx: calls sharing
+ * a context must be ordered on one stream.
+ */
+#define ET_FUSED_MAX_VERTICES 1024
+#define ET_FUSED_MAX_SLOTS 8192
+int et_bridges_batch_fused(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col, const int64_t* d_voff,
+                           const int64_t* d_soff, const int64_t* d_moff, int32_t n_graphs, int32_t n_total,
+                           int32_t nnz_total, int32_t max_graph_vertices, int32_t max_graph_slots,
+                           uint32_t* d_mask, int64_t mask_words, int64_t* d_counts, hipStream_t s);
+
 /* Device-side bridge count of the most recent et_bridges call (for a batch:
  * the total over its graphs) on ctx
  * (written to a caller-owned device int64). */

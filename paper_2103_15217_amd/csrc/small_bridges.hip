@@ -1,0 +1,516 @@
+// Bridges of many small graphs in one launch (Section 4.1, Tarjan-Vishkin,
+// for a batch of instances as the tree batch of Section 3.3 does for LCA).
+//
+// A workgroup of 1024 lanes takes one graph at a time from an atomic counter
+// (a persistent grid sized to what stays resident) and runs the whole method
+// on it in LDS, reading only its CSR from HBM and writing only its mask words
+// and its bridge count:
+//   1. row pointers and columns into LDS, checked (monotone rows from 0 to
+//      the slot count, sorted rows, every slot's twin present);
+//   2. spanning forest: union-find over the first slot of every run of equal
+//      columns (u < w), the larger root linked under the smaller by an LDS
+//      compare-and-swap; a successful link marks the slot and its twin as a
+//      forest edge;
+//   3. the forest's half-edges per vertex in row order, twins by binary
+//      search, succ = next(twin) cyclically per vertex (Section 2.1), the
+//      component tours cut before each root's first half-edge and chained in
+//      root order;
+//   4. ranks along the chained tour by pointer jumping, a half-edge going
+//      down iff it comes before its twin, preorder from a scan of the down
+//      flags in tour order, subtree sizes from the two ranks of each edge;
+//   5. per vertex the min / max preorder over its non-forest slots (itself
+//      included), low / high as range min / max over the subtree interval
+//      (in-block prefix and suffix extremes plus a sparse table over
+//      32-position blocks), and the bridge test: low == pre and high ==
+//      pre + size - 1, for an edge of multiplicity one.
+// Ids, slots, ranks and preorder numbers are below 2^16 here (a graph has at
+// most 1024 vertices and 8192 CSR slots), so the LDS tables hold 16-bit
+// entries.
+#include "et_internal.hpp"
+
+namespace et {
+namespace {
+
+constexpr int kBT = 1024;            // lanes per workgroup
+constexpr int kBW = kBT / 64;
+constexpr int kGMaxV = 1024;         // vertices of a graph at most
+constexpr int kGMaxS = 8192;         // CSR slots of a graph at most
+constexpr uint16_t kNil = 0xffff;    // list end, no slot
+constexpr int kRB = 32;              // range-minimum block (positions)
+constexpr int kRLev = 6;             // sparse-table levels over at most 32 blocks
+
+__host__ __device__ inline uint32_t a64(uint32_t x) { return (x + 63u) & ~63u; }
+
+// LDS regions for graphs of at most N vertices and M slots (multiples of 64):
+//   rp u16[N+1], col u16[M], src u16[M]      the CSR and each slot's row
+//   uf u32[N]                                 union-find parents, then roots
+//   tf, mb u32[M/32]                          forest-slot bits, bridge bits
+//   tptr u16[N+1], hs/tsl/tnb/ttw u16[2N]     forest half-edges per vertex
+//   nx u16[2][2N], dd u16[2][2N]              pointer jumping
+//   tour u16[2N], dc u32[2N]                  tour order, down-flag scan
+//   pre/size/pslot/ridx/rl u16[N]             per vertex; root list
+//   amn/amx u32[N]                            per preorder position
+//   pmn/smn/pmx/smx u16[N], st u16[2][kRLev][N/32]
+struct BLayout {
+  uint32_t rp, col, src, uf, tf, mb, tptr, hs, tsl, tnb, ttw, nx, dd, tour, dc, pre, size, pslot, ridx, rl, amn,
+      amx, pmn, smn, pmx, smx, st, sc, total;
+};
+
+__host__ __device__ inline BLayout blayout(uint32_t N, uint32_t M) {
+  BLayout L;
+  uint32_t at = 0;
+  auto take = [&](uint32_t bytes) {
+    const uint32_t r = at;
+    at += a64(bytes);
+    return r;
+  };
+  L.rp = take(2 * (N + 1));
+  L.col = take(2 * M);
+  L.src = take(2 * M);
+  L.uf = take(4 * N);
+  L.tf = take(M / 8 + 4);
+  L.mb = take(M / 8 + 4);
+  L.tptr = take(2 * (N + 1));
+  L.hs = take(4 * N);
+  L.tsl = take(4 * N);
+  L.tnb = take(4 * N);
+  L.ttw = take(4 * N);
+  L.nx = take(8 * N);
+  L.dd = take(8 * N);
+  L.tour = take(4 * N);
+  L.dc = take(8 * N);
+  L.pre = take(2 * N);
+  L.size = take(2 * N);
+  L.pslot = take(2 * N);
+  L.ridx = take(2 * N);
+  L.rl = take(2 * N);
+  L.amn = take(4 * N);
+  L.amx = take(4 * N);
+  L.pmn = take(2 * N);
+  L.smn = take(2 * N);
+  L.pmx = take(2 * N);
+  L.smx = take(2 * N);
+  L.st = take(2 * 2 * kRLev * (N / kRB + 1));
+  L.sc = take(256);
+  L.total = at;
+  return L;
+}
+
+enum { B_GRAPH = 0, B_FAIL, B_BAD, B_ET, B_NR, B_HEAD, B_CNT, B_TOT, B_WSUM = 16 };
+
+// first index in [lo, hi) of the sorted u16 array a with a[i] >= x
+__device__ __forceinline__ uint32_t lower16(const uint16_t* a, uint32_t lo, uint32_t hi, uint32_t x) {
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint32_t uf_find(uint32_t* uf, uint32_t x) {
+  for (;;) {
+    const uint32_t p = uf[x];
+    if (p == x) return x;
+    const uint32_t g = uf[p];
+    if (g != p) uf[x] = g;  // path halving; only a non-root is ever rewritten
+    x = g;
+  }
+}
+
+__global__ __launch_bounds__(kBT) void k_small_bridges(
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const int64_t* __restrict__ voff,
+    const int64_t* __restrict__ soff, const int64_t* __restrict__ moff, int32_t T, int64_t n_total,
+    int64_t nnz_total, int64_t mask_words, uint32_t N, uint32_t M, int32_t vmax, int32_t smax,
+    uint32_t* __restrict__ mask, int64_t* __restrict__ counts, uint32_t* __restrict__ counters,
+    uint32_t* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const BLayout L = blayout(N, M);
+  uint16_t* RP = reinterpret_cast<uint16_t*>(lds + L.rp);
+  uint16_t* COL = reinterpret_cast<uint16_t*>(lds + L.col);
+  uint16_t* SRC = reinterpret_cast<uint16_t*>(lds + L.src);
+  uint32_t* UF = reinterpret_cast<uint32_t*>(lds + L.uf);
+  uint32_t* TF = reinterpret_cast<uint32_t*>(lds + L.tf);
+  uint32_t* MB = reinterpret_cast<uint32_t*>(lds + L.mb);
+  uint16_t* TPTR = reinterpret_cast<uint16_t*>(lds + L.tptr);
+  uint16_t* HS = reinterpret_cast<uint16_t*>(lds + L.hs);
+  uint16_t* TSL = reinterpret_cast<uint16_t*>(lds + L.tsl);
+  uint16_t* TNB = reinterpret_cast<uint16_t*>(lds + L.tnb);
+  uint16_t* TTW = reinterpret_cast<uint16_t*>(lds + L.ttw);
+  uint16_t* NXa = reinterpret_cast<uint16_t*>(lds + L.nx);
+  uint16_t* DDa = reinterpret_cast<uint16_t*>(lds + L.dd);
+  uint16_t* TOUR = reinterpret_cast<uint16_t*>(lds + L.tour);
+  uint32_t* DC = reinterpret_cast<uint32_t*>(lds + L.dc);
+  uint16_t* PRE = reinterpret_cast<uint16_t*>(lds + L.pre);
+  uint16_t* SIZE = reinterpret_cast<uint16_t*>(lds + L.size);
+  uint16_t* PSLOT = reinterpret_cast<uint16_t*>(lds + L.pslot);
+  uint16_t* RIDX = reinterpret_cast<uint16_t*>(lds + L.ridx);
+  uint16_t* RL = reinterpret_cast<uint16_t*>(lds + L.rl);
+  uint32_t* AMN = reinterpret_cast<uint32_t*>(lds + L.amn);
+  uint32_t* AMX = reinterpret_cast<uint32_t*>(lds + L.amx);
+  uint16_t* PMN = reinterpret_cast<uint16_t*>(lds + L.pmn);
+  uint16_t* SMN = reinterpret_cast<uint16_t*>(lds + L.smn);
+  uint16_t* PMX = reinterpret_cast<uint16_t*>(lds + L.pmx);
+  uint16_t* SMX = reinterpret_cast<uint16_t*>(lds + L.smx);
+  uint16_t* ST = reinterpret_cast<uint16_t*>(lds + L.st);
+  int32_t* SC = reinterpret_cast<int32_t*>(lds + L.sc);
+  const uint32_t tid = threadIdx.x;
+  const uint32_t nbk = N / kRB + 1;  // sparse-table row length
+#define STMN(l) (ST + (l) * nbk)
+#define STMX(l) (ST + (kRLev + (l)) * nbk)
+
+  if (blockIdx.x == 0 && tid == 0) {
+    if (voff[0] != 0 || voff[T] != n_total || soff[0] != 0 || soff[T] != nnz_total || moff[0] != 0 ||
+        moff[T] > mask_words)
+      flag(status, ST_BAD_CSR);
+  }
+  for (;;) {
+    if (tid == 0) SC[B_GRAPH] = (int32_t)atomicAdd(&counters[0], 1u);
+    __syncthreads();
+    const int32_t t = SC[B_GRAPH];
+    if (t >= T) break;
+    const int64_t vb = voff[t], nv = voff[t + 1] - vb;
+    const int64_t sb = soff[t], ns = soff[t + 1] - sb;
+    const int64_t mw = moff[t], nw = moff[t + 1] - mw;
+    const bool out_ok = mw >= 0 && nw == (ns + 31) / 32 && mw + nw <= mask_words && ns >= 0;
+    const bool g_ok = out_ok && vb >= 0 && nv >= 0 && nv <= vmax && sb >= 0 && ns <= smax &&
+                      vb + nv <= n_total && sb + ns <= nnz_total;
+    if (!g_ok && tid == 0) flag(status, ST_BAD_CSR);
+    const uint32_t n = g_ok ? (uint32_t)nv : 0u, m = g_ok ? (uint32_t)ns : 0u;
+    const int32_t* rpg = row_ptr + vb + t;  // graph t's n + 1 row pointers
+    if (tid == 0) {
+      SC[B_FAIL] = g_ok ? 0 : 1;
+      SC[B_BAD] = 0;
+      SC[B_CNT] = 0;
+      SC[B_NR] = 0;
+    }
+    for (uint32_t i = tid; i < (m + 31) / 32 + 1; i += kBT) {
+      TF[i] = 0;
+      MB[i] = 0;
+    }
+    __syncthreads();
+
+    // 1. the CSR (nothing is read for a graph whose offsets are out of range)
+    for (uint32_t v = tid; g_ok && v <= n; v += kBT) {
+      const int32_t r = rpg[v];
+      if (r < 0 || (uint32_t)r > m || (v == 0 && r != 0) || (v == n && (uint32_t)r != m)) {
+        SC[B_BAD] = 1;
+        RP[v] = 0;
+      } else {
+        RP[v] = (uint16_t)r;
+      }
+    }
+    for (uint32_t k = tid; k < m; k += kBT) {
+      const int32_t w = col[sb + k];
+      if (w < 0 || (uint32_t)w >= n) {
+        SC[B_BAD] = 1;
+        COL[k] = 0;
+      } else {
+        COL[k] = (uint16_t)w;
+      }
+    }
+    __syncthreads();
+    for (uint32_t v = tid; v < n; v += kBT)
+      if (RP[v] > RP[v + 1]) SC[B_BAD] = 1;
+    __syncthreads();
+    if (!SC[B_BAD] && n > 0) {
+      for (uint32_t k = tid; k < m; k += kBT) {
+        // row of slot k: the last v with RP[v] <= k (rows may be empty)
+        uint32_t lo = 0, hi = n;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (RP[mid] <= k) lo = mid;
+          else hi = mid;
+        }
+        SRC[k] = (uint16_t)lo;
+        const uint32_t w = COL[k];
+        if (k > RP[lo] && COL[k - 1] > w) SC[B_BAD] = 1;  // rows sorted
+        const uint32_t tw = lower16(COL, RP[w], RP[w + 1], lo);
+        if (tw >= RP[w + 1] || COL[tw] != lo) SC[B_BAD] = 1;  // the twin slot
+      }
+    }
+    __syncthreads();
+    if (tid == 0 && SC[B_BAD] && !SC[B_FAIL]) {
+      flag(status, ST_BAD_CSR);
+      SC[B_FAIL] = 1;
+    }
+    __syncthreads();
+
+    if (!SC[B_FAIL] && m > 0) {
+      // 2. spanning forest
+      for (uint32_t v = tid; v < n; v += kBT) UF[v] = v;
+      __syncthreads();
+      for (uint32_t k = tid; k < m; k += kBT) {
+        const uint32_t u = SRC[k], w = COL[k];
+        if (u >= w || (k > RP[u] && COL[k - 1] == w)) continue;  // one slot per u-w run, u < w
+        uint32_t ru = uf_find(UF, u), rw = uf_find(UF, w);
+        while (ru != rw) {
+          const uint32_t lo = min(ru, rw), hi = max(ru, rw);
+          if (atomicCAS(&UF[hi], hi, lo) == hi) {
+            const uint32_t tw = lower16(COL, RP[w], RP[w + 1], u);
+            atomicOr(&TF[k >> 5], 1u << (k & 31));
+            atomicOr(&TF[tw >> 5], 1u << (tw & 31));
+            break;
+          }
+          ru = uf_find(UF, ru);
+          rw = uf_find(UF, rw);
+        }
+      }
+      __syncthreads();
+      for (uint32_t v = tid; v < n; v += kBT) UF[v] = uf_find(UF, v);  // roots (the least id of each component)
+      __syncthreads();
+
+      // 3. forest half-edges per vertex, in row order
+      for (uint32_t v = tid; v < n; v += kBT) {
+        uint32_t d = 0;
+        for (uint32_t k = RP[v]; k < RP[v + 1]; ++k) d += (TF[k >> 5] >> (k & 31)) & 1u;
+        DC[v] = d;
+      }
+      __syncthreads();
+      const uint32_t dlast = n ? DC[n - 1] : 0;
+      wg_scan_excl<kBT>(DC, (int)n, SC + B_WSUM);
+      for (uint32_t v = tid; v <= n; v += kBT) TPTR[v] = (uint16_t)(v < n ? DC[v] : DC[n - 1] + dlast);
+      __syncthreads();
+      const uint32_t Et = TPTR[n];
+      for (uint32_t v = tid; v < n; v += kBT) {
+        uint32_t h = TPTR[v];
+        for (uint32_t k = RP[v]; k < RP[v + 1]; ++k)
+          if ((TF[k >> 5] >> (k & 31)) & 1u) {
+            HS[h] = (uint16_t)v;
+            TSL[h] = (uint16_t)k;
+            TNB[h] = COL[k];
+            ++h;
+          }
+      }
+      __syncthreads();
+      uint16_t* SUCC = NXa;  // buffer 0 of the pointer jumping starts as the successor array
+      for (uint32_t h = tid; h < Et; h += kBT) {
+        const uint32_t u = HS[h], w = TNB[h];
+        const uint32_t tw = lower16(TNB, TPTR[w], TPTR[w + 1], u);
+        TTW[h] = (uint16_t)tw;
+        // succ(h) = next(twin(h)) in w's cyclic list
+        SUCC[h] = (uint16_t)((tw + 1 == TPTR[w + 1]) ? TPTR[w] : tw + 1);
+      }
+      // component roots that own forest edges, in id order
+      for (uint32_t v = tid; v < n; v += kBT) DC[v] = (UF[v] == v && TPTR[v + 1] > TPTR[v]) ? 1u : 0u;
+      __syncthreads();
+      const uint32_t rlast = n ? DC[n - 1] : 0;
+      wg_scan_excl<kBT>(DC, (int)n, SC + B_WSUM);
+      for (uint32_t v = tid; v < n; v += kBT)
+        if (UF[v] == v && TPTR[v + 1] > TPTR[v]) {
+          RIDX[v] = (uint16_t)DC[v];
+          RL[DC[v]] = (uint16_t)v;
+        }
+      if (tid == 0) {
+        SC[B_NR] = (int32_t)(n ? DC[n - 1] + rlast : 0);
+        SC[B_ET] = (int32_t)Et;
+      }
+      __syncthreads();
+      const uint32_t R = (uint32_t)SC[B_NR];
+      // cut each component's cycle before its root's first half-edge and chain them
+      for (uint32_t i = tid; i < R; i += kBT) {
+        const uint32_t r = RL[i];
+        const uint32_t last = TTW[TPTR[r + 1] - 1];  // its successor is r's first half-edge
+        SUCC[last] = (i + 1 < R) ? TPTR[RL[i + 1]] : kNil;
+      }
+      __syncthreads();
+
+      if (R > 0) {
+        // 4. ranks: distance to the end by pointer jumping
+        uint16_t* NX0 = NXa;
+        uint16_t* NX1 = NXa + 2 * N;
+        uint16_t* DD0 = DDa;
+        uint16_t* DD1 = DDa + 2 * N;
+        for (uint32_t h = tid; h < Et; h += kBT) DD0[h] = NX0[h] == kNil ? 0 : 1;
+        __syncthreads();
+        const int jumps = (32 - __clz((int)Et)) + 1;
+        for (int it = 0; it < jumps; ++it) {
+          for (uint32_t h = tid; h < Et; h += kBT) {
+            const uint32_t x = NX0[h];
+            if (x != kNil && x < Et) {
+              NX1[h] = NX0[x];
+              DD1[h] = (uint16_t)(DD0[h] + DD0[x]);
+            } else {
+              NX1[h] = kNil;
+              DD1[h] = DD0[h];
+            }
+          }
+          __syncthreads();
+          uint16_t* tn = NX0;
+          NX0 = NX1;
+          NX1 = tn;
+          uint16_t* td = DD0;
+          DD0 = DD1;
+          DD1 = td;
+        }
+        const uint32_t head = TPTR[RL[0]];
+        if (tid == 0 && (uint32_t)DD0[head] + 1 != Et) {
+          flag(status, ST_UNREACHED);
+          SC[B_FAIL] = 1;
+        }
+        __syncthreads();
+        if (!SC[B_FAIL]) {
+          uint16_t* RK = DD1;  // rank = Et - 1 - distance to the end
+          for (uint32_t h = tid; h < Et; h += kBT) {
+            const uint32_t r = Et - 1 - DD0[h];
+            RK[h] = (uint16_t)r;
+            TOUR[r] = (uint16_t)h;
+          }
+          __syncthreads();
+          for (uint32_t r = tid; r < Et; r += kBT) {
+            const uint32_t h = TOUR[r];
+            DC[r] = RK[h] < RK[TTW[h]] ? 1u : 0u;
+          }
+          __syncthreads();
+          wg_scan_excl<kBT>(DC, (int)Et, SC + B_WSUM);  // down half-edges before each tour position
+          // preorder and subtree size: a down half-edge (u -> w) enters w
+          for (uint32_t h = tid; h < Et; h += kBT) {
+            const uint32_t r = RK[h], rt = RK[TTW[h]];
+            if (r < rt) {
+              const uint32_t w = TNB[h];
+              PRE[w] = (uint16_t)(RIDX[UF[w]] + DC[r] + 1);
+              SIZE[w] = (uint16_t)((rt - r + 1) >> 1);
+              PSLOT[w] = TSL[h];
+            }
+          }
+          for (uint32_t i = tid; i < R; i += kBT) {
+            const uint32_t r = RL[i];
+            const uint32_t start = RK[TPTR[r]];
+            const uint32_t end = (i + 1 < R) ? RK[TPTR[RL[i + 1]]] : Et;  // one past its last half-edge
+            PRE[r] = (uint16_t)(i + DC[start]);
+            SIZE[r] = (uint16_t)((end - start) / 2 + 1);
+            PSLOT[r] = kNil;
+          }
+          __syncthreads();
+
+          // 5. non-forest extremes per preorder position
+          const uint32_t P = Et / 2 + R;  // vertices in components with forest edges
+          for (uint32_t v = tid; v < n; v += kBT)
+            if (TPTR[v + 1] > TPTR[v]) {
+              AMN[PRE[v]] = PRE[v];
+              AMX[PRE[v]] = PRE[v];
+            }
+          __syncthreads();
+          for (uint32_t k = tid; k < m; k += kBT) {
+            if ((TF[k >> 5] >> (k & 31)) & 1u) continue;
+            const uint32_t u = SRC[k], w = COL[k];
+            if (TPTR[u + 1] == TPTR[u]) continue;  // a loop on a vertex without forest edges
+            atomicMin(&AMN[PRE[u]], (uint32_t)PRE[w]);
+            atomicMax(&AMX[PRE[u]], (uint32_t)PRE[w]);
+          }
+          __syncthreads();
+          // in-block prefix / suffix extremes and the block extremes
+          const uint32_t nb = (P + kRB - 1) / kRB;
+          for (uint32_t b = tid; b < nb; b += kBT) {
+            const uint32_t lo = b * kRB, hi = min(lo + kRB, P);
+            uint32_t mn = 0xffffu, mx = 0;
+            for (uint32_t i = lo; i < hi; ++i) {
+              mn = min(mn, AMN[i]);
+              mx = max(mx, AMX[i]);
+              PMN[i] = (uint16_t)mn;
+              PMX[i] = (uint16_t)mx;
+            }
+            STMN(0)[b] = (uint16_t)mn;
+            STMX(0)[b] = (uint16_t)mx;
+            mn = 0xffffu;
+            mx = 0;
+            for (uint32_t i = hi; i-- > lo;) {
+              mn = min(mn, AMN[i]);
+              mx = max(mx, AMX[i]);
+              SMN[i] = (uint16_t)mn;
+              SMX[i] = (uint16_t)mx;
+            }
+          }
+          __syncthreads();
+          for (int l = 1; l < kRLev; ++l) {
+            for (uint32_t b = tid; b + (1u << l) <= nb; b += kBT) {
+              const uint32_t b2 = b + (1u << (l - 1));
+              STMN(l)[b] = min(STMN(l - 1)[b], STMN(l - 1)[b2]);
+              STMX(l)[b] = max(STMX(l - 1)[b], STMX(l - 1)[b2]);
+            }
+            __syncthreads();
+          }
+          // the bridge test for the forest edge above every non-root vertex
+          for (uint32_t w = tid; w < n; w += kBT) {
+            const uint32_t k = PSLOT[w];
+            if (TPTR[w + 1] == TPTR[w] || k == kNil) continue;
+            const uint32_t l = PRE[w], r = l + SIZE[w] - 1;
+            uint32_t mn, mx;
+            const uint32_t bl = l / kRB, br = r / kRB;
+            if (bl == br) {
+              mn = 0xffffu;
+              mx = 0;
+              for (uint32_t i = l; i <= r; ++i) {
+                mn = min(mn, AMN[i]);
+                mx = max(mx, AMX[i]);
+              }
+            } else {
+              mn = min((uint32_t)SMN[l], (uint32_t)PMN[r]);
+              mx = max((uint32_t)SMX[l], (uint32_t)PMX[r]);
+              if (br > bl + 1) {
+                const uint32_t a = bl + 1, cnt = br - bl - 1;
+                const int lev = 31 - __clz((int)cnt);
+                const uint32_t b2 = a + cnt - (1u << lev);
+                mn = min(mn, (uint32_t)min(STMN(lev)[a], STMN(lev)[b2]));
+                mx = max(mx, (uint32_t)max(STMX(lev)[a], STMX(lev)[b2]));
+              }
+            }
+            if (mn != l || mx != r) continue;
+            const uint32_t u = SRC[k];
+            if (k + 1 < RP[u + 1] && COL[k + 1] == w) continue;  // a parallel edge is never a bridge
+            const uint32_t tw = lower16(COL, RP[w], RP[w + 1], u);
+            atomicOr(&MB[k >> 5], 1u << (k & 31));
+            atomicOr(&MB[tw >> 5], 1u << (tw & 31));
+            atomicAdd(&SC[B_CNT], 1);
+          }
+          __syncthreads();
+        }
+      }
+    }
+    // 6. the graph's mask words and count
+    if (out_ok) {
+      const bool fail = SC[B_FAIL] != 0;
+      for (int64_t i = tid; i < nw; i += kBT) mask[mw + i] = fail ? 0u : MB[i];
+      if (tid == 0 && counts) counts[t] = fail ? 0 : SC[B_CNT];
+    }
+    __syncthreads();  // the tables and SC[B_GRAPH] are rewritten by the next graph
+  }
+  if (tid == 0) {
+    __threadfence();
+    if (atomicAdd(&counters[1], 1u) == gridDim.x - 1) {
+      atomicExch(&counters[0], 0u);
+      atomicExch(&counters[1], 0u);
+    }
+  }
+#undef STMN
+#undef STMX
+}
+
+}  // namespace
+
+int small_bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, const int64_t* voff, const int64_t* soff,
+                      const int64_t* moff, int32_t T, int32_t n_total, int32_t nnz_total, int32_t max_vertices,
+                      int32_t max_slots, uint32_t* mask, int64_t mask_words, int64_t* counts, hipStream_t s) {
+  if (T == 0) return ET_OK;
+  if (max_vertices < 0 || max_slots < 0) return ET_EINVAL;
+  if (max_vertices > kGMaxV || max_slots > kGMaxS) return ET_ESIZE;
+  const uint32_t N = a64((uint32_t)std::max(max_vertices, 1)), M = a64((uint32_t)std::max(max_slots, 1));
+  const uint32_t lds = blayout(N, M).total;
+  int dev = 0, max_lds = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ET_EHIP;
+  if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return ET_EHIP;
+  if ((int)lds > max_lds) return ET_ESIZE;
+  const void* kern = reinterpret_cast<const void*>(k_small_bridges);
+  if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return ET_EHIP;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_small_bridges, kBT, lds) != hipSuccess) return ET_EHIP;
+  const int grid = (int)std::min<int64_t>(T, (int64_t)std::max(per_cu, 1) * cus);
+  ET_PROF(c, s, "k_small_bridges");
+  hipLaunchKernelGGL(k_small_bridges, dim3(grid), dim3(kBT), lds, s, row_ptr, col, voff, soff, moff, T,
+                     (int64_t)n_total, (int64_t)nnz_total, mask_words, N, M, max_vertices, max_slots, mask, counts,
+                     c->d_fused, c->d_status);
+  return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
+}
+
+}  // namespace et

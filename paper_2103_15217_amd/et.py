@@ -37,6 +37,8 @@ _SIG = {
     "et_list_scan": ([_P, _P, _P, _i32, _P, _i32, _P, _P, _P], ctypes.c_int),
     "et_list_rank_noalloc": ([_P, _P, _i32, _P, _i32, _P, _P], ctypes.c_int),
     "et_lca_batch_fused": ([_P, _P, _P, _i32, _i64, _i32, _P, _P, _P, _i64, _P, _P, _P, _P, _P], ctypes.c_int),
+    "et_bridges_batch_fused": ([_P, _P, _P, _P, _P, _P, _i32, _i32, _i32, _i32, _i32, _P, _i64, _P, _P],
+                               ctypes.c_int),
     "et_tree_build": ([_P, _P, _i32, _P, ctypes.POINTER(_P)], ctypes.c_int),
     "et_tree_size": ([_P], _i32),
     "et_tree_batch_size": ([_P], _i32),
@@ -68,6 +70,7 @@ for _name, (_args, _res) in _SIG.items():
 
 ET_OK, ET_EINVAL, ET_ENOMEM, ET_EHIP, ET_EINPUT, ET_ESIZE = 0, -1, -2, -3, -4, -5
 FUSED_MAX_NODES = 4096  # trees of et_lca_batch_fused (et.h)
+FUSED_MAX_VERTICES, FUSED_MAX_SLOTS = 1024, 8192  # graphs of et_bridges_batch_fused (et.h)
 # limits of et_list_rank_noalloc (et.h)
 NOALLOC_MAX_LEN = 1 << 20
 NOALLOC_MAX_HEADS = 1 << 16
@@ -557,6 +560,64 @@ def et_bridges_batch(graphs=None, *, row_ptr=None, col=None, voff=None, soff=Non
     return mask, list(zip(starts, words)), out
 
 
+def et_bridges_batch_fused(graphs=None, *, row_ptr=None, col=None, voff=None, soff=None, slots=None,
+                           vertices=None, moff=None, max_vertices=None, max_slots=None, mask=None, ctx=None,
+                           counts=True):
+    """Bridges of many small graphs (at most ``FUSED_MAX_VERTICES`` vertices
+    and ``FUSED_MAX_SLOTS`` CSR slots each) in one kernel launch. Arguments
+    and results as for :func:`et_bridges_batch` (``vertices``: the host list
+    of vertex counts per graph, read back from ``voff`` when absent); the
+    bounds default to the largest graph's. ``moff``, the device int64 word
+    offsets of the graphs' masks, is uploaded from the slot counts when not
+    given (give it to capture the call in a graph: the upload's pinned
+    buffer would not outlive the capture)."""
+    ctx = ctx or default_context()
+    if graphs is not None:
+        if len(graphs) == 0:
+            raise ValueError("a batch needs at least one graph")
+        rps = [_dev(g[0], torch.int32, "row_ptr") for g in graphs]
+        cols = [_dev(g[1], torch.int32, "col") for g in graphs]
+        dev = rps[0].device
+        vs = [r.numel() - 1 for r in rps]
+        ss = [c.numel() for c in cols]
+        row_ptr = torch.cat(rps)
+        col = torch.cat(cols) if sum(ss) else torch.empty(0, dtype=torch.int32, device=dev)
+        voff = torch.tensor([0] + vs, dtype=torch.int64).cumsum(0).pin_memory().to(dev, non_blocking=True)
+        soff = torch.tensor([0] + ss, dtype=torch.int64).cumsum(0).pin_memory().to(dev, non_blocking=True)
+    else:
+        row_ptr = _dev(row_ptr, torch.int32, "row_ptr")
+        col = _dev(col, torch.int32, "col")
+        voff = _dev(voff, torch.int64, "voff")
+        soff = _dev(soff, torch.int64, "soff")
+        if soff.numel() != voff.numel():
+            raise ValueError("voff and soff must have the same length")
+        ss = list(slots) if slots is not None else torch.diff(soff).cpu().tolist()
+        vs = list(vertices) if vertices is not None else torch.diff(voff).cpu().tolist()
+    T = _i32(len(ss), "number of graphs")
+    n_total = _i32(row_ptr.numel() - T, "total vertex count", NODE_MAX)
+    nnz = _i32(col.numel(), "total CSR slot count")
+    if T < 1 or sum(ss) != nnz or sum(vs) != n_total:
+        raise ValueError("offsets do not match the concatenated arrays")
+    words = [(x + 31) // 32 for x in ss]
+    starts = [0]
+    for w in words:
+        starts.append(starts[-1] + w)
+    if moff is None:
+        moff = torch.tensor(starts, dtype=torch.int64).pin_memory().to(col.device, non_blocking=True)
+    else:
+        moff = _dev(moff, torch.int64, "moff")
+    total = starts[-1]
+    if mask is None:
+        mask = torch.empty(max(total, 1), dtype=torch.int32, device=col.device)
+    out = torch.empty(T, dtype=torch.int64, device=col.device) if counts else None
+    mv = _i32(max(vs) if max_vertices is None else max_vertices, "max_vertices")
+    ms = _i32(max(ss) if max_slots is None else max_slots, "max_slots")
+    _check(_lib.et_bridges_batch_fused(ctx.handle, _ptr(row_ptr), _ptr(col), _ptr(voff), _ptr(soff), _ptr(moff), T,
+                                       n_total, nnz, mv, ms, _ptr(mask), mask.numel(), _ptr(out) if counts else None,
+                                       _stream()), "et_bridges_batch_fused")
+    return mask, list(zip(starts[:-1], words)), out
+
+
 def et_bridges_ck(row_ptr, col, spanning="bfs", mask=None, ctx=None, count=True):
     """Bridges by Chaitanya-Kothapalli marking on a BFS forest
     (``spanning="bfs"``) or on the connectivity forest rooted by the Euler
@@ -662,6 +723,38 @@ class FusedBatchGraph:
     def replay(self):
         self.graph.replay()
         return self.out
+
+    def close(self):
+        torch.cuda.synchronize()
+        self.graph = None
+
+
+class BridgesFusedGraph:
+    """The one-launch graph batch (et_bridges_batch_fused) captured in a HIP
+    graph: each replay is one kernel node writing ``mask`` and ``counts``.
+    The context must not run another one-launch call while a replay is in
+    flight."""
+
+    def __init__(self, row_ptr, col, voff, soff, slots, vertices, ctx=None):
+        self.ctx = ctx or Context()
+        slots, vertices = list(slots), list(vertices)
+        words = [(x + 31) // 32 for x in slots]
+        starts = [0]
+        for w in words:
+            starts.append(starts[-1] + w)
+        self.moff = torch.tensor(starts, dtype=torch.int64, device=col.device)
+        self.inputs = (row_ptr, col, voff, soff, self.moff)
+        kw = dict(row_ptr=row_ptr, col=col, voff=voff, soff=soff, slots=slots, vertices=vertices, moff=self.moff,
+                  ctx=self.ctx)
+        et_bridges_batch_fused(**kw)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.mask, self.spans, self.counts = et_bridges_batch_fused(**kw)
+
+    def replay(self):
+        self.graph.replay()
+        return self.mask, self.counts
 
     def close(self):
         torch.cuda.synchronize()
