@@ -7,6 +7,8 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
+#include <utility>
 
 #include "et_internal.hpp"
 
@@ -169,6 +171,47 @@ void* fixed_scratch(int dev) {
   return g_fixed[dev];
 }
 }  // namespace
+
+namespace et {
+
+int persistent_grid(const void* kern, int threads, uint32_t lds, int64_t items, int* grid) {
+  struct DevInfo {
+    int max_lds = 0, cus = 0;
+  };
+  static std::mutex mu;
+  static std::map<int, DevInfo> devs;
+  static std::map<std::pair<int, const void*>, bool> attr_set;
+  static std::map<std::tuple<int, const void*, int, uint32_t>, int> occ;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ET_EHIP;
+  std::lock_guard<std::mutex> lock(mu);
+  auto d = devs.find(dev);
+  if (d == devs.end()) {
+    DevInfo info;
+    if (hipDeviceGetAttribute(&info.max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&info.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return ET_EHIP;
+    d = devs.emplace(dev, info).first;
+  }
+  if ((int)lds > d->second.max_lds) return ET_ESIZE;
+  if (!attr_set[{dev, kern}]) {
+    // allow every dynamic LDS size this device offers, once per kernel
+    if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, d->second.max_lds) != hipSuccess)
+      return ET_EHIP;
+    attr_set[{dev, kern}] = true;
+  }
+  const auto key = std::make_tuple(dev, kern, threads, lds);
+  auto o = occ.find(key);
+  if (o == occ.end()) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess) return ET_EHIP;
+    o = occ.emplace(key, std::max(per_cu, 1)).first;
+  }
+  *grid = (int)std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)o->second * d->second.cus));
+  return ET_OK;
+}
+
+}  // namespace et
 
 extern "C" {
 

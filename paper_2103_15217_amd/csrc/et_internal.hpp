@@ -354,6 +354,12 @@ int list_rank_arena(Ctx* c, void* arena, size_t bytes, const int32_t* succ, int3
                     int32_t nheads, int32_t* rank, hipStream_t s);
 int list_scan_generic(Ctx* c, const int32_t* succ, const int32_t* weights, int32_t len, const int32_t* heads,
                       int32_t nheads, int32_t* rank, int32_t* sum, hipStream_t s);
+// Grid of a persistent kernel (one launch, workgroups taking work items
+// from a counter): as many workgroups as stay resident on the current device
+// with `lds` bytes of dynamic LDS each, at most `items`. Device limits, the
+// kernel's LDS attribute and its occupancy are looked up once and cached.
+// ET_ESIZE if one workgroup cannot take `lds` bytes.
+int persistent_grid(const void* kern, int threads, uint32_t lds, int64_t items, int* grid);
 // small_bridges.hip: bridges of many graphs of at most 1024 vertices and 8192
 // CSR slots in one launch; moff[t] is graph t's first mask word
 int small_bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, const int64_t* voff, const int64_t* soff,

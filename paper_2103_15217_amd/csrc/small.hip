@@ -53,11 +53,13 @@ __host__ __device__ inline uint32_t al64(uint32_t x) { return (x + 63u) & ~63u; 
 // multiple of 64). Regions are reused as the phases go:
 //   p   parent u16[N]                                  (whole tree)
 //   rb  successor u16[2N], later head u32[N+1]
-//   rc  radix counters u32[kDigits][waves], later rank / down u16[2N] each,
+//   rc  radix counters u32[kDigits][waves], later per node the rank of its
+//       two half-edges and the down count at the first (u16[N] each),
 //       later parent path labels u16[N+1]
-//   rd  sort buffers u16[2][N], later inlabel, ascendant, depth u16[N] each
-//   rf  sublists: next, length, down u16[2][kSubMax] each
+//   rd  sort buffers u16[2][N], then the sublists (next, length, down
+//       u16[2][kSubMax] each), later inlabel, ascendant, depth u16[N] each
 //   sc  scalars and wavefront sums
+// (at N = 4096 about 73 KB: two 1024-lane workgroups share a compute unit)
 struct SmallLayout {
   uint32_t p, rb, rc, rd, rf, sc, total;
 };
@@ -70,11 +72,10 @@ __host__ __device__ inline SmallLayout small_layout(uint32_t N) {
   L.rb = at;
   at += al64(4 * N + 4);
   L.rc = at;
-  at += al64(8 * N > (uint32_t)(kDigits * kWavesMax * 4) ? 8 * N : (uint32_t)(kDigits * kWavesMax * 4));
+  at += al64(max(6 * N + 2, (uint32_t)(kDigits * kWavesMax * 4)));
   L.rd = at;
-  at += al64(6 * N);
-  L.rf = at;
-  at += al64(12 * kSubMax);
+  L.rf = at;  // the sublists live between the sort and the node statistics
+  at += al64(max(6 * N, (uint32_t)(12 * kSubMax)));
   L.sc = at;
   at += 256;
   L.total = at;
@@ -100,7 +101,7 @@ __device__ __forceinline__ uint64_t match_digit(bool valid, uint32_t d) {
 __device__ __forceinline__ uint16_t root_key(uint16_t p, uint32_t n) { return p == kEnd ? (uint16_t)n : p; }
 
 template <int kFT>
-__global__ __launch_bounds__(kFT) void k_small_batch(
+__global__ __launch_bounds__(kFT, kFT == 1024 ? 8 : 1) void k_small_batch(
     const int32_t* __restrict__ parent, const int64_t* __restrict__ off, int32_t T, int64_t n_total, uint32_t N,
     int32_t nmax, const int64_t* __restrict__ qoff, int64_t q_total, const int32_t* __restrict__ qx,
     const int32_t* __restrict__ qy, int32_t* __restrict__ out, int32_t* __restrict__ depth_out,
@@ -114,8 +115,9 @@ __global__ __launch_bounds__(kFT) void k_small_batch(
   uint16_t* SUCC = reinterpret_cast<uint16_t*>(lds + L.rb);
   uint32_t* HEAD = reinterpret_cast<uint32_t*>(lds + L.rb);
   uint32_t* CNT = reinterpret_cast<uint32_t*>(lds + L.rc);
-  uint16_t* RK = reinterpret_cast<uint16_t*>(lds + L.rc);
-  uint16_t* DN = RK + 2 * N;
+  uint16_t* R0 = reinterpret_cast<uint16_t*>(lds + L.rc);  // rank of 2c
+  uint16_t* R1 = R0 + N;                                     // rank of 2c + 1
+  uint16_t* D0 = R0 + 2 * N;                                 // down count through 2c
   uint16_t* PLAB = reinterpret_cast<uint16_t*>(lds + L.rc);
   uint16_t* ORD0 = reinterpret_cast<uint16_t*>(lds + L.rd);
   uint16_t* ORD1 = ORD0 + N;
@@ -330,8 +332,12 @@ __global__ __launch_bounds__(kFT) void k_small_batch(
           uint32_t e = e0;
           for (uint32_t steps = 0; steps < E; ++steps) {
             d += !(e & 1u);
-            RK[e] = (uint16_t)r;
-            DN[e] = (uint16_t)d;
+            if (e & 1u) {
+              R1[e >> 1] = (uint16_t)r;
+            } else {
+              R0[e >> 1] = (uint16_t)r;
+              D0[e >> 1] = (uint16_t)d;
+            }
             ++r;
             const uint32_t nx = SUCC[e];
             if (nx >= E || !((nx >> 1) & M)) break;
@@ -351,7 +357,7 @@ __global__ __launch_bounds__(kFT) void k_small_batch(
           pre = 0;
           size = (int32_t)n;
         } else {
-          const int32_t r0 = RK[2 * c], d0 = DN[2 * c], r1 = RK[2 * c + 1];
+          const int32_t r0 = R0[c], d0 = D0[c], r1 = R1[c];
           pre = d0;
           dep = 2 * d0 - r0 - 1;
           size = (r1 - r0 + 1) >> 1;
@@ -362,7 +368,7 @@ __global__ __launch_bounds__(kFT) void k_small_batch(
         if (pre_out) pre_out[base + c] = pre;
         if (size_out) size_out[base + c] = size;
       }
-      __syncthreads();  // RK / DN dead from here: PLAB takes RC
+      __syncthreads();  // the ranks are dead from here: PLAB takes RC
       for (uint32_t I = tid; I <= n; I += kFT) PLAB[I] = kEnd;
       __syncthreads();
       // path tops: head[label] = {parent of the top, its depth}, plab = the parent's label
@@ -487,21 +493,17 @@ int small_batch_run(Ctx* c, const int32_t* parent, const int64_t* off, int32_t T
   if (max_nodes < 1 || max_nodes > kFMax) return ET_ESIZE;
   const uint32_t N = al64((uint32_t)max_nodes);
   const uint32_t lds = small_layout(N).total;
-  int dev = 0, max_lds = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return ET_EHIP;
-  if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return ET_EHIP;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) return ET_EHIP;
   // 256 lanes hold four trees where 1024 lanes hold one; worth it once there
   // are more trees than compute units (one 1024-lane workgroup fits a unit)
   const bool narrow = max_nodes <= kFSmall && T > cus;
   const int threads = narrow ? 256 : 1024;
   const void* kern = narrow ? reinterpret_cast<const void*>(k_small_batch<256>)
                             : reinterpret_cast<const void*>(k_small_batch<1024>);
-  if ((int)lds > max_lds) return ET_ESIZE;
-  if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return ET_EHIP;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess) return ET_EHIP;
-  const int grid = (int)std::min<int64_t>(T, (int64_t)std::max(per_cu, 1) * cus);
+  int grid = 0;
+  const int rc = persistent_grid(kern, threads, lds, T, &grid);
+  if (rc) return rc;
   ET_PROF(c, s, "k_small_batch");
   if (narrow)
     hipLaunchKernelGGL(k_small_batch<256>, dim3(grid), dim3(256), lds, s, parent, off, T, n_total, N, max_nodes,

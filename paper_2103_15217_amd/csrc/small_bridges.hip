@@ -496,16 +496,9 @@ int small_bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, const 
   if (max_vertices > kGMaxV || max_slots > kGMaxS) return ET_ESIZE;
   const uint32_t N = a64((uint32_t)std::max(max_vertices, 1)), M = a64((uint32_t)std::max(max_slots, 1));
   const uint32_t lds = blayout(N, M).total;
-  int dev = 0, max_lds = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return ET_EHIP;
-  if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return ET_EHIP;
-  if ((int)lds > max_lds) return ET_ESIZE;
-  const void* kern = reinterpret_cast<const void*>(k_small_bridges);
-  if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return ET_EHIP;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_small_bridges, kBT, lds) != hipSuccess) return ET_EHIP;
-  const int grid = (int)std::min<int64_t>(T, (int64_t)std::max(per_cu, 1) * cus);
+  int grid = 0;
+  const int rc = persistent_grid(reinterpret_cast<const void*>(k_small_bridges), kBT, lds, T, &grid);
+  if (rc) return rc;
   ET_PROF(c, s, "k_small_bridges");
   hipLaunchKernelGGL(k_small_bridges, dim3(grid), dim3(kBT), lds, s, row_ptr, col, voff, soff, moff, T,
                      (int64_t)n_total, (int64_t)nnz_total, mask_words, N, M, max_vertices, max_slots, mask, counts,
