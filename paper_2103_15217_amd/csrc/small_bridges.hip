@@ -42,18 +42,21 @@ constexpr int kRLev = 6;             // sparse-table levels over at most 32 bloc
 __host__ __device__ inline uint32_t a64(uint32_t x) { return (x + 63u) & ~63u; }
 
 // LDS regions for graphs of at most N vertices and M slots (multiples of 64):
-//   rp u16[N+1], col u16[M], src u16[M]      the CSR and each slot's row
+//   rp u16[N+1], col u16[M]                   the CSR
 //   uf u32[N]                                 union-find parents, then roots
 //   tf, mb u32[M/32]                          forest-slot bits, bridge bits
 //   tptr u16[N+1], hs/tsl/tnb/ttw u16[2N]     forest half-edges per vertex
-//   nx u16[2][2N], dd u16[2][2N]              pointer jumping
-//   tour u16[2N], dc u32[2N]                  tour order, down-flag scan
+//                                             (tour order later takes hs)
+//   nx u16[2][2N], dd u16[2][2N]              pointer jumping; later the
+//                                             extremes per preorder position:
+//                                             amn/amx u32[N], pmn/smn/pmx/smx u16[N]
+//   dc u32[2N]                                scans (degrees, roots, down flags)
 //   pre/size/pslot/ridx/rl u16[N]             per vertex; root list
-//   amn/amx u32[N]                            per preorder position
-//   pmn/smn/pmx/smx u16[N], st u16[2][kRLev][N/32]
+//   st u16[2][kRLev][N/32]                    sparse tables over 32-position blocks
+// (about 77 KB at 1024 vertices and 8192 slots: two workgroups per compute unit)
 struct BLayout {
-  uint32_t rp, col, src, uf, tf, mb, tptr, hs, tsl, tnb, ttw, nx, dd, tour, dc, pre, size, pslot, ridx, rl, amn,
-      amx, pmn, smn, pmx, smx, st, sc, total;
+  uint32_t rp, col, uf, tf, mb, tptr, hs, tsl, tnb, ttw, nx, dd, tour, dc, pre, size, pslot, ridx, rl, amn, amx,
+      pmn, smn, pmx, smx, st, sc, total;
 };
 
 __host__ __device__ inline BLayout blayout(uint32_t N, uint32_t M) {
@@ -66,30 +69,31 @@ __host__ __device__ inline BLayout blayout(uint32_t N, uint32_t M) {
   };
   L.rp = take(2 * (N + 1));
   L.col = take(2 * M);
-  L.src = take(2 * M);
   L.uf = take(4 * N);
   L.tf = take(M / 8 + 4);
   L.mb = take(M / 8 + 4);
   L.tptr = take(2 * (N + 1));
   L.hs = take(4 * N);
+  L.tour = L.hs;  // the half-edges' rows are dead once successors and twins are known
   L.tsl = take(4 * N);
   L.tnb = take(4 * N);
   L.ttw = take(4 * N);
-  L.nx = take(8 * N);
-  L.dd = take(8 * N);
-  L.tour = take(4 * N);
+  // pointer jumping, then (once preorder and sizes are known) the extremes
+  L.nx = at;
+  L.dd = at + 8 * N;
+  L.amn = at;
+  L.amx = at + 4 * N;
+  L.pmn = at + 8 * N;
+  L.smn = at + 10 * N;
+  L.pmx = at + 12 * N;
+  L.smx = at + 14 * N;
+  at += a64(16 * N);
   L.dc = take(8 * N);
   L.pre = take(2 * N);
   L.size = take(2 * N);
   L.pslot = take(2 * N);
   L.ridx = take(2 * N);
   L.rl = take(2 * N);
-  L.amn = take(4 * N);
-  L.amx = take(4 * N);
-  L.pmn = take(2 * N);
-  L.smn = take(2 * N);
-  L.pmx = take(2 * N);
-  L.smx = take(2 * N);
   L.st = take(2 * 2 * kRLev * (N / kRB + 1));
   L.sc = take(256);
   L.total = at;
@@ -108,6 +112,17 @@ __device__ __forceinline__ uint32_t lower16(const uint16_t* a, uint32_t lo, uint
   return lo;
 }
 
+// row of slot k: the last v < n with rp[v] <= k (rows may be empty)
+__device__ __forceinline__ uint32_t row_of_slot(const uint16_t* rp, uint32_t n, uint32_t k) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (rp[mid] <= k) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 __device__ __forceinline__ uint32_t uf_find(uint32_t* uf, uint32_t x) {
   for (;;) {
     const uint32_t p = uf[x];
@@ -118,7 +133,7 @@ __device__ __forceinline__ uint32_t uf_find(uint32_t* uf, uint32_t x) {
   }
 }
 
-__global__ __launch_bounds__(kBT) void k_small_bridges(
+__global__ __launch_bounds__(kBT, 8) void k_small_bridges(
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const int64_t* __restrict__ voff,
     const int64_t* __restrict__ soff, const int64_t* __restrict__ moff, int32_t T, int64_t n_total,
     int64_t nnz_total, int64_t mask_words, uint32_t N, uint32_t M, int32_t vmax, int32_t smax,
@@ -128,7 +143,6 @@ __global__ __launch_bounds__(kBT) void k_small_bridges(
   const BLayout L = blayout(N, M);
   uint16_t* RP = reinterpret_cast<uint16_t*>(lds + L.rp);
   uint16_t* COL = reinterpret_cast<uint16_t*>(lds + L.col);
-  uint16_t* SRC = reinterpret_cast<uint16_t*>(lds + L.src);
   uint32_t* UF = reinterpret_cast<uint32_t*>(lds + L.uf);
   uint32_t* TF = reinterpret_cast<uint32_t*>(lds + L.tf);
   uint32_t* MB = reinterpret_cast<uint32_t*>(lds + L.mb);
@@ -215,14 +229,7 @@ __global__ __launch_bounds__(kBT) void k_small_bridges(
     __syncthreads();
     if (!SC[B_BAD] && n > 0) {
       for (uint32_t k = tid; k < m; k += kBT) {
-        // row of slot k: the last v with RP[v] <= k (rows may be empty)
-        uint32_t lo = 0, hi = n;
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (RP[mid] <= k) lo = mid;
-          else hi = mid;
-        }
-        SRC[k] = (uint16_t)lo;
+        const uint32_t lo = row_of_slot(RP, n, k);
         const uint32_t w = COL[k];
         if (k > RP[lo] && COL[k - 1] > w) SC[B_BAD] = 1;  // rows sorted
         const uint32_t tw = lower16(COL, RP[w], RP[w + 1], lo);
@@ -241,7 +248,7 @@ __global__ __launch_bounds__(kBT) void k_small_bridges(
       for (uint32_t v = tid; v < n; v += kBT) UF[v] = v;
       __syncthreads();
       for (uint32_t k = tid; k < m; k += kBT) {
-        const uint32_t u = SRC[k], w = COL[k];
+        const uint32_t u = row_of_slot(RP, n, k), w = COL[k];
         if (u >= w || (k > RP[u] && COL[k - 1] == w)) continue;  // one slot per u-w run, u < w
         uint32_t ru = uf_find(UF, u), rw = uf_find(UF, w);
         while (ru != rw) {
@@ -393,7 +400,7 @@ __global__ __launch_bounds__(kBT) void k_small_bridges(
           __syncthreads();
           for (uint32_t k = tid; k < m; k += kBT) {
             if ((TF[k >> 5] >> (k & 31)) & 1u) continue;
-            const uint32_t u = SRC[k], w = COL[k];
+            const uint32_t u = row_of_slot(RP, n, k), w = COL[k];
             if (TPTR[u + 1] == TPTR[u]) continue;  // a loop on a vertex without forest edges
             atomicMin(&AMN[PRE[u]], (uint32_t)PRE[w]);
             atomicMax(&AMX[PRE[u]], (uint32_t)PRE[w]);
@@ -456,7 +463,7 @@ __global__ __launch_bounds__(kBT) void k_small_bridges(
               }
             }
             if (mn != l || mx != r) continue;
-            const uint32_t u = SRC[k];
+            const uint32_t u = row_of_slot(RP, n, k);
             if (k + 1 < RP[u + 1] && COL[k + 1] == w) continue;  // a parallel edge is never a bridge
             const uint32_t tw = lower16(COL, RP[w], RP[w + 1], u);
             atomicOr(&MB[k >> 5], 1u << (k & 31));
