@@ -531,7 +531,9 @@ class GpuBackend:
     """The library on several HIP streams (one context per stream). Trees are
     built on stream 0 with context 0; their queries run on any stream after
     the build's event (LCA queries take no scratch and only read the tables);
-    bridge batches run on the stream of their own context."""
+    bridge batches run on the stream of their own context. A batch of one
+    tree or one graph goes through the single-instance calls (et_tree_build,
+    et_lca, et_bridges), which skip the batch's concatenation and splitting."""
 
     def __init__(self, dinp, streams=4, tuned=True):
         import torch
@@ -547,6 +549,7 @@ class GpuBackend:
         self.autotune = autotune
         self.rr = 0
         self.t0 = None
+        self.sched = None       # the scheduler driving this backend (set by it)
 
     def start(self):
         self.t0 = time.perf_counter()
@@ -555,12 +558,15 @@ class GpuBackend:
         return time.perf_counter() - self.t0
 
     def wait(self, until):
-        # spin briefly rather than sleep: a completion is only seen when the
-        # scheduler looks again, and a sleep of the OS's granularity would add
-        # its length to the latency of every job that finishes meanwhile
+        # spin rather than sleep (a sleep of the OS's granularity would add its
+        # length to the latency of every job that finishes meanwhile), and
+        # return as soon as a launch in flight completes, at an arrival or a
+        # deadline, or after 50 us at the latest
         end = self.t0 + min(until, self.now() + 5e-5)
+        events = [w["token"][0] for w in self.sched.inflight] if self.sched else []
         while time.perf_counter() < end:
-            pass
+            if any(e.query() for e in events):
+                return
 
     def finish(self):
         self.torch.cuda.synchronize()
@@ -588,6 +594,8 @@ class GpuBackend:
         n = sum(j.n for j in jobs)
         nnz = sum(j.nnz for j in jobs)
         words = sum((j.nnz + 31) // 32 for j in jobs)
+        if len(jobs) == 1:   # et_bridges on the resident CSR: its scratch and the mask
+            return et.bridges_footprint(n, nnz, 0, ctx=self.ctxs[0]) + 4 * max(words, 1)
         scratch = et.bridges_footprint(n, nnz, len(jobs), ctx=self.ctxs[0])
         return scratch + 4 * (n + len(jobs) + nnz + words) + 16 * (len(jobs) + 1)
 
@@ -597,17 +605,24 @@ class GpuBackend:
         st, ctx = self.streams[0], self.ctxs[0]
         parts = [self.dinp.trees[k] for k in keys]
         with torch.cuda.stream(st):
-            if self.tuned:
-                self.autotune.apply(ctx, "batch", size=sum(sizes))
-            parent = torch.cat(parts) if len(parts) > 1 else parts[0]
-            # offsets go up from pinned memory without waiting for the stream
-            h_offs = torch.tensor(np.concatenate([[0], np.cumsum(sizes)]), dtype=torch.int64).pin_memory()
-            offs = h_offs.to(parent.device, non_blocking=True)
-            tree = et.et_tree_build_batch(parent, offs, ctx=ctx)
+            if len(parts) == 1:
+                if self.tuned:
+                    self.autotune.apply(ctx, "single", size=sizes[0])
+                parent, keep = parts[0], ()
+                tree = et.et_tree_build(parent, ctx=ctx)
+            else:
+                if self.tuned:
+                    self.autotune.apply(ctx, "batch", size=sum(sizes))
+                parent = torch.cat(parts)
+                # offsets go up from pinned memory without waiting for the stream
+                h_offs = torch.tensor(np.concatenate([[0], np.cumsum(sizes)]), dtype=torch.int64).pin_memory()
+                offs = h_offs.to(parent.device, non_blocking=True)
+                keep = (offs, h_offs)
+                tree = et.et_tree_build_batch(parent, offs, ctx=ctx)
             ev = torch.cuda.Event()
             ev.record(st)
         # the inputs stay referenced until the build has completed
-        return (tree, ev), (ev, (parent, offs, h_offs)), self.build_io_bytes(sizes)
+        return (tree, ev), (ev, (parent,) + keep), self.build_io_bytes(sizes)
 
     def lca(self, handle, k, j):
         torch = self.torch
@@ -616,8 +631,12 @@ class GpuBackend:
         self.rr += 1
         with torch.cuda.stream(st):
             st.wait_event(ready)
-            qt = torch.full((j.nq,), k, dtype=torch.int32, device=j.qx.device)
-            out = tree.lca_batch(qt, j.qx, j.qy)
+            if tree.batch:
+                qt = torch.full((j.nq,), k, dtype=torch.int32, device=j.qx.device)
+                out = tree.lca_batch(qt, j.qx, j.qy)
+            else:
+                qt = None
+                out = tree.lca(j.qx, j.qy)
             ev = torch.cuda.Event()
             ev.record(st)
         return (ev, qt), out
@@ -628,9 +647,16 @@ class GpuBackend:
         self.rr += 1
         st, ctx = self.streams[i], self.ctxs[i]
         with torch.cuda.stream(st):
-            if self.tuned:
-                self.autotune.apply(ctx, "batch", size=sum(j.n for j in jobs))
-            mask, spans, _ = et.et_bridges_batch([self.dinp.graphs[j.key] for j in jobs], ctx=ctx, counts=False)
+            if len(jobs) == 1:
+                if self.tuned:
+                    self.autotune.apply(ctx, "single", size=jobs[0].n)
+                mask, _ = et.et_bridges(*self.dinp.graphs[jobs[0].key], ctx=ctx, count=False)
+                spans = [(0, mask.numel())]
+            else:
+                if self.tuned:
+                    self.autotune.apply(ctx, "batch", size=sum(j.n for j in jobs))
+                mask, spans, _ = et.et_bridges_batch([self.dinp.graphs[j.key] for j in jobs], ctx=ctx,
+                                                     counts=False)
             ev = torch.cuda.Event()
             ev.record(st)
         outs = []
