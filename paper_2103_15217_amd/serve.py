@@ -550,6 +550,7 @@ class GpuBackend:
         self.rr = 0
         self.t0 = None
         self.sched = None       # the scheduler driving this backend (set by it)
+        self.calls = collections.Counter()   # library calls made, by kind
 
     def start(self):
         self.t0 = time.perf_counter()
@@ -575,7 +576,8 @@ class GpuBackend:
 
     def report(self):
         pools = [c.pool_stats() for c in self.ctxs]
-        return {"pool_held_bytes": sum(p["held"] for p in pools), "pool_peak_live_bytes": max(p["peak_live"] for p in pools)}
+        return {"pool_held_bytes": sum(p["held"] for p in pools), "pool_peak_live_bytes": max(p["peak_live"] for p in pools),
+                "calls": dict(self.calls)}
 
     # sizes, from the library
     def tree_cost(self, sizes):
@@ -610,6 +612,7 @@ class GpuBackend:
                     self.autotune.apply(ctx, "single", size=sizes[0])
                 parent, keep = parts[0], ()
                 tree = et.et_tree_build(parent, ctx=ctx)
+                self.calls["et_tree_build"] += 1
             else:
                 if self.tuned:
                     self.autotune.apply(ctx, "batch", size=sum(sizes))
@@ -619,6 +622,7 @@ class GpuBackend:
                 offs = h_offs.to(parent.device, non_blocking=True)
                 keep = (offs, h_offs)
                 tree = et.et_tree_build_batch(parent, offs, ctx=ctx)
+                self.calls["et_tree_build_batch"] += 1
             ev = torch.cuda.Event()
             ev.record(st)
         # the inputs stay referenced until the build has completed
@@ -652,11 +656,13 @@ class GpuBackend:
                     self.autotune.apply(ctx, "single", size=jobs[0].n)
                 mask, _ = et.et_bridges(*self.dinp.graphs[jobs[0].key], ctx=ctx, count=False)
                 spans = [(0, mask.numel())]
+                self.calls["et_bridges"] += 1
             else:
                 if self.tuned:
                     self.autotune.apply(ctx, "batch", size=sum(j.n for j in jobs))
                 mask, spans, _ = et.et_bridges_batch([self.dinp.graphs[j.key] for j in jobs], ctx=ctx,
                                                      counts=False)
+                self.calls["et_bridges_batch"] += 1
             ev = torch.cuda.Event()
             ev.record(st)
         outs = []

@@ -22,25 +22,23 @@ def _d(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
 
 
-def test_served_results_equal_alone(oracle_mod):
+def _served_vs_alone(oracle_mod, rate, duration, seed, budget_trees, max_batch):
     import torch
     from paper_2103_15217_amd import serve
     dev = torch.device("cuda", 0)
-    bases = serve.make_bases(seed=3, count=10, tree_log2=(4, 15))
-    graphs = serve.make_graphs(seed=3, count=4, graph_log2=(8, 13))
-    jobs, specs = serve.make_trace(bases, graphs, rate=20000, duration=0.03, seed=3, qlog2=(0, 9))
-    assert len(jobs) > 200
+    bases = serve.make_bases(seed=seed, count=10, tree_log2=(4, 15))
+    graphs = serve.make_graphs(seed=seed, count=4, graph_log2=(8, 13))
+    jobs, specs = serve.make_trace(bases, graphs, rate=rate, duration=duration, seed=seed, qlog2=(0, 9))
     dinp = serve.DeviceInputs(bases, graphs, dev)
     dinp.prepare(jobs, specs)
     plain = serve.PlainExecutor(dinp, keep_results=True)
     plain.run(jobs)
-    # a budget of a few trees forces evictions, rebuilds and deferrals in the mix
-    budget = 3 * sum(serve.et.tree_footprint(1 << 15)) + (4 << 20)
-    served = serve.ServedExecutor(dinp, streams=3, budget_bytes=budget, keep_results=True, max_batch=5)
+    budget = budget_trees * sum(serve.et.tree_footprint(1 << 15)) + (4 << 20)
+    served = serve.ServedExecutor(dinp, streams=3, budget_bytes=budget, keep_results=True, max_batch=max_batch)
     stats = served.run(jobs)
     served.close()
     assert stats["completed"] == len(jobs)
-    assert stats["evictions"] > 0 and stats["over_budget"] == 0
+    assert stats["over_budget"] == 0
     assert stats["cold_fraction"] >= serve.cold_fraction(jobs) - 1e-9
     for j in jobs:
         a, b = plain.results[j.jid].numpy(), served.results[j.jid].numpy()
@@ -55,6 +53,23 @@ def test_served_results_equal_alone(oracle_mod):
         rp, col = graphs[j.key]
         ref, _ = oracle_mod.bridges(rp, col)
         assert np.array_equal(served.results[j.jid].numpy().view(np.uint32)[: len(ref)], ref)
+    return jobs, stats
+
+
+def test_served_results_equal_alone(oracle_mod):
+    # many jobs at once, and a budget of a few trees: evictions, rebuilds and
+    # deferrals in the mix, and the batched build and bridge calls
+    jobs, stats = _served_vs_alone(oracle_mod, rate=20000, duration=0.03, seed=3, budget_trees=3, max_batch=5)
+    assert len(jobs) > 200
+    assert stats["evictions"] > 0
+    assert stats["calls"].get("et_tree_build_batch", 0) > 0 and stats["calls"].get("et_bridges_batch", 0) > 0
+
+
+def test_served_single_jobs_equal_alone(oracle_mod):
+    # jobs far enough apart that most go out alone: the single-instance calls
+    jobs, stats = _served_vs_alone(oracle_mod, rate=300, duration=0.2, seed=4, budget_trees=3, max_batch=5)
+    assert len(jobs) > 30
+    assert stats["calls"].get("et_tree_build", 0) > 0 and stats["calls"].get("et_bridges", 0) > 0
 
 
 @pytest.mark.parametrize("n", [1, 2, 1000, 1 << 16, (1 << 20) + 7, 1 << 22])
