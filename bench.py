@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--graph-log2m", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-tree batched vs plain comparison")
+    ap.add_argument("--only-small-batches", action="store_true",
+                    help="of the batch components run only the one-launch sweeps (small trees, small graphs)")
     ap.add_argument("--batch-trees", type=int, default=4096)
     ap.add_argument("--batch-graphs", type=int, default=1024)
     ap.add_argument("--no-serve", action="store_true", help="skip the served vs plain trace replay")
@@ -299,7 +301,7 @@ def main():
     }
 
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
-    if not args.no_batch:
+    if not args.no_batch and not args.only_small_batches:
         log("batched forest: generating")
         result["components"]["batched"] = batched_vs_plain(args, et, bctx, d, dev)
     if not args.no_batch:
@@ -308,7 +310,7 @@ def main():
     if not args.no_batch:
         log("small-graph batches: one fused launch vs the multi-kernel batch")
         result["components"]["small_graph_batches"] = small_graph_batches(args, et, bctx, d)
-    if not args.no_batch:
+    if not args.no_batch and not args.only_small_batches:
         log("batched graphs: generating")
         result["components"]["bridges_batched"] = bridges_batched_vs_plain(args, et, bctx, d)
     if not args.no_engines:
