@@ -18,10 +18,13 @@
 //      parent; the first child under its parent's down half-edge), the same
 //      rule as the multi-kernel build;
 //   4. list ranking of the tour: both half-edges of every 2^k-th node (and
-//      the head) start a sublist that one lane walks, recording its length and down
-//      count; pointer jumping over the sublists gives suffix sums, hence each
-//      sublist's offset; a second walk writes every half-edge's rank and
-//      inclusive down count. The tour must reach all 2(n-1) half-edges;
+//      the head) start a sublist that one lane walks, recording its length
+//      and down count, and per half-edge its rank and inclusive down count
+//      within the sublist and (in place of its successor, which no other
+//      lane reads) the sublist's index; pointer jumping over the sublists
+//      gives suffix sums, hence each sublist's offset, which one pass over
+//      the nodes adds to the half-edges' local values. The tour must reach
+//      all 2(n-1) half-edges;
 //   5. depth, preorder, size and inlabel per node from the two ranks of its
 //      half-edges, the head table and parent path labels per inlabel path,
 //      the ascendants one path level at a time from the highest;
@@ -52,7 +55,8 @@ __host__ __device__ inline uint32_t al64(uint32_t x) { return (x + 63u) & ~63u; 
 // Byte offsets of the LDS regions for trees of at most N nodes (N a
 // multiple of 64). Regions are reused as the phases go:
 //   p   parent u16[N]                                  (whole tree)
-//   rb  successor u16[2N], later head u32[N+1]
+//   rb  successor u16[2N] (an entry becomes its half-edge's sublist index
+//       once walked), later head u32[N+1]
 //   rc  radix counters u32[kDigits][waves], later per node the rank of its
 //       two half-edges and the down count at the first (u16[N] each),
 //       later parent path labels u16[N+1]
@@ -277,9 +281,16 @@ __global__ __launch_bounds__(kFT, kFT == 1024 ? 8 : 1) void k_small_batch(
         if (valid) {
           uint32_t e = e0;
           for (;;) {
+            const uint32_t nx = SUCC[e];
+            SUCC[e] = (uint16_t)s;  // only this lane reads e's successor
+            if (e & 1u) {
+              R1[e >> 1] = (uint16_t)len;
+            } else {
+              R0[e >> 1] = (uint16_t)len;
+              D0[e >> 1] = (uint16_t)(dn + 1);
+            }
             ++len;
             dn += !(e & 1u);
-            const uint32_t nx = SUCC[e];
             if (nx == kEnd) break;
             if (nx >= E || len >= E) {
               SC[S_BAD] = 1;
@@ -323,27 +334,24 @@ __global__ __launch_bounds__(kFT, kFT == 1024 ? 8 : 1) void k_small_batch(
       }
       __syncthreads();
       if (!SC[S_FAIL]) {
-        // second walk: rank and inclusive down count of every half-edge
-        for (uint32_t s = tid; s < S; s += kFT) {
-          const uint32_t e0 = (s == Sreg) ? head : ((((s >> 1) << m) << 1) | (s & 1u));
-          const bool valid = (s == Sreg) ? ((head >> 1) & M) != 0 : (e0 < E && SUCC[e0] != kNoSucc);
-          if (!valid) continue;
-          uint32_t r = total - LN(cur)[s], d = total_dn - DS(cur)[s];
-          uint32_t e = e0;
-          for (uint32_t steps = 0; steps < E; ++steps) {
-            d += !(e & 1u);
-            if (e & 1u) {
-              R1[e >> 1] = (uint16_t)r;
-            } else {
-              R0[e >> 1] = (uint16_t)r;
-              D0[e >> 1] = (uint16_t)d;
-            }
-            ++r;
-            const uint32_t nx = SUCC[e];
-            if (nx >= E || !((nx >> 1) & M)) break;
-            e = nx;
+        // each half-edge's rank and inclusive down count: its sublist's
+        // offset plus its value within the sublist
+        for (uint32_t c = tid; c < n; c += kFT) {
+          if (c == root) continue;
+          const uint32_t s0 = SUCC[2 * c], s1 = SUCC[2 * c + 1];
+          if (s0 >= S || s1 >= S) {  // not walked: cannot happen once the tour covers every half-edge
+            SC[S_BAD] = 1;
+            continue;
           }
+          R0[c] = (uint16_t)(R0[c] + total - LN(cur)[s0]);
+          D0[c] = (uint16_t)(D0[c] + total_dn - DS(cur)[s0]);
+          R1[c] = (uint16_t)(R1[c] + total - LN(cur)[s1]);
         }
+      }
+      __syncthreads();
+      if (tid == 0 && SC[S_BAD] && !SC[S_FAIL]) {
+        flag(status, ST_UNREACHED);
+        SC[S_FAIL] = 1;
       }
       __syncthreads();
     }
