@@ -190,16 +190,17 @@ __device__ __forceinline__ int ctz32(uint32_t x) { return __ffs((int)x) - 1; }
 __device__ __forceinline__ int ctz64(uint64_t x) { return __ffsll((unsigned long long)x) - 1; }
 
 // (used by the one-launch small-instance kernels)
-// Exclusive scan of a[0..m) in place by a workgroup of kFT lanes; wsum:
-// kFT / 64 + 1 slots.
-template <int kFT>
-__device__ inline void wg_scan_excl(uint32_t* a, int m, int32_t* wsum) {
+// Exclusive scan in place by a workgroup of kFT lanes of the m values
+// a[at(0)], a[at(1)], ..., a[at(m - 1)] (at maps scan order to storage);
+// wsum: kFT / 64 + 1 slots.
+template <int kFT, typename At>
+__device__ inline void wg_scan_excl_at(uint32_t* a, int m, int32_t* wsum, At at) {
   constexpr int kFW = kFT / 64;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int per = (m + kFT - 1) / kFT;
   const int lo = min(tid * per, m), hi = min(lo + per, m);
   uint32_t sum = 0;
-  for (int i = lo; i < hi; ++i) sum += a[i];
+  for (int i = lo; i < hi; ++i) sum += a[at(i)];
   uint32_t incl = sum;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -221,11 +222,17 @@ __device__ inline void wg_scan_excl(uint32_t* a, int m, int32_t* wsum) {
   __syncthreads();
   uint32_t run = (uint32_t)wsum[w] + incl - sum;
   for (int i = lo; i < hi; ++i) {
-    const uint32_t x = a[i];
-    a[i] = run;
+    const uint32_t x = a[at(i)];
+    a[at(i)] = run;
     run += x;
   }
   __syncthreads();
+}
+
+// Exclusive scan of a[0..m) in place by a workgroup of kFT lanes.
+template <int kFT>
+__device__ inline void wg_scan_excl(uint32_t* a, int m, int32_t* wsum) {
+  wg_scan_excl_at<kFT>(a, m, wsum, [](int i) { return i; });
 }
 
 // In-block range-minimum masks: one bit per position of a block of 2^LOG

@@ -47,6 +47,7 @@ constexpr uint16_t kEnd = 0xffff;   // list end, no node, unused label
 constexpr uint16_t kNoSucc = 0xfffe;  // a half-edge id of the root (not on the tour)
 constexpr int kDigitBits = 7;
 constexpr int kDigits = 1 << kDigitBits;
+constexpr int kCP = kDigits + 1;    // a wavefront's digit counters: one row, padded so rows start in other banks
 constexpr int kSubMax = 1025;       // sublists: at most 1024 regular ones and the head's
 constexpr int kQPer = 4;            // queries a lane loads before answering them
 
@@ -57,7 +58,7 @@ __host__ __device__ inline uint32_t al64(uint32_t x) { return (x + 63u) & ~63u; 
 //   p   parent u16[N]                                  (whole tree)
 //   rb  successor u16[2N] (an entry becomes its half-edge's sublist index
 //       once walked), later head u32[N+1]
-//   rc  radix counters u32[kDigits][waves], later per node the rank of its
+//   rc  radix counters u32[waves][kDigits + 1], later per node the rank of its
 //       two half-edges and the down count at the first (u16[N] each),
 //       later parent path labels u16[N+1]
 //   rd  sort buffers u16[2][N], then the sublists (next, length, down
@@ -76,7 +77,7 @@ __host__ __device__ inline SmallLayout small_layout(uint32_t N) {
   L.rb = at;
   at += al64(4 * N + 4);
   L.rc = at;
-  at += al64(max(6 * N + 2, (uint32_t)(kDigits * kWavesMax * 4)));
+  at += al64(max(6 * N + 2, (uint32_t)(kCP * kWavesMax * 4)));
   L.rd = at;
   L.rf = at;  // the sublists live between the sort and the node statistics
   at += al64(max(6 * N, (uint32_t)(12 * kSubMax)));
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(kFT, kFT == 1024 ? 8 : 1) void k_small_batch(
       const int rounds = (int)(seg / 64);
       const uint64_t below = lanemask_lt();
       for (int sh = 0; sh < kbits; sh += kDigitBits) {
-        for (int i = tid; i < kDigits * kFW; i += kFT) CNT[i] = 0;
+        for (int i = tid; i < kCP * kFW; i += kFT) CNT[i] = 0;
         __syncthreads();
         uint32_t lr[kRoundsMax], dg[kRoundsMax];
         uint16_t vv[kRoundsMax];
@@ -217,20 +218,21 @@ __global__ __launch_bounds__(kFT, kFT == 1024 ? 8 : 1) void k_small_batch(
           const uint32_t d = valid ? ((uint32_t)root_key(P[v], n) >> sh) & (kDigits - 1) : 0u;
           const uint64_t peers = match_digit(valid, d);
           uint32_t old = 0;
-          if (valid) old = CNT[d * kFW + w];
+          if (valid) old = CNT[w * kCP + d];
           if (valid && lane == __ffsll((unsigned long long)peers) - 1)
-            CNT[d * kFW + w] = old + (uint32_t)__popcll(peers);
+            CNT[w * kCP + d] = old + (uint32_t)__popcll(peers);
           lr[r] = old + (uint32_t)__popcll(peers & below);
           dg[r] = d;
           vv[r] = v;
         }
         __syncthreads();
-        wg_scan_excl<kFT>(CNT, kDigits * kFW, SC + S_WSUM);
+        // digit-major: digit d of wavefront w is number d * kFW + w in the scan
+        wg_scan_excl_at<kFT>(CNT, kDigits * kFW, SC + S_WSUM, [](int i) { return (i % kFW) * kCP + i / kFW; });
 #pragma unroll
         for (int r = 0; r < kRoundsMax; ++r) {
           if (r >= rounds) break;
           const uint32_t idx = w * seg + r * 64 + lane;
-          if (idx < n) dst[CNT[dg[r] * kFW + w] + lr[r]] = vv[r];
+          if (idx < n) dst[CNT[w * kCP + dg[r]] + lr[r]] = vv[r];
         }
         __syncthreads();
         uint16_t* tmp = src;
