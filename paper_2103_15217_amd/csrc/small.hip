@@ -27,7 +27,7 @@
 //      all 2(n-1) half-edges;
 //   5. depth, preorder, size and inlabel per node from the two ranks of its
 //      half-edges, the head table and parent path labels per inlabel path,
-//      the ascendants one path level at a time from the highest;
+//      each node's ascendant from its chain of parent path labels;
 //   6. the tree's queries by the Schieber-Vishkin rule on the LDS tables.
 // Ids are below 2^16 here (a tree has at most 4096 nodes, 8192 half-edges),
 // so the LDS tables hold 16-bit entries.
@@ -397,22 +397,27 @@ __global__ __launch_bounds__(kFT, kFT == 1024 ? 8 : 1) void k_small_batch(
         }
       }
       __syncthreads();
-      // ascendants by label, highest level first
-      for (int lv = 31 - __clz((int)n); lv >= 0; --lv) {
-        for (uint32_t k = tid; ((2 * k + 1) << lv) <= n; k += kFT) {
-          const uint32_t I = (2 * k + 1) << lv;
-          const uint16_t pl = PLAB[I];
-          if (pl == kEnd) continue;
-          uint32_t up = 0;
-          if (pl != 0) {
-            if (pl <= n && (__ffs((int)pl) - 1) > lv) up = PLAB[pl];
-            else SC[S_BAD] = 1;
+      // ascendant of each node: the level bits of the labels on its chain of
+      // parent path labels (levels strictly rise along it: at most 16 links)
+      for (uint32_t v = tid; v < n; v += kFT) {
+        uint32_t I = INL[v], acc = 0;
+        for (int k = 0; k < 16; ++k) {
+          if (I < 1 || I > n) {  // flagged where the labels were made
+            SC[S_BAD] = 1;
+            break;
           }
-          PLAB[I] = (uint16_t)(up | (1u << lv));
+          const int lv = __ffs((int)I) - 1;
+          acc |= 1u << lv;
+          const uint32_t pl = PLAB[I];
+          if (pl == 0) break;  // the root's path
+          if (pl > n || (__ffs((int)pl) - 1) <= lv) {
+            SC[S_BAD] = 1;
+            break;
+          }
+          I = pl;
         }
-        __syncthreads();
+        ASC[v] = (uint16_t)acc;
       }
-      for (uint32_t v = tid; v < n; v += kFT) ASC[v] = PLAB[min((uint32_t)INL[v], n)];
       __syncthreads();
       if (tid == 0 && SC[S_BAD]) flag(status, ST_BAD_INDEX);
     }
