@@ -406,37 +406,53 @@ __global__ __launch_bounds__(kBT, 8) void k_small_bridges(
             atomicMax(&AMX[PRE[u]], (uint32_t)PRE[w]);
           }
           __syncthreads();
-          // in-block prefix / suffix extremes and the block extremes
+          // in-block prefix / suffix extremes by shuffles within 32-lane
+          // segments (one lane per position, a segment per block), then the
+          // sparse table over the at most 32 blocks by one wavefront
           const uint32_t nb = (P + kRB - 1) / kRB;
-          for (uint32_t b = tid; b < nb; b += kBT) {
-            const uint32_t lo = b * kRB, hi = min(lo + kRB, P);
-            uint32_t mn = 0xffffu, mx = 0;
-            for (uint32_t i = lo; i < hi; ++i) {
-              mn = min(mn, AMN[i]);
-              mx = max(mx, AMX[i]);
-              PMN[i] = (uint16_t)mn;
-              PMX[i] = (uint16_t)mx;
+          for (uint32_t i = tid; i < nb * kRB; i += kBT) {
+            const uint32_t j = i & (kRB - 1);
+            const uint32_t a = i < P ? AMN[i] : 0xffffu, x = i < P ? AMX[i] : 0u;
+            uint32_t pmn = a, pmx = x, smn = a, smx = x;
+#pragma unroll
+            for (int d = 1; d < kRB; d <<= 1) {
+              const uint32_t p0 = __shfl_up(pmn, d, kRB), p1 = __shfl_up(pmx, d, kRB);
+              const uint32_t s0 = __shfl_down(smn, d, kRB), s1 = __shfl_down(smx, d, kRB);
+              if (j >= (uint32_t)d) {
+                pmn = min(pmn, p0);
+                pmx = max(pmx, p1);
+              }
+              if (j + d < (uint32_t)kRB) {
+                smn = min(smn, s0);
+                smx = max(smx, s1);
+              }
             }
-            STMN(0)[b] = (uint16_t)mn;
-            STMX(0)[b] = (uint16_t)mx;
-            mn = 0xffffu;
-            mx = 0;
-            for (uint32_t i = hi; i-- > lo;) {
-              mn = min(mn, AMN[i]);
-              mx = max(mx, AMX[i]);
-              SMN[i] = (uint16_t)mn;
-              SMX[i] = (uint16_t)mx;
+            if (i < P) {
+              PMN[i] = (uint16_t)pmn;
+              PMX[i] = (uint16_t)pmx;
+              SMN[i] = (uint16_t)smn;
+              SMX[i] = (uint16_t)smx;
+            }
+            if (j == kRB - 1) {
+              STMN(0)[i / kRB] = (uint16_t)pmn;
+              STMX(0)[i / kRB] = (uint16_t)pmx;
             }
           }
           __syncthreads();
-          for (int l = 1; l < kRLev; ++l) {
-            for (uint32_t b = tid; b + (1u << l) <= nb; b += kBT) {
-              const uint32_t b2 = b + (1u << (l - 1));
-              STMN(l)[b] = min(STMN(l - 1)[b], STMN(l - 1)[b2]);
-              STMX(l)[b] = max(STMX(l - 1)[b], STMX(l - 1)[b2]);
+          if (tid < 64) {  // nb <= 32: one wavefront, one block per lane
+            uint32_t vmn = tid < nb ? STMN(0)[tid] : 0xffffu, vmx = tid < nb ? STMX(0)[tid] : 0u;
+            for (int l = 1; l < kRLev; ++l) {
+              const uint32_t h = 1u << (l - 1);
+              const uint32_t omn = __shfl_down(vmn, h), omx = __shfl_down(vmx, h);
+              vmn = min(vmn, omn);
+              vmx = max(vmx, omx);
+              if (tid + (1u << l) <= nb) {
+                STMN(l)[tid] = (uint16_t)vmn;
+                STMX(l)[tid] = (uint16_t)vmx;
+              }
             }
-            __syncthreads();
           }
+          __syncthreads();
           // the bridge test for the forest edge above every non-root vertex
           for (uint32_t w = tid; w < n; w += kBT) {
             const uint32_t k = PSLOT[w];
