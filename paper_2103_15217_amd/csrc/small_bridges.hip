@@ -267,28 +267,29 @@ __global__ __launch_bounds__(kBT, 8) void k_small_bridges(
       for (uint32_t v = tid; v < n; v += kBT) UF[v] = uf_find(UF, v);  // roots (the least id of each component)
       __syncthreads();
 
-      // 3. forest half-edges per vertex, in row order
-      for (uint32_t v = tid; v < n; v += kBT) {
-        uint32_t d = 0;
-        for (uint32_t k = RP[v]; k < RP[v + 1]; ++k) d += (TF[k >> 5] >> (k & 31)) & 1u;
-        DC[v] = d;
+      // 3. forest half-edges per vertex, in row order: rows are stored in
+      // slot order, so a forest slot's half-edge is its rank among the
+      // forest slots (forest bits before its word, then within the word)
+      const uint32_t nwd = (m + 31) / 32;
+      for (uint32_t i = tid; i < nwd; i += kBT) DC[i] = __popc(TF[i]);
+      __syncthreads();
+      const uint32_t wlast = DC[nwd - 1];
+      wg_scan_excl<kBT>(DC, (int)nwd, SC + B_WSUM);
+      const uint32_t Et = DC[nwd - 1] + wlast;
+      for (uint32_t v = tid; v <= n; v += kBT) {
+        const uint32_t k = RP[v];
+        TPTR[v] = (uint16_t)(k >= m ? Et : DC[k >> 5] + __popc(TF[k >> 5] & ((1u << (k & 31)) - 1u)));
+      }
+      for (uint32_t k = tid; k < m; k += kBT) {
+        const uint32_t bits = TF[k >> 5];
+        if (!((bits >> (k & 31)) & 1u)) continue;
+        const uint32_t h = DC[k >> 5] + __popc(bits & ((1u << (k & 31)) - 1u));
+        TSL[h] = (uint16_t)k;
+        TNB[h] = COL[k];
       }
       __syncthreads();
-      const uint32_t dlast = n ? DC[n - 1] : 0;
-      wg_scan_excl<kBT>(DC, (int)n, SC + B_WSUM);
-      for (uint32_t v = tid; v <= n; v += kBT) TPTR[v] = (uint16_t)(v < n ? DC[v] : DC[n - 1] + dlast);
-      __syncthreads();
-      const uint32_t Et = TPTR[n];
-      for (uint32_t v = tid; v < n; v += kBT) {
-        uint32_t h = TPTR[v];
-        for (uint32_t k = RP[v]; k < RP[v + 1]; ++k)
-          if ((TF[k >> 5] >> (k & 31)) & 1u) {
-            HS[h] = (uint16_t)v;
-            TSL[h] = (uint16_t)k;
-            TNB[h] = COL[k];
-            ++h;
-          }
-      }
+      for (uint32_t v = tid; v < n; v += kBT)
+        for (uint32_t h = TPTR[v]; h < TPTR[v + 1]; ++h) HS[h] = (uint16_t)v;
       __syncthreads();
       uint16_t* SUCC = NXa;  // buffer 0 of the pointer jumping starts as the successor array
       for (uint32_t h = tid; h < Et; h += kBT) {
@@ -370,14 +371,21 @@ __global__ __launch_bounds__(kBT, 8) void k_small_bridges(
           }
           __syncthreads();
           wg_scan_excl<kBT>(DC, (int)Et, SC + B_WSUM);  // down half-edges before each tour position
-          // preorder and subtree size: a down half-edge (u -> w) enters w
+          // preorder and subtree size: a down half-edge (u -> w) enters w;
+          // the bridge test also takes u and the slot of (w -> u), kept in
+          // the tour order's place (dead now)
+          uint16_t* PU = TOUR;
+          uint16_t* PTW = TOUR + N;
           for (uint32_t h = tid; h < Et; h += kBT) {
-            const uint32_t r = RK[h], rt = RK[TTW[h]];
+            const uint32_t t = TTW[h];
+            const uint32_t r = RK[h], rt = RK[t];
             if (r < rt) {
               const uint32_t w = TNB[h];
               PRE[w] = (uint16_t)(RIDX[UF[w]] + DC[r] + 1);
               SIZE[w] = (uint16_t)((rt - r + 1) >> 1);
               PSLOT[w] = TSL[h];
+              PU[w] = TNB[t];
+              PTW[w] = TSL[t];
             }
           }
           for (uint32_t i = tid; i < R; i += kBT) {
@@ -479,9 +487,9 @@ __global__ __launch_bounds__(kBT, 8) void k_small_bridges(
               }
             }
             if (mn != l || mx != r) continue;
-            const uint32_t u = row_of_slot(RP, n, k);
+            const uint32_t u = PU[w];
             if (k + 1 < RP[u + 1] && COL[k + 1] == w) continue;  // a parallel edge is never a bridge
-            const uint32_t tw = lower16(COL, RP[w], RP[w + 1], u);
+            const uint32_t tw = PTW[w];
             atomicOr(&MB[k >> 5], 1u << (k & 31));
             atomicOr(&MB[tw >> 5], 1u << (tw & 31));
             atomicAdd(&SC[B_CNT], 1);
