@@ -46,7 +46,9 @@ __host__ __device__ inline uint32_t a64(uint32_t x) { return (x + 63u) & ~63u; }
 //   uf u32[N]                                 union-find parents, then roots
 //   tf, mb u32[M/32]                          forest-slot bits, bridge bits
 //   tptr u16[N+1], hs/tsl/tnb/ttw u16[2N]     forest half-edges per vertex
-//                                             (tour order later takes hs)
+//                                             (tour order later takes hs,
+//                                             then each vertex's parent and
+//                                             the slot of its edge's twin)
 //   nx u16[2][2N], dd u16[2][2N]              pointer jumping; later the
 //                                             extremes per preorder position:
 //                                             amn/amx u32[N], pmn/smn/pmx/smx u16[N]
