@@ -87,7 +87,7 @@ def parse():
     ap.add_argument("--no-lists", action="store_true",
                     help="skip the plain vs weighted list ranking of the tours and of a random list")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
-    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-budget-gib", type=float, default=2.0,
                     help="device-memory budget of the continuous-batching server (GiB)")
     ap.add_argument("--serve-sweep", default="1000,4000,8000",
