@@ -587,6 +587,28 @@ def list_ranking(args, et, ctx, d, d_parent):
     return res
 
 
+def _small_first(b, limit):
+    """The batch with its trees of at most ``limit`` nodes first (stable):
+    a relabelling of tree ids, the order a batching host that sorts work by
+    size class would hand over. Queries stay grouped by tree."""
+    sizes = b["sizes"]
+    order = np.argsort(sizes > limit, kind="stable")
+    off = b["offsets"]
+    qs = np.searchsorted(b["qtree"], np.arange(len(sizes) + 1))
+    new_sizes = sizes[order]
+    new_off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    new_off[1:] = np.cumsum(new_sizes)
+    qn = np.diff(qs)[order]
+    parent = np.concatenate([b["parent"][off[t]:off[t + 1]] for t in order])
+    qx = np.concatenate([b["qx"][qs[t]:qs[t + 1]] for t in order])
+    qy = np.concatenate([b["qy"][qs[t]:qs[t + 1]] for t in order])
+    qtree = np.repeat(np.arange(len(sizes), dtype=np.int32), qn)
+    out = {"parent": parent, "offsets": new_off, "sizes": new_sizes, "qx": qx, "qy": qy, "qtree": qtree}
+    if "grasp" in b:
+        out["grasp"] = np.asarray(b["grasp"])[order]
+    return out
+
+
 def batched_vs_plain(args, et, ctx, d, dev):
     """4096 trees of log-uniform size in [2^6, 2^18] (grasp 1, 64 or n) with
     2^10..2^14 queries each: one batched build + one batched query launch
@@ -594,7 +616,7 @@ def batched_vs_plain(args, et, ctx, d, dev):
     import torch
     import gen
     t0 = time.time()
-    b = gen.forest_batch(args.batch_trees, seed=args.seed)
+    b = _small_first(gen.forest_batch(args.batch_trees, seed=args.seed), et.FUSED_MAX_NODES)
     log(f"batched forest: {int(b['offsets'][-1])} nodes generated in {time.time() - t0:.1f}s")
     T = len(b["sizes"])
     d_parent = d(b["parent"])
@@ -644,6 +666,24 @@ def batched_vs_plain(args, et, ctx, d, dev):
     graph_ok = bool(torch.equal(g.out, d_out))
     g.close()
     ctx.check()
+    # the trees that fit one workgroup through the one-launch kernel, the
+    # rest through the multi-kernel batch, in one HIP graph
+    sctx = et.Context()
+    sg = et.SplitBatchGraph(d_parent, off, qs, d_qx, d_qy, ctx=sctx)
+    sg.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        sg.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    split_ms = e0.elapsed_time(e1) / 5
+    split_ok = bool(torch.equal(sg.out, d_out))
+    split_trees = sg.split
+    sg.close()
+    sctx.check()
+    sctx.close()
     nodes, q = int(off[-1]), len(b["qx"])
     return {"trees": T, "nodes": nodes, "queries": q,
             "batched_ms": res["batched"]["gpu_ms"], "plain_ms": res["plain"]["gpu_ms"],
@@ -652,7 +692,10 @@ def batched_vs_plain(args, et, ctx, d, dev):
             "plain_nodes_per_s": nodes / (res["plain"]["gpu_ms"] * 1e-3),
             "batched_queries_per_s": q / (res["batched"]["gpu_ms"] * 1e-3),
             "speedup": res["plain"]["gpu_ms"] / res["batched"]["gpu_ms"],
-            "graph_ms": res["graph"]["gpu_ms"], "graph_matches_eager": graph_ok, **res["breakdown"]}
+            "graph_ms": res["graph"]["gpu_ms"], "graph_matches_eager": graph_ok,
+            "split_graph_ms": split_ms, "split_fused_trees": split_trees,
+            "split_fused_nodes": int(off[split_trees]), "split_fused_queries": int(qs[split_trees]),
+            "split_matches_batched": split_ok, **res["breakdown"]}
 
 
 def small_batches(args, et, ctx, d, dev):

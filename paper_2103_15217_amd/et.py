@@ -729,6 +729,83 @@ class FusedBatchGraph:
         self.graph = None
 
 
+class SplitBatchGraph:
+    """A batch of trees split by size and captured in one HIP graph: the
+    leading trees of at most ``FUSED_MAX_NODES`` nodes go through the
+    one-launch kernel (et_lca_batch_fused), the others through the
+    multi-kernel batched build and queries (et_tree_build_batch +
+    et_lca_batch), one after the other on the capturing stream.
+
+    ``offsets`` and ``qoffsets`` are host sequences of T + 1 int64 offsets
+    (trees concatenated in ``parent``, their queries grouped by tree in
+    ``qx``/``qy``); the caller orders the small trees first, as a batching
+    host does when it sorts work by size class (the split is the longest
+    such prefix). Answers land in ``out`` in query order. The tree-id and
+    offset arrays of the two parts are made once here; replays read the
+    same device buffers. The context (a new one unless ``ctx`` is given)
+    must run no other work while the graph lives."""
+
+    def __init__(self, parent, offsets, qoffsets, qx, qy, ctx=None):
+        import numpy as np
+        off = np.asarray(offsets, dtype=np.int64)
+        qoff = np.asarray(qoffsets, dtype=np.int64)
+        T = len(off) - 1
+        if T < 1 or len(qoff) != T + 1 or off[0] != 0 or qoff[0] != 0:
+            raise ValueError("offsets and qoffsets need T + 1 >= 2 entries starting at 0")
+        if off[-1] != parent.numel() or qoff[-1] != qx.numel() or qx.numel() != qy.numel():
+            raise ValueError("offsets or qoffsets do not match the arrays")
+        sizes = np.diff(off)
+        if (sizes < 1).any() or (np.diff(qoff) < 0).any():
+            raise ValueError("every tree needs a node; query offsets must not decrease")
+        big = np.nonzero(sizes > FUSED_MAX_NODES)[0]
+        k = int(big[0]) if len(big) else T  # trees [0, k) fit one workgroup
+        self.split = k
+        self.ctx = ctx or Context()
+        dev = parent.device
+        n_s, q_s = int(off[k]), int(qoff[k])
+        self.out = torch.empty_like(qx)
+        self._small = None
+        if k > 0:
+            self._small = (parent[:n_s], torch.from_numpy(off[:k + 1].copy()).to(dev),
+                           torch.from_numpy(qoff[:k + 1].copy()).to(dev), qx[:q_s], qy[:q_s],
+                           int(sizes[:k].max()), self.out[:q_s])
+        self._large = None
+        if k < T:
+            qt = np.repeat(np.arange(T - k, dtype=np.int32), np.diff(qoff[k:]))
+            self._large = (parent[n_s:], torch.from_numpy(off[k:] - off[k]).to(dev),
+                           torch.from_numpy(qt).to(dev), qx[q_s:], qy[q_s:], self.out[q_s:])
+        self.tree = None
+        self._run(keep=False)  # warm-up: fills the scratch pool, so the captured calls allocate nothing
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._run(keep=True)
+
+    def _run(self, keep):
+        if self._small is not None:
+            p, o, qo, x, y, mx, out = self._small
+            et_lca_batch_fused(p, o, qo, x, y, mx, out=out, ctx=self.ctx)
+        if self._large is not None:
+            p, o, qt, x, y, out = self._large
+            tree = et_tree_build_batch(p, o, ctx=self.ctx)
+            tree.lca_batch(qt, x, y, out=out)
+            if keep:
+                self.tree = tree  # the captured tables stay alive with the graph
+            else:
+                tree.free()
+
+    def replay(self):
+        self.graph.replay()
+        return self.out
+
+    def close(self):
+        torch.cuda.synchronize()
+        self.graph = None
+        if self.tree is not None:
+            self.tree.free()
+            self.tree = None
+
+
 class BridgesFusedGraph:
     """The one-launch graph batch (et_bridges_batch_fused) captured in a HIP
     graph: each replay is one kernel node writing ``mask`` and ``counts``.

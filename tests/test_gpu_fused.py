@@ -200,3 +200,55 @@ def test_host_argument_errors(lib):
     with pytest.raises(lib.EtError) as e:
         lib.et_lca_batch_fused(big, z64, z64, z32, z32, 100)  # 300 nodes cannot be one tree of <= 100
     assert e.value.code == lib.et.ET_EINVAL
+
+
+@pytest.mark.parametrize("n_small,n_large,seed", [(300, 20, 41), (40, 0, 42), (0, 6, 43)])
+def test_split_batch_graph(lib, oracle_mod, n_small, n_large, seed):
+    """Trees that fit one workgroup first (one-launch kernel), larger ones
+    after (multi-kernel batch), captured in one HIP graph: every answer
+    equals the multi-kernel batch's on the same batch and, tree by tree on a
+    sample, the oracle's; replays with eager work between them agree."""
+    import torch
+    rng = np.random.default_rng(seed)
+    sizes = np.concatenate([rng.integers(1, lib.et.FUSED_MAX_NODES + 1, size=n_small),
+                            rng.integers(lib.et.FUSED_MAX_NODES + 1, 20000, size=n_large)]).astype(int)
+    parents = [gen.random_tree(int(s), [None, 1, 64][i % 3], seed=1000 * seed + i) for i, s in enumerate(sizes)]
+    batch = _batch_from_trees(parents, [int(x) for x in rng.integers(0, 400, size=len(sizes))], seed=seed)
+    T = len(sizes)
+    qoff = _qoff(batch["qtree"], T)
+    d_parent, d_qx, d_qy = _dev(batch["parent"]), _dev(batch["qx"]), _dev(batch["qy"])
+    ctx = lib.Context()
+    g = lib.SplitBatchGraph(d_parent, batch["offsets"], qoff, d_qx, d_qy, ctx=ctx)
+    try:
+        assert g.split == n_small
+        tree = lib.et_tree_build_batch(d_parent, _dev(batch["offsets"], np.int64))
+        want = tree.lca_batch(_dev(batch["qtree"]), d_qx, d_qy).cpu().numpy()
+        tree.free()
+        lib.default_context().check()
+        small = gen.forest_batch(5, seed=seed, log2_min=4, log2_max=8, qlog2_min=2, qlog2_max=6)
+        first_small = run_fused(lib, small, 256)[0]
+        for _ in range(3):
+            g.out.fill_(-7)
+            g.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(g.out.cpu().numpy(), want)
+            assert np.array_equal(run_fused(lib, small, 256)[0], first_small)  # eager work in between
+        ctx.check()
+        off = batch["offsets"]
+        sample = sorted(set(range(0, T, 7)) | set(range(n_small, T)))
+        for t in sample:
+            qa, qb = int(qoff[t]), int(qoff[t + 1])
+            if qb > qa:
+                p = batch["parent"][int(off[t]):int(off[t + 1])]
+                assert np.array_equal(want[qa:qb], oracle_mod.lca_offline(p, batch["qx"][qa:qb], batch["qy"][qa:qb])), t
+    finally:
+        g.close()
+        ctx.close()
+
+
+def test_split_batch_graph_rejects_bad_offsets(lib):
+    z = _dev(np.zeros(4, dtype=np.int32))
+    with pytest.raises(ValueError):
+        lib.SplitBatchGraph(_dev(np.array([-1, 0, 0], dtype=np.int32)), [0, 2], [0, 4], z, z)  # 3 nodes, offsets say 2
+    with pytest.raises(ValueError):
+        lib.SplitBatchGraph(_dev(np.array([-1, 0], dtype=np.int32)), [0, 2], [0, 2, 4], z, z)  # qoffsets too long
