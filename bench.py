@@ -84,6 +84,8 @@ def parse():
                     help="skip the edge-list (DCEL construction) build comparison")
     ap.add_argument("--no-naive", action="store_true",
                     help="skip the naive (climbing) LCA comparison and its depth and q:n sweeps")
+    ap.add_argument("--no-concurrent", action="store_true",
+                    help="skip the same step with its independent jobs on two streams")
     ap.add_argument("--no-lists", action="store_true",
                     help="skip the plain vs weighted list ranking of the tours and of a random list")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -301,6 +303,10 @@ def main():
     }
 
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
+    if not args.no_concurrent:
+        log("the step's independent jobs on two streams")
+        result["components"]["concurrent_step"] = concurrent_step(args, et, d_parent, d_qx, d_qy, d_rp, d_col,
+                                                                  ms_per_step, elements)
     if not args.no_batch and not args.only_small_batches:
         log("batched forest: generating")
         result["components"]["batched"] = batched_vs_plain(args, et, bctx, d, dev)
@@ -585,6 +591,68 @@ def list_ranking(args, et, ctx, d, d_parent):
     ctx.check()
     log(f"list ranking 2^{args.log2n + 1}: rank {r['rank_ms']:.3f} ms, weighted {r['scan_ms']:.3f} ms")
     return res
+
+
+def concurrent_step(args, et, d_parent, d_qx, d_qy, d_rp, d_col, seq_ms, elements):
+    """The timed step's four independent jobs (the three trees, each built,
+    queried and freed, and the bridges) split over two streams, each with
+    its own context: the latency-bound kernels and launch gaps of one
+    stream overlap the other's work. Answers are compared with the same
+    jobs run one after another on one stream. The headline step stays
+    sequential, so its per-kernel times are the kernels' own."""
+    import torch
+    from paper_2103_15217_amd import autotune
+    dev = d_qx.device
+    q = d_qx.numel()
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    ctxs = []
+    for st in streams:
+        with torch.cuda.stream(st):
+            c = et.Context()
+            if not args.default_params:
+                autotune.apply(c, "single")
+            ctxs.append(c)
+    outs = [torch.empty(q, dtype=torch.int32, device=dev) for _ in d_parent]
+    mask = torch.empty(max((d_col.numel() + 31) // 32, 1), dtype=torch.int32, device=dev)
+    jobs = [("tree", i) for i in range(len(d_parent))] + [("bridges", None)]
+
+    def run(nstreams):
+        main = torch.cuda.current_stream()
+        for st in streams[:nstreams]:
+            st.wait_stream(main)
+        for j, (kind, i) in enumerate(jobs):
+            st, c = streams[j % nstreams], ctxs[j % nstreams]
+            with torch.cuda.stream(st):
+                if kind == "tree":
+                    t = et.et_tree_build(d_parent[i], ctx=c)
+                    t.lca(d_qx, d_qy, out=outs[i])
+                    t.free()
+                else:
+                    et.et_bridges(d_rp, d_col, mask=mask, ctx=c, count=False)
+        for st in streams[:nstreams]:
+            main.wait_stream(st)
+
+    run(1)
+    torch.cuda.synchronize()
+    ref = [o.clone() for o in outs] + [mask.clone()]
+    for _ in range(3):
+        run(2)
+    torch.cuda.synchronize()
+    reps = max(5, min(args.steps, 20))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        run(2)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    same = all(torch.equal(a, b) for a, b in zip(ref, outs + [mask]))
+    for c in ctxs:
+        c.check()
+        c.close()
+    return {"streams": 2, "jobs_per_stream": [[f"{k}{'' if i is None else i}" for k, i in jobs[s::2]] for s in range(2)],
+            "ms_per_step": ms, "sequential_ms_per_step": seq_ms, "elements_per_s": elements / (ms * 1e-3),
+            "speedup_over_sequential": seq_ms / ms, "answers_equal": same}
 
 
 def _small_first(b, limit):
