@@ -737,6 +737,9 @@ def batched_vs_plain(args, et, ctx, d, dev):
     # the trees that fit one workgroup through the one-launch kernel, the
     # rest through the multi-kernel batch, in one HIP graph
     sctx = et.Context()
+    if not args.default_params:
+        from paper_2103_15217_amd import autotune
+        autotune.apply(sctx, "batch")  # the shapes the batched path runs with
     sg = et.SplitBatchGraph(d_parent, off, qs, d_qx, d_qy, ctx=sctx)
     sg.replay()
     torch.cuda.synchronize()
