@@ -50,3 +50,25 @@ def test_multi_gpu_request_is_refused():
     p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert p.returncode == 2 and "one GPU" in p.stderr
+
+
+def test_small_first_moves_whole_trees():
+    """The 4096-tree batch handed over with its small trees first: every
+    tree keeps its parents and its queries, only the tree order changes."""
+    import numpy as np
+    import gen
+    b = gen.forest_batch(120, seed=3, log2_min=6, log2_max=14, qlog2_min=0, qlog2_max=6)
+    limit = 4096
+    r = bench._small_first(b, limit)
+    order = np.argsort(b["sizes"] > limit, kind="stable")
+    k = int(np.sum(b["sizes"] <= limit))
+    assert 0 < k < len(order)
+    assert (r["sizes"][:k] <= limit).all() and (r["sizes"][k:] > limit).all()
+    assert r["offsets"][0] == 0 and r["offsets"][-1] == b["offsets"][-1]
+    qs = np.searchsorted(b["qtree"], np.arange(len(order) + 1))
+    rqs = np.searchsorted(r["qtree"], np.arange(len(order) + 1))
+    for i, t in enumerate(order):
+        assert np.array_equal(r["parent"][r["offsets"][i]:r["offsets"][i + 1]],
+                              b["parent"][b["offsets"][t]:b["offsets"][t + 1]])
+        assert np.array_equal(r["qx"][rqs[i]:rqs[i + 1]], b["qx"][qs[t]:qs[t + 1]])
+        assert np.array_equal(r["qy"][rqs[i]:rqs[i + 1]], b["qy"][qs[t]:qs[t + 1]])
