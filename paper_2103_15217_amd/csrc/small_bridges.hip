@@ -49,6 +49,9 @@ __host__ __device__ inline uint32_t a64(uint32_t x) { return (x + 63u) & ~63u; }
 //                                             (tour order later takes hs,
 //                                             then each vertex's parent and
 //                                             the slot of its edge's twin)
+//   row u16[M]                                the row of every slot while
+//                                             the CSR is checked and the
+//                                             forest made; then
 //   nx u16[2][2N], dd u16[2][2N]              pointer jumping; later the
 //                                             extremes per preorder position:
 //                                             amn/amx u32[N], pmn/smn/pmx/smx u16[N]
@@ -58,7 +61,7 @@ __host__ __device__ inline uint32_t a64(uint32_t x) { return (x + 63u) & ~63u; }
 // (about 77 KB at 1024 vertices and 8192 slots: two workgroups per compute unit)
 struct BLayout {
   uint32_t rp, col, uf, tf, mb, tptr, hs, tsl, tnb, ttw, nx, dd, tour, dc, pre, size, pslot, ridx, rl, amn, amx,
-      pmn, smn, pmx, smx, st, sc, total;
+      pmn, smn, pmx, smx, row, st, sc, total;
 };
 
 __host__ __device__ inline BLayout blayout(uint32_t N, uint32_t M) {
@@ -89,7 +92,8 @@ __host__ __device__ inline BLayout blayout(uint32_t N, uint32_t M) {
   L.smn = at + 10 * N;
   L.pmx = at + 12 * N;
   L.smx = at + 14 * N;
-  at += a64(16 * N);
+  L.row = at;  // before any of these: the row of every slot, u16[M]
+  at += a64(max(16 * N, 2 * M));
   L.dc = take(8 * N);
   L.pre = take(2 * N);
   L.size = take(2 * N);
@@ -125,6 +129,42 @@ __device__ __forceinline__ uint32_t row_of_slot(const uint16_t* rp, uint32_t n, 
   return lo;
 }
 
+// Inclusive prefix maximum of the u16 values a[0..m) in place by the
+// workgroup; wsum: kBW slots.
+__device__ inline void wg_prefix_max_u16(uint16_t* a, int m, int32_t* wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int per = (m + kBT - 1) / kBT;
+  const int lo = min(tid * per, m), hi = min(lo + per, m);
+  uint32_t mx = 0;
+  for (int i = lo; i < hi; ++i) mx = max(mx, (uint32_t)a[i]);
+  uint32_t incl = mx;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t v = __shfl_up(incl, d);
+    if (lane >= d) incl = max(incl, v);
+  }
+  if (lane == 63) wsum[w] = (int32_t)incl;
+  __syncthreads();
+  if (tid < 64) {
+    uint32_t x = tid < kBW ? (uint32_t)wsum[tid] : 0u;
+#pragma unroll
+    for (int d = 1; d < kBW; d <<= 1) {
+      const uint32_t y = __shfl_up(x, d);
+      if (lane >= d) x = max(x, y);
+    }
+    const uint32_t before = __shfl_up(x, 1);  // the waves before this one
+    if (tid < kBW) wsum[tid] = (int32_t)(tid == 0 ? 0u : before);
+  }
+  __syncthreads();
+  const uint32_t lanes_before = __shfl_up(incl, 1);
+  uint32_t run = max((uint32_t)wsum[w], lane == 0 ? 0u : lanes_before);
+  for (int i = lo; i < hi; ++i) {
+    run = max(run, (uint32_t)a[i]);
+    a[i] = (uint16_t)run;
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ uint32_t uf_find(uint32_t* uf, uint32_t x) {
   for (;;) {
     const uint32_t p = uf[x];
@@ -154,6 +194,7 @@ __global__ __launch_bounds__(kBT, 8) void k_small_bridges(
   uint16_t* TNB = reinterpret_cast<uint16_t*>(lds + L.tnb);
   uint16_t* TTW = reinterpret_cast<uint16_t*>(lds + L.ttw);
   uint16_t* NXa = reinterpret_cast<uint16_t*>(lds + L.nx);
+  uint16_t* ROW = reinterpret_cast<uint16_t*>(lds + L.row);
   uint16_t* DDa = reinterpret_cast<uint16_t*>(lds + L.dd);
   uint16_t* TOUR = reinterpret_cast<uint16_t*>(lds + L.tour);
   uint32_t* DC = reinterpret_cast<uint32_t*>(lds + L.dc);
@@ -230,8 +271,16 @@ __global__ __launch_bounds__(kBT, 8) void k_small_bridges(
       if (RP[v] > RP[v + 1]) SC[B_BAD] = 1;
     __syncthreads();
     if (!SC[B_BAD] && n > 0) {
+      // the row of every slot: each non-empty row's first slot marked with
+      // the row, then a prefix maximum (rows are stored in vertex order)
+      for (uint32_t k = tid; k < m; k += kBT) ROW[k] = 0;
+      __syncthreads();
+      for (uint32_t v = tid; v < n; v += kBT)
+        if (RP[v] < RP[v + 1]) ROW[RP[v]] = (uint16_t)v;
+      __syncthreads();
+      wg_prefix_max_u16(ROW, (int)m, SC + B_WSUM);
       for (uint32_t k = tid; k < m; k += kBT) {
-        const uint32_t lo = row_of_slot(RP, n, k);
+        const uint32_t lo = ROW[k];
         const uint32_t w = COL[k];
         if (k > RP[lo] && COL[k - 1] > w) SC[B_BAD] = 1;  // rows sorted
         const uint32_t tw = lower16(COL, RP[w], RP[w + 1], lo);
@@ -250,7 +299,7 @@ __global__ __launch_bounds__(kBT, 8) void k_small_bridges(
       for (uint32_t v = tid; v < n; v += kBT) UF[v] = v;
       __syncthreads();
       for (uint32_t k = tid; k < m; k += kBT) {
-        const uint32_t u = row_of_slot(RP, n, k), w = COL[k];
+        const uint32_t u = ROW[k], w = COL[k];
         if (u >= w || (k > RP[u] && COL[k - 1] == w)) continue;  // one slot per u-w run, u < w
         uint32_t ru = uf_find(UF, u), rw = uf_find(UF, w);
         while (ru != rw) {
