@@ -61,8 +61,9 @@ __host__ __device__ inline uint32_t al64(uint32_t x) { return (x + 63u) & ~63u; 
 //   rc  radix counters u32[waves][kDigits + 1], later per node the rank of its
 //       two half-edges and the down count at the first (u16[N] each),
 //       later parent path labels u16[N+1]
-//   rd  sort buffers u16[2][N], then the sublists (next, length, down
-//       u16[2][kSubMax] each), later inlabel, ascendant, depth u16[N] each
+//   rd  sort buffers u16[2][N], then the sublists (next u16[2][kSubMax],
+//       length and down count packed u32[2][kSubMax]), later inlabel,
+//       ascendant, depth u16[N] each
 //   sc  scalars and wavefront sums
 // (at N = 4096 about 73 KB: two 1024-lane workgroups share a compute unit)
 struct SmallLayout {
@@ -129,11 +130,12 @@ __global__ __launch_bounds__(kFT, kFT == 1024 ? 8 : 1) void k_small_batch(
   uint16_t* INL = reinterpret_cast<uint16_t*>(lds + L.rd);
   uint16_t* ASC = INL + N;
   uint16_t* DEP = ASC + N;
-  // sublist next / length / down count, two buffers each (pointer jumping)
+  // sublist next, and length << 16 | down count (both below 2^16, so one
+  // 32-bit add sums both), two buffers each (pointer jumping)
   uint16_t* SUB = reinterpret_cast<uint16_t*>(lds + L.rf);
+  uint32_t* LDa = reinterpret_cast<uint32_t*>(lds + L.rf + 4 * kSubMax);
 #define NX(b) (SUB + (b) * kSubMax)
-#define LN(b) (SUB + (2 + (b)) * kSubMax)
-#define DS(b) (SUB + (4 + (b)) * kSubMax)
+#define LD(b) (LDa + (b) * kSubMax)
   int32_t* SC = reinterpret_cast<int32_t*>(lds + L.sc);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 
@@ -306,8 +308,7 @@ __global__ __launch_bounds__(kFT, kFT == 1024 ? 8 : 1) void k_small_batch(
           }
         }
         NX(0)[s] = (uint16_t)nxs;
-        LN(0)[s] = (uint16_t)len;
-        DS(0)[s] = (uint16_t)dn;
+        LD(0)[s] = (len << 16) | dn;
       }
       __syncthreads();
       // suffix sums along the sublist list by pointer jumping
@@ -318,18 +319,16 @@ __global__ __launch_bounds__(kFT, kFT == 1024 ? 8 : 1) void k_small_batch(
           const uint16_t nx = NX(cur)[s];
           if (nx != kEnd && nx < S) {
             NX(cur ^ 1)[s] = NX(cur)[nx];
-            LN(cur ^ 1)[s] = (uint16_t)(LN(cur)[s] + LN(cur)[nx]);
-            DS(cur ^ 1)[s] = (uint16_t)(DS(cur)[s] + DS(cur)[nx]);
+            LD(cur ^ 1)[s] = LD(cur)[s] + LD(cur)[nx];
           } else {
             NX(cur ^ 1)[s] = kEnd;
-            LN(cur ^ 1)[s] = LN(cur)[s];
-            DS(cur ^ 1)[s] = DS(cur)[s];
+            LD(cur ^ 1)[s] = LD(cur)[s];
           }
         }
         __syncthreads();
         cur ^= 1;
       }
-      const uint32_t total = LN(cur)[hsub], total_dn = DS(cur)[hsub];
+      const uint32_t total = LD(cur)[hsub] >> 16, total_dn = LD(cur)[hsub] & 0xffffu;
       if (tid == 0 && (SC[S_BAD] || total != E - 2)) {
         flag(status, ST_UNREACHED);
         SC[S_FAIL] = 1;
@@ -345,9 +344,10 @@ __global__ __launch_bounds__(kFT, kFT == 1024 ? 8 : 1) void k_small_batch(
             SC[S_BAD] = 1;
             continue;
           }
-          R0[c] = (uint16_t)(R0[c] + total - LN(cur)[s0]);
-          D0[c] = (uint16_t)(D0[c] + total_dn - DS(cur)[s0]);
-          R1[c] = (uint16_t)(R1[c] + total - LN(cur)[s1]);
+          const uint32_t l0 = LD(cur)[s0];
+          R0[c] = (uint16_t)(R0[c] + total - (l0 >> 16));
+          D0[c] = (uint16_t)(D0[c] + total_dn - (l0 & 0xffffu));
+          R1[c] = (uint16_t)(R1[c] + total - (LD(cur)[s1] >> 16));
         }
       }
       __syncthreads();
@@ -490,8 +490,7 @@ __global__ __launch_bounds__(kFT, kFT == 1024 ? 8 : 1) void k_small_batch(
     }
   }
 #undef NX
-#undef LN
-#undef DS
+#undef LD
 }
 
 }  // namespace
