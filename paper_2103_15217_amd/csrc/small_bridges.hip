@@ -52,7 +52,9 @@ __host__ __device__ inline uint32_t a64(uint32_t x) { return (x + 63u) & ~63u; }
 //   row u16[M]                                the row of every slot while
 //                                             the CSR is checked and the
 //                                             forest made; then
-//   nx u16[2][2N], dd u16[2][2N]              pointer jumping; later the
+//   nx, dd: u32[2N] each                      the successors (u16, in dd),
+//                                             then pointer jumping over
+//                                             next << 16 | distance; later the
 //                                             extremes per preorder position:
 //                                             amn/amx u32[N], pmn/smn/pmx/smx u16[N]
 //   dc u32[2N]                                scans (degrees, roots, down flags)
@@ -342,7 +344,7 @@ __global__ __launch_bounds__(kBT, 8) void k_small_bridges(
       for (uint32_t v = tid; v < n; v += kBT)
         for (uint32_t h = TPTR[v]; h < TPTR[v + 1]; ++h) HS[h] = (uint16_t)v;
       __syncthreads();
-      uint16_t* SUCC = NXa;  // buffer 0 of the pointer jumping starts as the successor array
+      uint16_t* SUCC = DDa;  // the successors, in the upper half of the pointer-jumping region
       for (uint32_t h = tid; h < Et; h += kBT) {
         const uint32_t u = HS[h], w = TNB[h];
         const uint32_t tw = lower16(TNB, TPTR[w], TPTR[w + 1], u);
@@ -376,42 +378,41 @@ __global__ __launch_bounds__(kBT, 8) void k_small_bridges(
 
       if (R > 0) {
         // 4. ranks: distance to the end by pointer jumping
-        uint16_t* NX0 = NXa;
-        uint16_t* NX1 = NXa + 2 * N;
-        uint16_t* DD0 = DDa;
-        uint16_t* DD1 = DDa + 2 * N;
-        for (uint32_t h = tid; h < Et; h += kBT) DD0[h] = NX0[h] == kNil ? 0 : 1;
+        // (next << 16 | distance) per half-edge, two buffers: one 32-bit add
+        // sums the distances
+        uint32_t* PJ0 = reinterpret_cast<uint32_t*>(NXa);
+        uint32_t* PJ1 = reinterpret_cast<uint32_t*>(DDa);
+        for (uint32_t h = tid; h < Et; h += kBT) {
+          const uint32_t x = SUCC[h];
+          PJ0[h] = (x << 16) | (x == kNil ? 0u : 1u);
+        }
         __syncthreads();
         const int jumps = (32 - __clz((int)Et)) + 1;
         for (int it = 0; it < jumps; ++it) {
           for (uint32_t h = tid; h < Et; h += kBT) {
-            const uint32_t x = NX0[h];
+            const uint32_t p = PJ0[h], x = p >> 16;
             if (x != kNil && x < Et) {
-              NX1[h] = NX0[x];
-              DD1[h] = (uint16_t)(DD0[h] + DD0[x]);
+              const uint32_t q = PJ0[x];
+              PJ1[h] = (q & 0xffff0000u) | ((p + q) & 0xffffu);
             } else {
-              NX1[h] = kNil;
-              DD1[h] = DD0[h];
+              PJ1[h] = ((uint32_t)kNil << 16) | (p & 0xffffu);
             }
           }
           __syncthreads();
-          uint16_t* tn = NX0;
-          NX0 = NX1;
-          NX1 = tn;
-          uint16_t* td = DD0;
-          DD0 = DD1;
-          DD1 = td;
+          uint32_t* tp = PJ0;
+          PJ0 = PJ1;
+          PJ1 = tp;
         }
         const uint32_t head = TPTR[RL[0]];
-        if (tid == 0 && (uint32_t)DD0[head] + 1 != Et) {
+        if (tid == 0 && (PJ0[head] & 0xffffu) + 1 != Et) {
           flag(status, ST_UNREACHED);
           SC[B_FAIL] = 1;
         }
         __syncthreads();
         if (!SC[B_FAIL]) {
-          uint16_t* RK = DD1;  // rank = Et - 1 - distance to the end
+          uint16_t* RK = reinterpret_cast<uint16_t*>(PJ1);  // rank = Et - 1 - distance to the end
           for (uint32_t h = tid; h < Et; h += kBT) {
-            const uint32_t r = Et - 1 - DD0[h];
+            const uint32_t r = Et - 1 - (PJ0[h] & 0xffffu);
             RK[h] = (uint16_t)r;
             TOUR[r] = (uint16_t)h;
           }
