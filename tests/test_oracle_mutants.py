@@ -8,7 +8,6 @@ oracle itself is untouched.
 import os
 import subprocess
 
-import numpy as np
 import pytest
 
 import oracle
