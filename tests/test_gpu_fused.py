@@ -252,3 +252,31 @@ def test_split_batch_graph_rejects_bad_offsets(lib):
         lib.SplitBatchGraph(_dev(np.array([-1, 0, 0], dtype=np.int32)), [0, 2], [0, 4], z, z)  # 3 nodes, offsets say 2
     with pytest.raises(ValueError):
         lib.SplitBatchGraph(_dev(np.array([-1, 0], dtype=np.int32)), [0, 2], [0, 2, 4], z, z)  # qoffsets too long
+
+
+def test_split_batch_graph_at_the_size_bound(lib, oracle_mod):
+    """Trees of exactly FUSED_MAX_NODES nodes go through the one-launch
+    kernel, one node more through the multi-kernel batch; a tree of the
+    bound after a larger one stays with the larger ones (the split is the
+    leading run of small trees)."""
+    bound = lib.et.FUSED_MAX_NODES
+    parents = [gen.path_tree(bound, seed=1), gen.random_tree(1, None, seed=2), gen.star_tree(bound, root=7),
+               gen.random_tree(bound + 1, None, seed=3), gen.random_tree(bound, 64, seed=4)]
+    batch = _batch_from_trees(parents, [50, 1, 60, 70, 80], seed=9)
+    T = len(parents)
+    qoff = _qoff(batch["qtree"], T)
+    ctx = lib.Context()
+    g = lib.SplitBatchGraph(_dev(batch["parent"]), batch["offsets"], qoff, _dev(batch["qx"]), _dev(batch["qy"]),
+                            ctx=ctx)
+    try:
+        assert g.split == 3
+        out = g.replay().cpu().numpy()
+        ctx.check()
+        off = batch["offsets"]
+        for t in range(T):
+            qa, qb = int(qoff[t]), int(qoff[t + 1])
+            p = batch["parent"][int(off[t]):int(off[t + 1])]
+            assert np.array_equal(out[qa:qb], oracle_mod.lca_offline(p, batch["qx"][qa:qb], batch["qy"][qa:qb])), t
+    finally:
+        g.close()
+        ctx.close()
