@@ -769,6 +769,12 @@ def batched_vs_plain(args, et, ctx, d, dev):
             "split_matches_batched": split_ok, **res["breakdown"]}
 
 
+def _fused_tree_bytes(nodes, queries, trees):
+    """Bytes the one-launch tree batch streams by design: the parents, the
+    query pairs and their answers, the node and query offsets."""
+    return 4 * nodes + 12 * queries + 16 * (trees + 1)
+
+
 def small_batches(args, et, ctx, d, dev):
     """Batches of small trees (log-uniform sizes in [2^6, 2^12], grasp 1, 64
     or n, 2^10..2^14 queries per tree) with total size from 2^10 to 2^22
@@ -832,11 +838,14 @@ def small_batches(args, et, ctx, d, dev):
         mctx.close()
         ctx.check()
         nodes = int(off[-1])
+        alg = _fused_tree_bytes(nodes, qn, keep)
         rows.append({"log2_target": lg, "trees": keep, "nodes": nodes, "queries": qn, "max_tree_nodes": max_nodes,
                      "fused_ms": fused_ms, "fused_graph_ms": fused_graph_ms, "multi_ms": multi_ms,
                      "multi_graph_ms": multi_graph_ms,
                      "fused_nodes_per_s": nodes / (fused_graph_ms * 1e-3),
                      "multi_nodes_per_s": nodes / (multi_graph_ms * 1e-3),
+                     "fused_alg_bytes": alg, "fused_alg_GBps": alg / (fused_graph_ms * 1e-3) / 1e9,
+                     "fused_frac_of_hbm": alg / (fused_graph_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "fused_over_multi_graph": multi_graph_ms / fused_graph_ms, "answers_equal": same})
     cross = next((r["nodes"] for r in rows if r["multi_graph_ms"] < r["fused_graph_ms"]), None)
     # tiny trees (2^4..2^10 nodes, 2^4..2^10 queries each): the 256-lane shape
@@ -862,9 +871,12 @@ def small_batches(args, et, ctx, d, dev):
         mctx.close()
         ctx.check()
         nodes = int(off[-1])
+        alg = _fused_tree_bytes(nodes, qn, keep)
         tiny.append({"log2_target": lg, "trees": keep, "nodes": nodes, "queries": qn, "max_tree_nodes": max_nodes,
                      "fused_graph_ms": fused_graph_ms, "multi_graph_ms": multi_graph_ms,
                      "fused_trees_per_s": keep / (fused_graph_ms * 1e-3),
+                     "fused_alg_bytes": alg, "fused_alg_GBps": alg / (fused_graph_ms * 1e-3) / 1e9,
+                     "fused_frac_of_hbm": alg / (fused_graph_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "fused_over_multi_graph": multi_graph_ms / fused_graph_ms, "answers_equal": same})
     return {"sweep": rows, "crossover_nodes": cross, "tiny_trees": tiny}
 
@@ -958,8 +970,14 @@ def small_graph_batches(args, et, ctx, d):
         mg.close()
         ctx.check()
         m = sum(ss) // 2
+        # streamed by design: row offsets, columns, the three offset arrays
+        # read; one bit per slot and a count per graph written
+        G = len(graphs)
+        alg = 4 * (nv + G) + 4 * sum(ss) + 24 * (G + 1) + sum(ss) // 8 + 4 * G
         rows_out.append({"log2_target": lg, "graphs": len(graphs), "vertices": nv, "edges": m,
                          "fused_graph_ms": fused_ms, "multi_graph_ms": multi_ms,
+                         "fused_alg_bytes": alg, "fused_alg_GBps": alg / (fused_ms * 1e-3) / 1e9,
+                         "fused_frac_of_hbm": alg / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "fused_edges_per_s": m / (fused_ms * 1e-3), "multi_edges_per_s": m / (multi_ms * 1e-3),
                          "fused_over_multi_graph": multi_ms / fused_ms, "answers_equal": same})
     cross = next((r["vertices"] for r in rows_out if r["multi_graph_ms"] < r["fused_graph_ms"]), None)
