@@ -817,8 +817,11 @@ def small_batches(args, et, ctx, d, dev):
         d_out = torch.empty_like(d_qx)
         reps = 20 if lg <= 16 else 5
 
+        # costliest trees first when they run 1024-lane workgroups, as FusedBatchGraph does
+        d_order = torch.from_numpy(et.et.fused_order(off, qoff)).to(dev) if max_nodes > 1024 else None
+
         def fused():
-            et.et_lca_batch_fused(d_parent, d_off, d_qoff, d_qx, d_qy, max_nodes, out=d_out, ctx=ctx)
+            et.et_lca_batch_fused(d_parent, d_off, d_qoff, d_qx, d_qy, max_nodes, out=d_out, ctx=ctx, order=d_order)
 
         def multi():
             tr = et.et_tree_build_batch(d_parent, d_off, ctx=ctx)

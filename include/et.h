@@ -288,6 +288,14 @@ int et_lca_batch(const et_tree* tree, const int32_t* d_qtree, const int32_t* d_q
  *   d_depth, d_pre, d_size   optional outputs (NULL allowed), n_total
  *                            entries each: depth, 0-based preorder and
  *                            subtree size of every node within its tree
+ *   d_order[n_trees]         optional (NULL = 0, 1, 2, ...): the order in
+ *                            which workgroups take the trees, a permutation
+ *                            of 0 .. n_trees-1; the data stays where it is.
+ *                            Costly trees first shortens the launch's tail
+ *                            (the last trees running on few compute units).
+ *                            An entry out of range sets ET_EINPUT and is
+ *                            skipped; a repeated entry leaves the tree it
+ *                            displaces unanswered
  * Same results as et_tree_build_batch + et_lca_batch (and per tree as
  * et_tree_build + et_lca). ET_ESIZE if max_tree_nodes exceeds
  * ET_FUSED_MAX_NODES or the LDS it needs exceeds what one workgroup may
@@ -300,7 +308,7 @@ int et_lca_batch(const et_tree* tree, const int32_t* d_qtree, const int32_t* d_q
 int et_lca_batch_fused(et_ctx* ctx, const int32_t* d_parent, const int64_t* d_offsets, int32_t n_trees,
                        int64_t n_total, int32_t max_tree_nodes, const int64_t* d_qoffsets, const int32_t* d_qx,
                        const int32_t* d_qy, int64_t q_total, int32_t* d_out, int32_t* d_depth, int32_t* d_pre,
-                       int32_t* d_size, hipStream_t s);
+                       int32_t* d_size, const int32_t* d_order, hipStream_t s);
 
 /*
  * The tour itself as an array (Section 2: the Euler tour as the sequence of

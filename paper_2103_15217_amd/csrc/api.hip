@@ -556,7 +556,7 @@ int et_lca_batch(const et_tree* tree, const int32_t* d_qtree, const int32_t* d_q
 int et_lca_batch_fused(et_ctx* ctx, const int32_t* d_parent, const int64_t* d_offsets, int32_t n_trees,
                        int64_t n_total, int32_t max_tree_nodes, const int64_t* d_qoffsets, const int32_t* d_qx,
                        const int32_t* d_qy, int64_t q_total, int32_t* d_out, int32_t* d_depth, int32_t* d_pre,
-                       int32_t* d_size, hipStream_t s) {
+                       int32_t* d_size, const int32_t* d_order, hipStream_t s) {
   if (!ctx || n_trees < 0 || n_total < n_trees || q_total < 0) return ET_EINVAL;
   if (n_trees == 0) return n_total == 0 && q_total == 0 ? ET_OK : ET_EINVAL;
   if (!d_parent || !d_offsets || !d_qoffsets || max_tree_nodes < 1) return ET_EINVAL;
@@ -564,7 +564,7 @@ int et_lca_batch_fused(et_ctx* ctx, const int32_t* d_parent, const int64_t* d_of
   if (n_total > (int64_t)n_trees * max_tree_nodes) return ET_EINVAL;  // some tree would exceed the bound
   if (max_tree_nodes > ET_FUSED_MAX_NODES) return ET_ESIZE;
   return et::small_batch_run(&ctx->impl, d_parent, d_offsets, n_trees, n_total, max_tree_nodes, d_qoffsets, d_qx,
-                             d_qy, q_total, d_out, d_depth, d_pre, d_size, s);
+                             d_qy, q_total, d_out, d_depth, d_pre, d_size, d_order, s);
 }
 
 int et_bridges_batch_fused(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col, const int64_t* d_voff,

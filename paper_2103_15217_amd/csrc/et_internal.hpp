@@ -376,7 +376,8 @@ int small_bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, const 
 size_t small_batch_lds_bytes(int32_t max_nodes);
 int small_batch_run(Ctx* c, const int32_t* parent, const int64_t* off, int32_t T, int64_t n_total,
                     int32_t max_nodes, const int64_t* qoff, const int32_t* qx, const int32_t* qy, int64_t q_total,
-                    int32_t* out, int32_t* depth, int32_t* pre, int32_t* size, hipStream_t s);
+                    int32_t* out, int32_t* depth, int32_t* pre, int32_t* size, const int32_t* order,
+                    hipStream_t s);
 
 }  // namespace et
 

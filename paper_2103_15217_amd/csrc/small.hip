@@ -4,7 +4,7 @@
 //
 // A workgroup of 1024 lanes (256 when no tree has more than 1024 nodes and
 // the trees outnumber the compute units) takes one tree at a time from an
-// atomic counter
+// atomic counter, in the caller's order when one is given
 // (the grid is sized to what stays resident, so the launch is persistent)
 // and runs the tree's whole path in LDS, reading only its parent array and
 // its queries from HBM and writing only the answers (and, on request, the
@@ -111,8 +111,8 @@ __global__ __launch_bounds__(kFT, kFT == 1024 ? 8 : 1) void k_small_batch(
     const int32_t* __restrict__ parent, const int64_t* __restrict__ off, int32_t T, int64_t n_total, uint32_t N,
     int32_t nmax, const int64_t* __restrict__ qoff, int64_t q_total, const int32_t* __restrict__ qx,
     const int32_t* __restrict__ qy, int32_t* __restrict__ out, int32_t* __restrict__ depth_out,
-    int32_t* __restrict__ pre_out, int32_t* __restrict__ size_out, uint32_t* __restrict__ counters,
-    uint32_t* __restrict__ status) {
+    int32_t* __restrict__ pre_out, int32_t* __restrict__ size_out, const int32_t* __restrict__ order,
+    uint32_t* __restrict__ counters, uint32_t* __restrict__ status) {
   constexpr int kFW = kFT / 64;  // wavefronts per workgroup
   static_assert(kFT * kRoundsMax >= kFSmall && kFW <= kWavesMax, "a lane holds at most kRoundsMax nodes");
   extern __shared__ __align__(16) unsigned char lds[];
@@ -146,13 +146,16 @@ __global__ __launch_bounds__(kFT, kFT == 1024 ? 8 : 1) void k_small_batch(
   for (;;) {
     if (tid == 0) SC[S_TREE] = (int32_t)atomicAdd(&counters[0], 1u);
     __syncthreads();
-    const int32_t t = SC[S_TREE];
-    if (t >= T) break;
-    const int64_t base = off[t], nt = off[t + 1] - base;
-    const int64_t qb = qoff[t], nq = qoff[t + 1] - qb;
-    const bool q_ok = qb >= 0 && nq >= 0 && qb + nq <= q_total;
-    if (!q_ok && tid == 0) flag(status, ST_BAD_QUERY);
-    const bool tree_ok = base >= 0 && nt >= 1 && nt <= (int64_t)nmax && base + nt <= n_total;
+    const int32_t k = SC[S_TREE];
+    if (k >= T) break;
+    const int32_t t = order ? order[k] : k;  // the k-th tree taken
+    const bool t_ok = (uint32_t)t < (uint32_t)T;
+    if (!t_ok && tid == 0) flag(status, ST_BAD_PARENT);
+    const int64_t base = t_ok ? off[t] : 0, nt = t_ok ? off[t + 1] - base : 0;
+    const int64_t qb = t_ok ? qoff[t] : 0, nq = t_ok ? qoff[t + 1] - qb : 0;
+    const bool q_ok = t_ok && qb >= 0 && nq >= 0 && qb + nq <= q_total;
+    if (t_ok && !q_ok && tid == 0) flag(status, ST_BAD_QUERY);
+    const bool tree_ok = t_ok && base >= 0 && nt >= 1 && nt <= (int64_t)nmax && base + nt <= n_total;
     if (!tree_ok && tid == 0) flag(status, ST_BAD_PARENT);
     const uint32_t n = tree_ok ? (uint32_t)nt : 0u;
 
@@ -502,7 +505,8 @@ size_t small_batch_lds_bytes(int32_t max_nodes) {
 
 int small_batch_run(Ctx* c, const int32_t* parent, const int64_t* off, int32_t T, int64_t n_total,
                     int32_t max_nodes, const int64_t* qoff, const int32_t* qx, const int32_t* qy, int64_t q_total,
-                    int32_t* out, int32_t* depth, int32_t* pre, int32_t* size, hipStream_t s) {
+                    int32_t* out, int32_t* depth, int32_t* pre, int32_t* size, const int32_t* order,
+                    hipStream_t s) {
   if (T == 0) return ET_OK;
   if (max_nodes < 1 || max_nodes > kFMax) return ET_ESIZE;
   const uint32_t N = al64((uint32_t)max_nodes);
@@ -521,10 +525,10 @@ int small_batch_run(Ctx* c, const int32_t* parent, const int64_t* off, int32_t T
   ET_PROF(c, s, "k_small_batch");
   if (narrow)
     hipLaunchKernelGGL(k_small_batch<256>, dim3(grid), dim3(256), lds, s, parent, off, T, n_total, N, max_nodes,
-                       qoff, q_total, qx, qy, out, depth, pre, size, c->d_fused, c->d_status);
+                       qoff, q_total, qx, qy, out, depth, pre, size, order, c->d_fused, c->d_status);
   else
     hipLaunchKernelGGL(k_small_batch<1024>, dim3(grid), dim3(1024), lds, s, parent, off, T, n_total, N, max_nodes,
-                       qoff, q_total, qx, qy, out, depth, pre, size, c->d_fused, c->d_status);
+                       qoff, q_total, qx, qy, out, depth, pre, size, order, c->d_fused, c->d_status);
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }
 

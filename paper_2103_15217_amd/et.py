@@ -36,7 +36,7 @@ _SIG = {
     "et_list_rank": ([_P, _P, _i32, _P, _i32, _P, _P], ctypes.c_int),
     "et_list_scan": ([_P, _P, _P, _i32, _P, _i32, _P, _P, _P], ctypes.c_int),
     "et_list_rank_noalloc": ([_P, _P, _i32, _P, _i32, _P, _P], ctypes.c_int),
-    "et_lca_batch_fused": ([_P, _P, _P, _i32, _i64, _i32, _P, _P, _P, _i64, _P, _P, _P, _P, _P], ctypes.c_int),
+    "et_lca_batch_fused": ([_P, _P, _P, _i32, _i64, _i32, _P, _P, _P, _i64, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "et_bridges_batch_fused": ([_P, _P, _P, _P, _P, _P, _i32, _i32, _i32, _i32, _i32, _P, _i64, _P, _P],
                                ctypes.c_int),
     "et_tree_build": ([_P, _P, _i32, _P, ctypes.POINTER(_P)], ctypes.c_int),
@@ -454,13 +454,29 @@ def et_lca_batch(tree, qtree, qx, qy, out=None):
     return tree.lca_batch(qtree, qx, qy, out)
 
 
-def et_lca_batch_fused(parent, offsets, qoffsets, qx, qy, max_tree_nodes, out=None, stats=False, ctx=None):
+def fused_order(offsets, qoffsets):
+    """An order for :func:`et_lca_batch_fused` that hands out the costliest
+    trees first (a tree's cost taken as its nodes plus a quarter of its
+    queries), so that the launch does not end on a few large trees.
+    ``offsets`` and ``qoffsets`` are host sequences of T + 1 offsets."""
+    import numpy as np
+    off = np.asarray(offsets, dtype=np.int64)
+    qoff = np.asarray(qoffsets, dtype=np.int64)
+    cost = np.diff(off) + np.diff(qoff) // 4
+    return np.argsort(-cost, kind="stable").astype(np.int32)
+
+
+def et_lca_batch_fused(parent, offsets, qoffsets, qx, qy, max_tree_nodes, out=None, stats=False, ctx=None,
+                       order=None):
     """Build many small trees (at most ``FUSED_MAX_NODES`` nodes each, at most
     ``max_tree_nodes``) and answer their queries in one kernel launch.
     ``parent`` / ``offsets`` as for :func:`et_tree_build_batch`; the queries
     come grouped by tree: tree t's are ``[qoffsets[t], qoffsets[t+1])`` of
-    ``qx`` / ``qy`` (local ids). Returns the answers (local ids), and with
-    ``stats`` also per-node depth, preorder and subtree size within each tree."""
+    ``qx`` / ``qy`` (local ids). ``order`` (optional, a permutation of the
+    tree ids on the device, e.g. from :func:`fused_order`) is the order in
+    which workgroups take the trees. Returns the answers (local ids), and
+    with ``stats`` also per-node depth, preorder and subtree size within each
+    tree."""
     ctx = ctx or default_context()
     parent = _dev(parent, torch.int32, "parent")
     offsets = _dev(offsets, torch.int64, "offsets")
@@ -482,9 +498,13 @@ def et_lca_batch_fused(parent, offsets, qoffsets, qx, qy, max_tree_nodes, out=No
     depth = pre = size = None
     if stats:
         depth, pre, size = (torch.empty(parent.numel(), dtype=torch.int32, device=parent.device) for _ in range(3))
+    if order is not None:
+        order = _dev(order, torch.int32, "order")
+        if order.numel() != T:
+            raise ValueError("order must name every tree once")
     _check(_lib.et_lca_batch_fused(ctx.handle, _ptr(parent), _ptr(offsets), T, parent.numel(),
                                    _i32(max_tree_nodes, "max_tree_nodes"), _ptr(qoffsets), _ptr(qx), _ptr(qy), q,
-                                   _ptr(out), _ptr(depth), _ptr(pre), _ptr(size), _stream()),
+                                   _ptr(out), _ptr(depth), _ptr(pre), _ptr(size), _ptr(order), _stream()),
            "et_lca_batch_fused")
     if stats:
         return out, {"depth": depth, "pre": pre, "size": size}
@@ -708,17 +728,32 @@ class FusedBatchGraph:
     graph: each replay is one kernel node. It allocates nothing and writes
     only ``out``; its work counter resets itself at the end of every launch,
     so replays need no set-up node. The context must not run another
-    et_lca_batch_fused call while a replay is in flight."""
+    et_lca_batch_fused call while a replay is in flight.
 
-    def __init__(self, parent, offsets, qoffsets, qx, qy, max_tree_nodes, ctx=None):
+    ``order`` is the order in which the launch hands out the trees: "auto"
+    (the default) takes the costliest trees first when some tree has more
+    than 1024 nodes (1024-lane workgroups, where a launch ending on a few
+    large trees leaves most compute units idle) and the stored order
+    otherwise; None keeps the stored order; or a device permutation."""
+
+    def __init__(self, parent, offsets, qoffsets, qx, qy, max_tree_nodes, ctx=None, order="auto"):
         self.ctx = ctx or Context()
+        if isinstance(order, str):
+            if order != "auto":
+                raise ValueError("order must be 'auto', None or a device permutation")
+            order = None
+            if max_tree_nodes > 1024:
+                order = torch.from_numpy(fused_order(offsets.cpu().numpy(), qoffsets.cpu().numpy())).to(qx.device)
+        self.order = order
         self.inputs = (parent, offsets, qoffsets, qx, qy)
         self.out = torch.empty_like(qx)
-        et_lca_batch_fused(parent, offsets, qoffsets, qx, qy, max_tree_nodes, out=self.out, ctx=self.ctx)
+        et_lca_batch_fused(parent, offsets, qoffsets, qx, qy, max_tree_nodes, out=self.out, ctx=self.ctx,
+                           order=order)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            et_lca_batch_fused(parent, offsets, qoffsets, qx, qy, max_tree_nodes, out=self.out, ctx=self.ctx)
+            et_lca_batch_fused(parent, offsets, qoffsets, qx, qy, max_tree_nodes, out=self.out, ctx=self.ctx,
+                               order=order)
 
     def replay(self):
         self.graph.replay()
@@ -766,9 +801,12 @@ class SplitBatchGraph:
         self.out = torch.empty_like(qx)
         self._small = None
         if k > 0:
+            mx = int(sizes[:k].max())
+            # costliest first when the trees run 1024-lane workgroups (see FusedBatchGraph)
+            order = torch.from_numpy(fused_order(off[:k + 1], qoff[:k + 1])).to(dev) if mx > 1024 else None
             self._small = (parent[:n_s], torch.from_numpy(off[:k + 1].copy()).to(dev),
-                           torch.from_numpy(qoff[:k + 1].copy()).to(dev), qx[:q_s], qy[:q_s],
-                           int(sizes[:k].max()), self.out[:q_s])
+                           torch.from_numpy(qoff[:k + 1].copy()).to(dev), qx[:q_s], qy[:q_s], mx, self.out[:q_s],
+                           order)
         self._large = None
         if k < T:
             qt = np.repeat(np.arange(T - k, dtype=np.int32), np.diff(qoff[k:]))
@@ -783,8 +821,8 @@ class SplitBatchGraph:
 
     def _run(self, keep):
         if self._small is not None:
-            p, o, qo, x, y, mx, out = self._small
-            et_lca_batch_fused(p, o, qo, x, y, mx, out=out, ctx=self.ctx)
+            p, o, qo, x, y, mx, out, order = self._small
+            et_lca_batch_fused(p, o, qo, x, y, mx, out=out, ctx=self.ctx, order=order)
         if self._large is not None:
             p, o, qt, x, y, out = self._large
             tree = et_tree_build_batch(p, o, ctx=self.ctx)

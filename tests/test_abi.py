@@ -57,9 +57,9 @@ def test_host_argument_checks():
     assert lib.et_bridges_batch(None, None, None, None, None, 1, 4, 8, None, 1, None, None) == -1
     assert lib.et_strerror(-5) == b"input beyond a fixed-size limit of this call"
     # one-launch small-tree batch: a null context is rejected before any HIP call
-    lib.et_lca_batch_fused.argtypes = [P, P, P, I32, I64, I32, P, P, P, I64, P, P, P, P, P]
+    lib.et_lca_batch_fused.argtypes = [P, P, P, I32, I64, I32, P, P, P, I64, P, P, P, P, P, P]
     assert lib.et_lca_batch_fused(None, None, None, 1, 1, 1, None, None, None, 0, None, None, None, None,
-                                  None) == -1
+                                  None, None) == -1
     # one-launch graph batch: a null context is rejected before any HIP call
     lib.et_bridges_batch_fused.argtypes = [P, P, P, P, P, P, I32, I32, I32, I32, I32, P, I64, P, P]
     assert lib.et_bridges_batch_fused(None, None, None, None, None, None, 1, 4, 8, 4, 8, None, 1, None,

@@ -280,3 +280,41 @@ def test_split_batch_graph_at_the_size_bound(lib, oracle_mod):
     finally:
         g.close()
         ctx.close()
+
+
+def test_tree_order_changes_nothing_but_the_order(lib, oracle_mod):
+    """Trees handed out in another order (a random permutation, or costliest
+    first as FusedBatchGraph does for 1024-lane workgroups) give the same
+    answers and statistics; an entry out of range is flagged and only the
+    tree it displaces goes unanswered."""
+    import torch
+    batch = gen.forest_batch(400, seed=51, log2_min=6, log2_max=12, qlog2_min=2, qlog2_max=8)
+    T = len(batch["sizes"])
+    qoff = _qoff(batch["qtree"], T)
+    args = (_dev(batch["parent"]), _dev(batch["offsets"], np.int64), _dev(qoff, np.int64), _dev(batch["qx"]),
+            _dev(batch["qy"]))
+    ctx = lib.default_context()
+    want, st = lib.et_lca_batch_fused(*args, 4096, stats=True)
+    want = want.cpu().numpy()
+    rng = np.random.default_rng(52)
+    for order in (rng.permutation(T).astype(np.int32), lib.fused_order(batch["offsets"], qoff)):
+        assert sorted(order.tolist()) == list(range(T))
+        got, st2 = lib.et_lca_batch_fused(*args, 4096, stats=True, order=_dev(order))
+        ctx.check()
+        assert np.array_equal(got.cpu().numpy(), want)
+        for k in ("depth", "pre", "size"):
+            assert torch.equal(st[k], st2[k]), k
+    g = lib.FusedBatchGraph(*args, 4096)
+    assert g.order is not None
+    assert np.array_equal(g.replay().cpu().numpy(), want)
+    g.close()
+    check_against_oracle(oracle_mod, batch, want, {k: v.cpu().numpy() for k, v in st.items()})
+    # tree 0's slot names no tree: flagged, tree 0 unanswered, the rest answered
+    bad = np.arange(T, dtype=np.int32)
+    bad[0] = T
+    out = torch.full((len(batch["qx"]),), -7, dtype=torch.int32, device="cuda")
+    lib.et_lca_batch_fused(*args, 4096, out=out, order=_dev(bad))
+    assert ctx.status_bits() != 0
+    got = out.cpu().numpy()
+    assert (got[:qoff[1]] == -7).all()
+    assert np.array_equal(got[qoff[1]:], want[qoff[1]:])
