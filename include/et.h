@@ -501,6 +501,12 @@ int et_bridges_batch(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col
  *                  ET_FUSED_MAX_SLOTS; they set the LDS each workgroup takes
  *   d_mask[mask_words]  output words (bit k of graph t's words = its slot k)
  *   d_counts[n_graphs]  optional device output: bridges per graph
+ *   d_order[n_graphs]   optional (NULL = 0, 1, 2, ...): the order in which
+ *                  workgroups take the graphs, a permutation of
+ *                  0 .. n_graphs-1 (costly graphs first shortens the
+ *                  launch's tail); an entry out of range sets ET_EINPUT and
+ *                  is skipped, a repeated entry leaves the graph it
+ *                  displaces unanswered
  * Same masks and counts as et_bridges_batch. ET_ESIZE if a bound exceeds
  * its maximum or the LDS it needs exceeds what one workgroup may take. A
  * graph larger than the bounds, offsets that do not match, rows that are
@@ -513,7 +519,8 @@ int et_bridges_batch(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col
 int et_bridges_batch_fused(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col, const int64_t* d_voff,
                            const int64_t* d_soff, const int64_t* d_moff, int32_t n_graphs, int32_t n_total,
                            int32_t nnz_total, int32_t max_graph_vertices, int32_t max_graph_slots,
-                           uint32_t* d_mask, int64_t mask_words, int64_t* d_counts, hipStream_t s);
+                           uint32_t* d_mask, int64_t mask_words, int64_t* d_counts, const int32_t* d_order,
+                           hipStream_t s);
 
 /* Device-side bridge count of the most recent et_bridges call (for a batch:
  * the total over its graphs) on ctx

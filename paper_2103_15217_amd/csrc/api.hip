@@ -570,7 +570,8 @@ int et_lca_batch_fused(et_ctx* ctx, const int32_t* d_parent, const int64_t* d_of
 int et_bridges_batch_fused(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t* d_col, const int64_t* d_voff,
                            const int64_t* d_soff, const int64_t* d_moff, int32_t n_graphs, int32_t n_total,
                            int32_t nnz_total, int32_t max_graph_vertices, int32_t max_graph_slots,
-                           uint32_t* d_mask, int64_t mask_words, int64_t* d_counts, hipStream_t s) {
+                           uint32_t* d_mask, int64_t mask_words, int64_t* d_counts, const int32_t* d_order,
+                           hipStream_t s) {
   if (!ctx || n_graphs < 0 || n_total < 0 || nnz_total < 0 || mask_words < 0) return ET_EINVAL;
   if (max_graph_vertices < 0 || max_graph_slots < 0) return ET_EINVAL;
   if (n_graphs == 0) return n_total == 0 && nnz_total == 0 ? ET_OK : ET_EINVAL;
@@ -580,7 +581,7 @@ int et_bridges_batch_fused(et_ctx* ctx, const int32_t* d_row_ptr, const int32_t*
     return ET_EINVAL;  // some graph would exceed the bounds
   if (max_graph_vertices > ET_FUSED_MAX_VERTICES || max_graph_slots > ET_FUSED_MAX_SLOTS) return ET_ESIZE;
   return et::small_bridges_run(&ctx->impl, d_row_ptr, d_col, d_voff, d_soff, d_moff, n_graphs, n_total, nnz_total,
-                               max_graph_vertices, max_graph_slots, d_mask, mask_words, d_counts, s);
+                               max_graph_vertices, max_graph_slots, d_mask, mask_words, d_counts, d_order, s);
 }
 
 int32_t et_tree_batch_size(const et_tree* tree) { return tree ? tree->batch : -1; }

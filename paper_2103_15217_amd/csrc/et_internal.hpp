@@ -371,7 +371,8 @@ int persistent_grid(const void* kern, int threads, uint32_t lds, int64_t items, 
 // CSR slots in one launch; moff[t] is graph t's first mask word
 int small_bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, const int64_t* voff, const int64_t* soff,
                       const int64_t* moff, int32_t T, int32_t n_total, int32_t nnz_total, int32_t max_vertices,
-                      int32_t max_slots, uint32_t* mask, int64_t mask_words, int64_t* counts, hipStream_t s);
+                      int32_t max_slots, uint32_t* mask, int64_t mask_words, int64_t* counts, const int32_t* order,
+                      hipStream_t s);
 // small.hip: build and query many trees of at most 4096 nodes in one launch
 size_t small_batch_lds_bytes(int32_t max_nodes);
 int small_batch_run(Ctx* c, const int32_t* parent, const int64_t* off, int32_t T, int64_t n_total,

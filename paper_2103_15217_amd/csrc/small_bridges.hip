@@ -2,6 +2,7 @@
 // for a batch of instances as the tree batch of Section 3.3 does for LCA).
 //
 // A workgroup of 1024 lanes takes one graph at a time from an atomic counter
+// (in the caller's order when one is given)
 // (a persistent grid sized to what stays resident) and runs the whole method
 // on it in LDS, reading only its CSR from HBM and writing only its mask words
 // and its bridge count:
@@ -181,8 +182,8 @@ __global__ __launch_bounds__(kBT, 8) void k_small_bridges(
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const int64_t* __restrict__ voff,
     const int64_t* __restrict__ soff, const int64_t* __restrict__ moff, int32_t T, int64_t n_total,
     int64_t nnz_total, int64_t mask_words, uint32_t N, uint32_t M, int32_t vmax, int32_t smax,
-    uint32_t* __restrict__ mask, int64_t* __restrict__ counts, uint32_t* __restrict__ counters,
-    uint32_t* __restrict__ status) {
+    uint32_t* __restrict__ mask, int64_t* __restrict__ counts, const int32_t* __restrict__ order,
+    uint32_t* __restrict__ counters, uint32_t* __restrict__ status) {
   extern __shared__ __align__(16) unsigned char lds[];
   const BLayout L = blayout(N, M);
   uint16_t* RP = reinterpret_cast<uint16_t*>(lds + L.rp);
@@ -226,12 +227,14 @@ __global__ __launch_bounds__(kBT, 8) void k_small_bridges(
   for (;;) {
     if (tid == 0) SC[B_GRAPH] = (int32_t)atomicAdd(&counters[0], 1u);
     __syncthreads();
-    const int32_t t = SC[B_GRAPH];
-    if (t >= T) break;
-    const int64_t vb = voff[t], nv = voff[t + 1] - vb;
-    const int64_t sb = soff[t], ns = soff[t + 1] - sb;
-    const int64_t mw = moff[t], nw = moff[t + 1] - mw;
-    const bool out_ok = mw >= 0 && nw == (ns + 31) / 32 && mw + nw <= mask_words && ns >= 0;
+    const int32_t k = SC[B_GRAPH];
+    if (k >= T) break;
+    const int32_t t = order ? order[k] : k;  // the k-th graph taken
+    const bool t_ok = (uint32_t)t < (uint32_t)T;
+    const int64_t vb = t_ok ? voff[t] : 0, nv = t_ok ? voff[t + 1] - vb : 0;
+    const int64_t sb = t_ok ? soff[t] : 0, ns = t_ok ? soff[t + 1] - sb : 0;
+    const int64_t mw = t_ok ? moff[t] : 0, nw = t_ok ? moff[t + 1] - mw : 0;
+    const bool out_ok = t_ok && mw >= 0 && nw == (ns + 31) / 32 && mw + nw <= mask_words && ns >= 0;
     const bool g_ok = out_ok && vb >= 0 && nv >= 0 && nv <= vmax && sb >= 0 && ns <= smax &&
                       vb + nv <= n_total && sb + ns <= nnz_total;
     if (!g_ok && tid == 0) flag(status, ST_BAD_CSR);
@@ -573,7 +576,8 @@ __global__ __launch_bounds__(kBT, 8) void k_small_bridges(
 
 int small_bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, const int64_t* voff, const int64_t* soff,
                       const int64_t* moff, int32_t T, int32_t n_total, int32_t nnz_total, int32_t max_vertices,
-                      int32_t max_slots, uint32_t* mask, int64_t mask_words, int64_t* counts, hipStream_t s) {
+                      int32_t max_slots, uint32_t* mask, int64_t mask_words, int64_t* counts, const int32_t* order,
+                      hipStream_t s) {
   if (T == 0) return ET_OK;
   if (max_vertices < 0 || max_slots < 0) return ET_EINVAL;
   if (max_vertices > kGMaxV || max_slots > kGMaxS) return ET_ESIZE;
@@ -585,7 +589,7 @@ int small_bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, const 
   ET_PROF(c, s, "k_small_bridges");
   hipLaunchKernelGGL(k_small_bridges, dim3(grid), dim3(kBT), lds, s, row_ptr, col, voff, soff, moff, T,
                      (int64_t)n_total, (int64_t)nnz_total, mask_words, N, M, max_vertices, max_slots, mask, counts,
-                     c->d_fused, c->d_status);
+                     order, c->d_fused, c->d_status);
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;
 }
 

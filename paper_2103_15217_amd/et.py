@@ -37,7 +37,7 @@ _SIG = {
     "et_list_scan": ([_P, _P, _P, _i32, _P, _i32, _P, _P, _P], ctypes.c_int),
     "et_list_rank_noalloc": ([_P, _P, _i32, _P, _i32, _P, _P], ctypes.c_int),
     "et_lca_batch_fused": ([_P, _P, _P, _i32, _i64, _i32, _P, _P, _P, _i64, _P, _P, _P, _P, _P, _P], ctypes.c_int),
-    "et_bridges_batch_fused": ([_P, _P, _P, _P, _P, _P, _i32, _i32, _i32, _i32, _i32, _P, _i64, _P, _P],
+    "et_bridges_batch_fused": ([_P, _P, _P, _P, _P, _P, _i32, _i32, _i32, _i32, _i32, _P, _i64, _P, _P, _P],
                                ctypes.c_int),
     "et_tree_build": ([_P, _P, _i32, _P, ctypes.POINTER(_P)], ctypes.c_int),
     "et_tree_size": ([_P], _i32),
@@ -466,6 +466,16 @@ def fused_order(offsets, qoffsets):
     return np.argsort(-cost, kind="stable").astype(np.int32)
 
 
+def fused_graph_order(slots, vertices):
+    """An order for :func:`et_bridges_batch_fused` that hands out the
+    costliest graphs first (a graph's cost taken as its CSR slots plus twice
+    its vertices); ``slots`` and ``vertices`` are host sequences, one entry
+    per graph."""
+    import numpy as np
+    cost = np.asarray(slots, dtype=np.int64) + 2 * np.asarray(vertices, dtype=np.int64)
+    return np.argsort(-cost, kind="stable").astype(np.int32)
+
+
 def et_lca_batch_fused(parent, offsets, qoffsets, qx, qy, max_tree_nodes, out=None, stats=False, ctx=None,
                        order=None):
     """Build many small trees (at most ``FUSED_MAX_NODES`` nodes each, at most
@@ -582,7 +592,7 @@ def et_bridges_batch(graphs=None, *, row_ptr=None, col=None, voff=None, soff=Non
 
 def et_bridges_batch_fused(graphs=None, *, row_ptr=None, col=None, voff=None, soff=None, slots=None,
                            vertices=None, moff=None, max_vertices=None, max_slots=None, mask=None, ctx=None,
-                           counts=True):
+                           counts=True, order=None):
     """Bridges of many small graphs (at most ``FUSED_MAX_VERTICES`` vertices
     and ``FUSED_MAX_SLOTS`` CSR slots each) in one kernel launch. Arguments
     and results as for :func:`et_bridges_batch` (``vertices``: the host list
@@ -590,7 +600,9 @@ def et_bridges_batch_fused(graphs=None, *, row_ptr=None, col=None, voff=None, so
     bounds default to the largest graph's. ``moff``, the device int64 word
     offsets of the graphs' masks, is uploaded from the slot counts when not
     given (give it to capture the call in a graph: the upload's pinned
-    buffer would not outlive the capture)."""
+    buffer would not outlive the capture). ``order`` (optional, a device
+    permutation of the graph ids, e.g. from :func:`fused_graph_order`) is the
+    order in which workgroups take the graphs."""
     ctx = ctx or default_context()
     if graphs is not None:
         if len(graphs) == 0:
@@ -632,9 +644,13 @@ def et_bridges_batch_fused(graphs=None, *, row_ptr=None, col=None, voff=None, so
     out = torch.empty(T, dtype=torch.int64, device=col.device) if counts else None
     mv = _i32(max(vs) if max_vertices is None else max_vertices, "max_vertices")
     ms = _i32(max(ss) if max_slots is None else max_slots, "max_slots")
+    if order is not None:
+        order = _dev(order, torch.int32, "order")
+        if order.numel() != T:
+            raise ValueError("order must name every graph once")
     _check(_lib.et_bridges_batch_fused(ctx.handle, _ptr(row_ptr), _ptr(col), _ptr(voff), _ptr(soff), _ptr(moff), T,
                                        n_total, nnz, mv, ms, _ptr(mask), mask.numel(), _ptr(out) if counts else None,
-                                       _stream()), "et_bridges_batch_fused")
+                                       _ptr(order), _stream()), "et_bridges_batch_fused")
     return mask, list(zip(starts[:-1], words)), out
 
 
@@ -848,11 +864,18 @@ class BridgesFusedGraph:
     """The one-launch graph batch (et_bridges_batch_fused) captured in a HIP
     graph: each replay is one kernel node writing ``mask`` and ``counts``.
     The context must not run another one-launch call while a replay is in
-    flight."""
+    flight. ``order`` is the order in which the launch hands out the graphs:
+    "auto" (the default) the costliest first (:func:`fused_graph_order`),
+    None the stored order, or a device permutation."""
 
-    def __init__(self, row_ptr, col, voff, soff, slots, vertices, ctx=None):
+    def __init__(self, row_ptr, col, voff, soff, slots, vertices, ctx=None, order="auto"):
         self.ctx = ctx or Context()
         slots, vertices = list(slots), list(vertices)
+        if isinstance(order, str):
+            if order != "auto":
+                raise ValueError("order must be 'auto', None or a device permutation")
+            order = torch.from_numpy(fused_graph_order(slots, vertices)).to(col.device)
+        self.order = order
         words = [(x + 31) // 32 for x in slots]
         starts = [0]
         for w in words:
@@ -860,7 +883,7 @@ class BridgesFusedGraph:
         self.moff = torch.tensor(starts, dtype=torch.int64, device=col.device)
         self.inputs = (row_ptr, col, voff, soff, self.moff)
         kw = dict(row_ptr=row_ptr, col=col, voff=voff, soff=soff, slots=slots, vertices=vertices, moff=self.moff,
-                  ctx=self.ctx)
+                  ctx=self.ctx, order=order)
         et_bridges_batch_fused(**kw)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()

@@ -61,6 +61,6 @@ def test_host_argument_checks():
     assert lib.et_lca_batch_fused(None, None, None, 1, 1, 1, None, None, None, 0, None, None, None, None,
                                   None, None) == -1
     # one-launch graph batch: a null context is rejected before any HIP call
-    lib.et_bridges_batch_fused.argtypes = [P, P, P, P, P, P, I32, I32, I32, I32, I32, P, I64, P, P]
+    lib.et_bridges_batch_fused.argtypes = [P, P, P, P, P, P, I32, I32, I32, I32, I32, P, I64, P, P, P]
     assert lib.et_bridges_batch_fused(None, None, None, None, None, None, 1, 4, 8, 4, 8, None, 1, None,
-                                      None) == -1
+                                      None, None) == -1

@@ -182,3 +182,49 @@ def test_host_argument_errors(lib):
     with pytest.raises(lib.EtError) as e:
         lib.et_bridges_batch_fused(g, max_vertices=1, max_slots=2)   # 2 vertices cannot be one graph of <= 1
     assert e.value.code == lib.et.ET_EINVAL
+
+
+def test_graph_order_changes_nothing_but_the_order(lib):
+    """Graphs handed out in another order (a random permutation, or the
+    costliest first as BridgesFusedGraph does) give the same masks and
+    counts; an entry out of range is flagged and only the graph it
+    displaces goes unanswered."""
+    import torch
+    rng = np.random.default_rng(61)
+    graphs = [gen.random_multigraph(int(rng.integers(2, 600)), int(rng.integers(1, 1500)), seed=t, loops=True,
+                                    multi=True) for t in range(200)]
+    ctx = lib.default_context()
+    want, spans, want_c = run_fused(lib, graphs, ctx=ctx)
+    ctx.check()
+    dg = [(_dev(rp), _dev(col)) for rp, col in graphs]
+    rows = torch.cat([g[0] for g in dg])
+    cols = torch.cat([g[1] for g in dg])
+    vs = [len(r) - 1 for r, _ in graphs]
+    ss = [len(c) for _, c in graphs]
+    voff = _dev(np.concatenate([[0], np.cumsum(vs)]), np.int64)
+    soff = _dev(np.concatenate([[0], np.cumsum(ss)]), np.int64)
+    kw = dict(row_ptr=rows, col=cols, voff=voff, soff=soff, slots=ss, vertices=vs, ctx=ctx)
+    T = len(graphs)
+    for order in (rng.permutation(T).astype(np.int32), lib.fused_graph_order(ss, vs)):
+        assert sorted(order.tolist()) == list(range(T))
+        mask, _, counts = lib.et_bridges_batch_fused(order=_dev(order), **kw)
+        ctx.check()
+        assert np.array_equal(mask.cpu().numpy().view(np.uint32), want)
+        assert np.array_equal(counts.cpu().numpy(), want_c)
+    g = lib.BridgesFusedGraph(rows, cols, voff, soff, ss, vs)
+    assert g.order is not None
+    g.replay()
+    torch.cuda.synchronize()
+    assert np.array_equal(g.mask.cpu().numpy().view(np.uint32), want)
+    g.close()
+    # graph 0's slot names no graph: flagged, graph 0's words untouched, the rest answered
+    bad = np.arange(T, dtype=np.int32)
+    bad[0] = T
+    total = sum((x + 31) // 32 for x in ss)
+    mask = torch.full((total,), -7, dtype=torch.int32, device="cuda")
+    lib.et_bridges_batch_fused(order=_dev(bad), mask=mask, **kw)
+    assert ctx.status_bits() != 0
+    got = mask.cpu().numpy().view(np.uint32)
+    w0 = (ss[0] + 31) // 32
+    assert (got[:w0] == np.uint32(0xfffffff9)).all()
+    assert np.array_equal(got[w0:], want[w0:])
