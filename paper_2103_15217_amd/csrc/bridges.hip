@@ -279,27 +279,61 @@ __global__ void k_tree_deg(const int32_t* __restrict__ row_ptr, const uint32_t* 
   tdeg[u] = d;
 }
 
-__global__ void k_tree_fill(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+// Forest entries of every vertex u at tptr[u]..: its forest slots in slot
+// order, the neighbour at each, and u. The vertices of a workgroup own one
+// contiguous output range; when it holds at most kFillStage entries it is
+// built in LDS and stored with consecutive lanes on consecutive addresses
+// (a lane per vertex storing its own entries leaves every line partly
+// written, four times the bytes); a longer range (a hub) is stored directly.
+constexpr int kFillStage = 2048;
+
+__global__ __launch_bounds__(kB) void k_tree_fill(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                             const uint32_t* __restrict__ tbits, const uint32_t* __restrict__ tptr, int32_t n,
                             int32_t nnz, int32_t Lcap, int32_t* __restrict__ tslot, int32_t* __restrict__ tnbr,
                             int32_t* __restrict__ tsrc) {
-  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= n) return;
-  const int32_t a = clampi(row_ptr[u], 0, nnz), b = clampi(row_ptr[u + 1], a, nnz);
-  uint32_t j = tptr[u];
-  if (a >= b) return;
-  for (int32_t wd = a >> 5; wd <= (b - 1) >> 5; ++wd) {
-    uint32_t x = bits_in(tbits, a, b, wd);
-    while (x) {
-      const int bit = __ffs((int)x) - 1;
-      x &= x - 1;
-      const int32_t k = (wd << 5) + bit;
-      if (j >= (uint32_t)Lcap) return;  // only with a malformed CSR (flagged)
-      tslot[j] = k;
-      tnbr[j] = col[k];
-      tsrc[j] = (int32_t)u;
-      ++j;
+  __shared__ int32_t st_slot[kFillStage], st_nbr[kFillStage], st_src[kFillStage];
+  const int64_t u0 = (int64_t)blockIdx.x * kB;
+  const int64_t u = u0 + threadIdx.x;
+  // tptr is an exclusive scan of the forest degrees (n + 1 entries), so the
+  // workgroup's entries are [J0, J1), cut at Lcap
+  const uint32_t J0 = tptr[u0];
+  const int64_t ue = (u0 + kB < (int64_t)n) ? u0 + kB : (int64_t)n;
+  const uint32_t J1 = min(tptr[ue], (uint32_t)Lcap);
+  const bool staged = J1 <= J0 || J1 - J0 <= (uint32_t)kFillStage;  // the same for every lane
+  if (u < n) {
+    const int32_t a = clampi(row_ptr[u], 0, nnz), b = clampi(row_ptr[u + 1], a, nnz);
+    uint32_t j = tptr[u];
+    for (int32_t wd = a >> 5; a < b && wd <= (b - 1) >> 5; ++wd) {
+      uint32_t x = bits_in(tbits, a, b, wd);
+      while (x) {
+        const int bit = __ffs((int)x) - 1;
+        x &= x - 1;
+        const int32_t k = (wd << 5) + bit;
+        if (j >= (uint32_t)Lcap) {  // only with a malformed CSR (flagged)
+          x = 0;
+          wd = b;
+          break;
+        }
+        if (staged) {
+          st_slot[j - J0] = k;
+          st_nbr[j - J0] = col[k];
+          st_src[j - J0] = (int32_t)u;
+        } else {
+          tslot[j] = k;
+          tnbr[j] = col[k];
+          tsrc[j] = (int32_t)u;
+        }
+        ++j;
+      }
     }
+  }
+  if (!staged) return;
+  __syncthreads();
+  if (J1 <= J0) return;
+  for (uint32_t i = threadIdx.x; i < J1 - J0; i += kB) {
+    tslot[J0 + i] = st_slot[i];
+    tnbr[J0 + i] = st_nbr[i];
+    tsrc[J0 + i] = st_src[i];
   }
 }
 

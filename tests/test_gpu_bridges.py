@@ -42,7 +42,8 @@ def test_tiny_multigraphs(lib, oracle_mod):
         compare(lib, oracle_mod, rp, col)
 
 
-@pytest.mark.parametrize("kind", ["tree", "path", "cycle", "complete", "doubled_tree", "empty", "isolated"])
+@pytest.mark.parametrize("kind", ["tree", "path", "cycle", "complete", "doubled_tree", "empty", "isolated",
+                                  "star", "wheel"])
 def test_special_graphs(lib, oracle_mod, kind):
     if kind == "tree":
         rp, col = gen.tree_graph(gen.random_tree(100003, None, seed=1))
@@ -56,6 +57,17 @@ def test_special_graphs(lib, oracle_mod, kind):
         p = gen.random_tree(20000, None, seed=3)
         c = np.nonzero(p >= 0)[0]
         rp, col = gen.csr_from_pairs(20000, np.concatenate([c, c]), np.concatenate([p[c], p[c]]))
+    elif kind in ("star", "wheel"):
+        # a hub of degree 4999 (every spanning forest of a star is the star):
+        # its workgroup's forest entries exceed what the fill stages in LDS
+        # and are stored directly, the other workgroups' are staged; the
+        # wheel adds a rim cycle, so no edge of it is a bridge
+        n = 5000
+        rim = np.arange(1, n)
+        u, w = np.zeros(n - 1, np.int64), rim
+        if kind == "wheel":
+            u, w = np.concatenate([u, rim]), np.concatenate([w, np.roll(rim, 1)])
+        rp, col = gen.csr_from_pairs(n, u, w)
     elif kind == "empty":
         rp, col = gen.csr_from_pairs(1000, np.array([], np.int64), np.array([], np.int64))
     else:
