@@ -25,8 +25,9 @@
 // eight XCDs in turn, and each XCD is given a contiguous range of tiles, so
 // the runs of one digit that adjacent tiles write (neighbours in the output)
 // and the histogram entries they write meet in the same L2, which merges
-// their partial lines before they go to memory. At 2^24 keys this takes a
-// downsweep pass from 126 to 83 us.
+// their partial lines before they go to memory. With the 512-lane shape
+// this takes a downsweep pass over 2^24 uniform keys from 126 to 83 us, and
+// one of a 2^24-node tree build from 116 to 91 us.
 //
 // The first pass reads the parent array directly (the root's -1 becomes the
 // all-ones key and sorts last), validates it, finds the root, and writes
