@@ -633,28 +633,42 @@ __device__ __forceinline__ void rmq(const Rmq<LOG>& q, int32_t l, int32_t r, int
 // one lane per preorder position i < (number of non-isolated vertices, the
 // last value of the preorder scan): the subtree interval starts at i, so
 // neighbouring lanes read neighbouring RMQ entries
+// the test runs a grid-stride loop over the vertices in preorder on at most
+// this many workgroups
+constexpr int kTestBlocks = 2048;
+
 template <int LOG>
 __global__ __launch_bounds__(kB) void k_bridge_test(const int4* __restrict__ byp, const uint32_t* __restrict__ I,
                                                    int32_t Lcap, int32_t n, Rmq<LOG> q, uint32_t* __restrict__ mask,
                                                    int64_t* __restrict__ count) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t npre = min((int32_t)I[Lcap - 1], n);
-  bool is_bridge = false;
-  if (i < npre) {
+  uint32_t found = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < npre; i += (int64_t)gridDim.x * kB) {
     const int4 b = byp[i];
     const int32_t l = (int32_t)i, r = l + b.x - 1;
     if (b.y >= 0 && r >= l && r < npre) {
       int32_t lo, hi;
       rmq(q, l, r, &lo, &hi);
       if (lo == l && hi == r) {
-        is_bridge = true;
+        ++found;
         atomicOr(mask + (b.y >> 5), 1u << (b.y & 31));
         if (b.z >= 0) atomicOr(mask + (b.z >> 5), 1u << (b.z & 31));
       }
     }
   }
-  const uint64_t bb = __ballot(is_bridge);
-  if (__lane_id() == 0 && bb) atomicAdd((unsigned long long*)count, (unsigned long long)__popcll(bb));
+  // one count update per workgroup: every wavefront adding its own to the
+  // one counter serialised some 65K same-address atomics at 2^22 vertices
+  __shared__ uint32_t wsum[kB / 64];
+  uint32_t t = found;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  if (__lane_id() == 0) wsum[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int w = 0; w < kB / 64; ++w) tot += wsum[w];
+    if (tot) atomicAdd((unsigned long long*)count, (unsigned long long)tot);
+  }
 }
 
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
@@ -891,10 +905,12 @@ int bridges_run(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, i
     if (rlog == 6) {
       Rmq<6> q{amin, amax, reinterpret_cast<const uint64_t*>(mmin), reinterpret_cast<const uint64_t*>(mmax), stmin,
                stmax, nb};
-      hipLaunchKernelGGL(k_bridge_test<6>, dim3(gn), dim3(kB), 0, s, byp, dw, Lcap, n, q, mask, c->d_bcount);
+      hipLaunchKernelGGL(k_bridge_test<6>, dim3(std::min(gn, kTestBlocks)), dim3(kB), 0, s, byp, dw, Lcap, n, q, mask,
+                         c->d_bcount);
     } else {
       Rmq<5> q{amin, amax, mmin, mmax, stmin, stmax, nb};
-      hipLaunchKernelGGL(k_bridge_test<5>, dim3(gn), dim3(kB), 0, s, byp, dw, Lcap, n, q, mask, c->d_bcount);
+      hipLaunchKernelGGL(k_bridge_test<5>, dim3(std::min(gn, kTestBlocks)), dim3(kB), 0, s, byp, dw, Lcap, n, q, mask,
+                         c->d_bcount);
     }
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;

@@ -211,19 +211,30 @@ __global__ __launch_bounds__(kB) void k_ck_mark(const int32_t* __restrict__ row_
 }
 
 // a tree edge nobody marked is a bridge: both of its slots get their bit
-__global__ void k_ck_out(const int32_t* __restrict__ par, const int32_t* __restrict__ pslot,
+__global__ __launch_bounds__(kB) void k_ck_out(const int32_t* __restrict__ par, const int32_t* __restrict__ pslot,
                          const int32_t* __restrict__ uslot, const uint8_t* __restrict__ mark, int32_t n,
                          uint32_t* __restrict__ mask, int64_t* __restrict__ count) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool is_bridge = false;
-  if (v < n && par[v] >= 0 && !mark[v]) {
-    is_bridge = true;
-    const int32_t k = pslot[v], t = uslot[v];
-    if (k >= 0) atomicOr(mask + (k >> 5), 1u << (k & 31));
-    if (t >= 0) atomicOr(mask + (t >> 5), 1u << (t & 31));
+  uint32_t found = 0;
+  for (int64_t v = (int64_t)blockIdx.x * kB + threadIdx.x; v < n; v += (int64_t)gridDim.x * kB) {
+    if (par[v] >= 0 && !mark[v]) {
+      ++found;
+      const int32_t k = pslot[v], t = uslot[v];
+      if (k >= 0) atomicOr(mask + (k >> 5), 1u << (k & 31));
+      if (t >= 0) atomicOr(mask + (t >> 5), 1u << (t & 31));
+    }
   }
-  const uint64_t bb = __ballot(is_bridge);
-  if (__lane_id() == 0 && bb) atomicAdd((unsigned long long*)count, (unsigned long long)__popcll(bb));
+  // one count update per workgroup (not one per wavefront on the one counter)
+  __shared__ uint32_t wsum[kB / 64];
+  uint32_t t = found;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  if (__lane_id() == 0) wsum[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int w = 0; w < kB / 64; ++w) tot += wsum[w];
+    if (tot) atomicAdd((unsigned long long*)count, (unsigned long long)tot);
+  }
 }
 
 }  // namespace
@@ -243,7 +254,7 @@ int ck_mark(Ctx* c, const int32_t* row_ptr, const int32_t* col, int32_t n, int32
   }
   {
     ET_PROF(c, s, "k_ck_out");
-    hipLaunchKernelGGL(k_ck_out, dim3(ceil_div(n, kB)), dim3(kB), 0, s, par, pslot, uslot, mark, n, mask,
+    hipLaunchKernelGGL(k_ck_out, dim3(std::min(ceil_div(n, kB), 2048)), dim3(kB), 0, s, par, pslot, uslot, mark, n, mask,
                        c->d_bcount);
   }
   return hipGetLastError() == hipSuccess ? ET_OK : ET_EHIP;

@@ -373,21 +373,25 @@ __global__ void k_final_walk(const int4* __restrict__ rec, int32_t T, int32_t hb
                              int2* __restrict__ off, int32_t* __restrict__ reached,
                              uint32_t* __restrict__ status) {
   const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= H) return;
-  int32_t e = hb + (int32_t)h, al = 0, ad = 0;
-  int64_t steps = 0;
-  while (e != -1) {
-    if (e < 0 || e >= T || ++steps > T) {
-      flag(status, ST_BAD_SUCC);
-      break;
+  int32_t al = 0, ad = 0;
+  if (h < H) {
+    int32_t e = hb + (int32_t)h;
+    int64_t steps = 0;
+    while (e != -1) {
+      if (e < 0 || e >= T || ++steps > T) {
+        flag(status, ST_BAD_SUCC);
+        break;
+      }
+      const int4 r = rec[e];
+      off[e] = make_int2(al, ad);
+      al += r.y;
+      ad = wadd(ad, r.z);
+      e = r.x;
     }
-    const int4 r = rec[e];
-    off[e] = make_int2(al, ad);
-    al += r.y;
-    ad = wadd(ad, r.z);
-    e = r.x;
   }
-  atomicAdd(reached, al);
+  // one add per wavefront to the shared count, not one per head
+  for (int dd = 32; dd >= 1; dd >>= 1) al += __shfl_xor(al, dd, 64);
+  if (__lane_id() == 0 && al) atomicAdd(reached, al);
 }
 
 __global__ void k_check_reached(const int32_t* __restrict__ reached, const int32_t* __restrict__ expected,
