@@ -215,8 +215,17 @@ __global__ __launch_bounds__(kBigSample) void k_big_component(const int32_t* cc,
   // the longest run of equal roots wins (smallest root on a tie)
   int len = 0;
   if (t == 0 || r[t - 1] != r[t]) {
-    len = 1;
-    while (t + len < kBigSample && r[t + len] == r[t]) ++len;
+    // the run's end by a binary search in the sorted samples (walking it
+    // took one LDS read per member: ~1000 in a row when one component
+    // holds nearly every sample)
+    const int32_t x = r[t];
+    int lo = t + 1, hi = kBigSample;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (r[mid] == x) lo = mid + 1;
+      else hi = mid;
+    }
+    len = lo - t;
     atomicMax(&best_count, len);
   }
   __syncthreads();
