@@ -639,13 +639,12 @@ __device__ __forceinline__ void rmq(const Rmq<LOG>& q, int32_t l, int32_t r, int
   *hi = mx;
 }
 
-// one lane per preorder position i < (number of non-isolated vertices, the
-// last value of the preorder scan): the subtree interval starts at i, so
-// neighbouring lanes read neighbouring RMQ entries
-// the test runs a grid-stride loop over the vertices in preorder on at most
-// this many workgroups
+// workgroups of the bridge test at most
 constexpr int kTestBlocks = 2048;
 
+// one lane per preorder position i < (number of non-isolated vertices, the
+// last value of the preorder scan), in a grid-stride loop: the subtree
+// interval starts at i, so neighbouring lanes read neighbouring RMQ entries
 template <int LOG>
 __global__ __launch_bounds__(kB) void k_bridge_test(const int4* __restrict__ byp, const uint32_t* __restrict__ I,
                                                    int32_t Lcap, int32_t n, Rmq<LOG> q, uint32_t* __restrict__ mask,
